@@ -1,0 +1,10 @@
+"""CPU FP64 oracle for the excessive gap technique on poker river endgames.
+
+TEST INFRASTRUCTURE ONLY: imported by ``tests/``, by the smoke check and by
+the CPU-baseline leg of the benchmark, never by the product path.  It shares
+no code with the HIP implementation; the only common input is the seeded
+instance generator in ``instances/``.
+"""
+from .game import Game  # noqa: F401,E402
+from .problem import Problem  # noqa: F401,E402
+from .egt import EGT, Trace, solve  # noqa: F401,E402

@@ -1,0 +1,103 @@
+"""Pins for the oracle's EGT drivers (CPU only).
+
+* Kuhn poker: the LP value and every EGT variant's limit equal the textbook
+  game value (golden fixture).
+* LP (Section 1's sequence-form LP) on tiny endgames: the best-response
+  bounds of every iterate bracket the LP value; the final value is within the
+  final gap of it.
+* Section 2's invariants: eps_sad >= 0; the excessive gap condition implies
+  eps_sad <= mu_x Omega_X + mu_y Omega_Y; EGT/as keeps EGV >= 0 at every
+  accepted step; EGT started at the theory-safe mu keeps the condition and the
+  O(1/T) bound.
+* The literal prox of Algorithm 2 (through grad d of the appendix) equals the
+  shift-free form.
+* The sequence-form flow constraints hold for every iterate.
+"""
+import os
+
+import numpy as np
+import pytest
+
+from instances import make_instance
+from oracle import Problem, solve
+from oracle.lp import lp_value
+
+
+def _golden_kuhn():
+    path = os.path.join(os.path.dirname(__file__), "golden", "kuhn_value.txt")
+    for line in open(path):
+        if line.startswith("value_player1"):
+            return float(line.split("=")[1])
+    raise AssertionError("fixture missing")
+
+
+@pytest.fixture(scope="module")
+def kuhn():
+    return Problem(make_instance("kuhn"))
+
+
+def test_kuhn_lp_value(kuhn):
+    v, x = lp_value(kuhn)
+    assert v == pytest.approx(-_golden_kuhn(), abs=1e-12)
+    assert kuhn.flow_residual(0, x) < 1e-9
+
+
+@pytest.mark.parametrize("variant", ["AS", "BAL", "ALT"])
+def test_kuhn_egt_converges_to_game_value(kuhn, variant):
+    tr = solve(kuhn, variant, eps=2e-4, max_iters=20000)
+    assert tr.converged
+    assert abs(tr.value_p2 - (-_golden_kuhn())) <= tr.gap
+    assert kuhn.flow_residual(0, tr.x) < 1e-13 and kuhn.flow_residual(1, tr.y) < 1e-13
+
+
+@pytest.mark.parametrize("seed", [0, 2])
+def test_iterates_bracket_lp_value(seed):
+    P = Problem(make_instance("micro", seed))
+    v_star, _ = lp_value(P)
+    tr = solve(P, "AS", eps=1e-3, max_iters=3000)
+    for r in tr.rows:
+        assert r["br_min_x"] <= v_star + 1e-10
+        assert r["br_max_y"] >= v_star - 1e-10
+        assert r["gap"] >= -1e-12
+    assert abs(tr.value_p2 - v_star) <= tr.gap + 1e-12
+
+
+@pytest.mark.parametrize("cfg,variant", [("c0", "AS"), ("micro", "AS"), ("c0", "BAL")])
+def test_excessive_gap_invariants(cfg, variant):
+    P = Problem(make_instance(cfg, 1))
+    OX, OY = P.omega(0), P.omega(1)
+    tr = solve(P, variant, max_iters=150)
+    rows = tr.rows
+    for prev, cur in zip(rows[:-1], rows[1:]):
+        if variant == "AS":
+            assert prev["egv"] >= 0.0
+        if prev["egv"] >= 0.0:
+            # EGV(x, y) > 0 implies eps_sad(x, y) <= mu_x Omega_X + mu_y Omega_Y
+            assert cur["gap"] <= cur["mu_x"] * OX + cur["mu_y"] * OY + 1e-12
+    assert tr.max_prox_diff < 1e-10
+    assert P.flow_residual(0, tr.x) < 1e-12 and P.flow_residual(1, tr.y) < 1e-12
+
+
+@pytest.mark.parametrize("cfg", ["kuhn", "micro"])
+def test_theory_safe_start_keeps_condition_and_rate(cfg):
+    """Algorithm 1 started at mu_x mu_y = ||A||^2 / (phi_X phi_Y), phi = 1/M
+    (Section 4's strong-convexity modulus): EGV >= 0 at every step and
+    eps_sad(x^T, y^T) <= 4 ||A|| / (T + 1) sqrt(Omega_X Omega_Y / (phi_X phi_Y))."""
+    P = Problem(make_instance(cfg, 0))
+    nA = P.norm_A()
+    MX, MY = P.max_l1(0), P.max_l1(1)
+    OX, OY = P.omega(0), P.omega(1)
+    mu = nA * np.sqrt(MX * MY)
+    tr = solve(P, "ALT", eps=0.0, max_iters=200, mu0=(mu, mu))
+    for r in tr.rows[:-1]:
+        assert r["egv"] >= 0.0
+    for r in tr.rows[1:]:
+        assert r["gap"] <= 4 * nA / (r["t"] + 1) * np.sqrt(OX * OY * MX * MY)
+
+
+def test_paper_gradient_accounting(kuhn):
+    # 3 products per EGT step; EGT/as adds one for the EGV test and 3 per retry
+    tr = solve(kuhn, "AS", eps=1e-3, max_iters=500)
+    assert tr.products_paper == 4 * tr.iters + 3 * tr.backtracks
+    tr = solve(kuhn, "ALT", eps=1e-3, max_iters=500)
+    assert tr.products_paper == 3 * tr.iters
