@@ -1,0 +1,166 @@
+"""Benchmark: FP64 EGT/as solves of the 1081-hand river endgame on one MI355X.
+
+One step = one complete solve (egt_solve: state creation with the initial-mu
+search, then EGT/as iterations until the saddle gap is <= 1e-3 * pot) of a
+52-card river endgame with 1081 hands per player, bets {0.5, 1, 2 pot,
+all-in} and at most 3 raises (241,063 sequences per player).  The game tables
+are built and resident in HBM before timing starts.
+
+Prints one JSON line: solves/s as the value, iterations/s, p50/p99 solve
+latency, the roofline of the dominant kernel (HIP-event timing of the same
+launch inside this process) and the CPU FP64 oracle timed on a bounded
+sample of the same solve.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "EGT iters/sec and endgame solves/sec to gap<=1e-3·pot; p50/p99 solve latency"
+HBM_PEAK_GBS = 8000.0
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--config", default="c1")
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--variant", default="AS")
+    ap.add_argument("--cpu-sample-iters", type=int, default=60)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--kernel-reps", type=int, default=200)
+    return ap.parse_args()
+
+
+def percentile(xs, q):
+    xs = sorted(xs)
+    if not xs:
+        return float("nan")
+    k = (len(xs) - 1) * q / 100.0
+    lo, hi = int(k), min(int(k) + 1, len(xs) - 1)
+    return xs[lo] + (xs[hi] - xs[lo]) * (k - lo)
+
+
+def kernel_roofline(egt, torch, G, reps):
+    """Average duration of the payoff-product launch (player 1's gradient
+    A y on a treeplex point), HIP events on the stream it runs on."""
+    y = egt.uniform(G, 1)
+    out = G.empty(0)
+    for _ in range(10):
+        egt.gradient(G, 0, y, out)
+    s = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(s)
+    for _ in range(reps):
+        egt.gradient(G, 0, y, out)
+    e1.record(s)
+    e1.synchronize()
+    avg_s = e0.elapsed_time(e1) / 1e3 / reps
+    n_fold, n_show = G.terminals()
+    # algorithmic bytes: one opponent row per terminal read, one output row per
+    # sequence written (8-byte doubles, n hands each)
+    bytes_ = 8.0 * G.n * ((n_fold + n_show) + G.n_seq[0])
+    gbs = bytes_ / avg_s / 1e9
+    return dict(kernel="gradient_kernel", bound="hbm", achieved=round(gbs, 3), peak=HBM_PEAK_GBS, unit="GB/s",
+                frac=round(gbs / HBM_PEAK_GBS, 6), traffic=None, avg_us=round(avg_s * 1e6, 3),
+                algorithmic_bytes=int(bytes_))
+
+
+def cpu_baseline(inst, sample_iters, iters_per_solve, variant):
+    import numpy as np  # noqa: F401
+    from threadpoolctl import threadpool_info
+
+    from oracle import Problem, solve
+
+    P = Problem(inst)
+    t0 = time.perf_counter()
+    tr = solve(P, variant, eps=0.0, max_iters=sample_iters)
+    dt = time.perf_counter() - t0
+    threads = max([d.get("num_threads", 1) for d in threadpool_info()] or [1])
+    ips = tr.iters / dt
+    return dict(value=ips / iters_per_solve, unit="solves/s", cores=int(threads), kind="oracle",
+                sample=f"{tr.iters} EGT/{variant} iterations of the same endgame (incl. start-up) in {dt:.1f} s "
+                       f"= {ips:.3f} iters/s, scaled by {iters_per_solve} iterations per solve",
+                iters_per_sec=ips)
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); multi-GPU sharding is not built.",
+              file=sys.stderr)
+        sys.exit(2)
+    import torch
+
+    from instances import make_instance
+    from paper_1810_03063_amd import egt
+
+    torch.cuda.set_device(0)
+    inst = make_instance(args.config, args.seed)
+    G = egt.Game(inst)
+    torch.cuda.synchronize()
+    for _ in range(args.warmup):
+        r, _ = egt.solve(G, variant=args.variant)
+        print(f"warmup solve: {r['iters']} iters, gap {r['gap']:.4g}, {r['seconds']*1e3:.1f} ms", file=sys.stderr,
+              flush=True)
+    lat = []
+    iters = 0
+    res = None
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        ts = time.perf_counter()
+        res, _ = egt.solve(G, variant=args.variant)
+        lat.append(time.perf_counter() - ts)
+        iters += res["iters"]
+        if res["converged"] != 1:
+            raise RuntimeError(f"solve {k} did not converge: {res}")
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    print(f"timed {args.steps} solves in {elapsed:.3f} s", file=sys.stderr, flush=True)
+    roof = kernel_roofline(egt, torch, G, args.kernel_reps)
+    iters_per_solve = iters / args.steps
+    out = {
+        "metric": METRIC,
+        "value": args.steps / elapsed,
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": elapsed / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": f"{args.config}: 52-card river endgame, {G.n} hands/player, bets "
+                        f"{list(inst.bet_fracs)} pot + all-in, max {inst.max_raises} raises, "
+                        f"{G.n_seq[0] * G.n} sequences/player; FP64 EGT/{args.variant} to gap <= 1e-3*pot",
+            "seed": args.seed,
+            "variant": args.variant,
+            "eps": 1e-3 * inst.pot,
+        },
+        "iters_per_sec": iters / elapsed,
+        "iters_per_solve": iters_per_solve,
+        "p50_ms": percentile(lat, 50) * 1e3,
+        "p99_ms": percentile(lat, 99) * 1e3,
+        "final_gap": res["gap"],
+        "roofline": roof,
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(inst, args.cpu_sample_iters, iters_per_solve, args.variant)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,231 @@
+/*
+ * egt.h -- C ABI of the MI355X EGT library (libegt.so).
+ *
+ * The library solves the bilinear saddle-point problem
+ *     min_{x in X} max_{y in Y} <x, A y>                   (Section 2, Eq. 2)
+ * over the sequence-form strategy polytopes (treeplexes, Section 3) of a
+ * two-player poker river endgame, with the excessive gap technique and the
+ * dilated entropy distance (Sections 2, 4 and 5).  x belongs to player 1, who
+ * acts first and minimises; A holds player 2's payoff (= player 1's loss), with
+ * chance weight pi(h1, h2) = b1(h1) b2(h2) [hands disjoint] / Z.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - Every call returns an int status: EGT_OK (0) or a negative EGT_E* code.
+ *   egt_last_error() returns a human-readable message for the calling
+ *   thread's last failure.  No C++ exception crosses this boundary.
+ * - Strategy and gradient vectors are caller-owned DEVICE pointers of doubles
+ *   in the library's canonical layout  v[seq * ld + slot]:
+ *     seq  : 0 .. n_seq(player)-1 in the library's sequence order (nodes sorted
+ *            by height, a node's actions contiguous); egt_game_layout() gives
+ *            each sequence's betting-history key;
+ *     slot : 0 .. n_hands-1, hands sorted by ascending strength (ties keep the
+ *            caller's order); egt_game_layout() gives slot -> caller hand index;
+ *     ld   : leading dimension >= n_hands (a multiple of 32); entries
+ *            n_hands .. ld-1 of every row are padding: outputs write 0 there and
+ *            inputs ignore them.
+ *   Pointers must be 8-byte aligned (256-byte alignment is faster).
+ * - Device work is enqueued on the given HIP stream (NULL = the null stream)
+ *   and runs asynchronously unless a call says it synchronises.  A game or
+ *   state handle must not be used from two threads at once.
+ * - Handles (egt_game, egt_state) are opaque and owned by the library.
+ */
+#ifndef EGT_H
+#define EGT_H
+
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  EGT_OK = 0,
+  EGT_EINVAL = -1,    /* bad argument: NULL pointer, bad player, shape, mu <= 0 ... */
+  EGT_ENOMEM = -2,    /* device or host allocation failed */
+  EGT_EDEVICE = -3,   /* a HIP runtime call failed */
+  EGT_ENUMERIC = -4,  /* a NaN or infinity appeared in a scalar the driver uses */
+  EGT_ENOTCONV = -5,  /* max_iters reached, or the step size fell below its floor */
+  EGT_EBUDGET = -6    /* serving: the request does not fit the memory budget */
+};
+
+enum { EGT_VARIANT_ALT = 0, EGT_VARIANT_BAL = 1, EGT_VARIANT_AS = 2 };
+enum { EGT_PRECISION_FP64 = 0, EGT_PRECISION_MIXED = 1 };
+
+typedef struct egt_game egt_game;
+typedef struct egt_state egt_state;
+
+/* Thread-local message describing the calling thread's last error. */
+const char* egt_last_error(void);
+
+/* ------------------------------------------------------------------------ */
+/* Game construction (the treeplexes of Section 3 and the terminal tables     */
+/* that define A).                                                           */
+/* ------------------------------------------------------------------------ */
+
+/* One river endgame.  All arrays are HOST memory, read during the call only.
+ * hand_cards  [n_hands * cards_per_hand] card ids in [0, n_cards); two hands
+ *             that share a card cannot be dealt together.
+ * strength    [n_hands] larger wins a showdown, equal strengths split the pot.
+ * belief[p]   [n_hands] player p's prior over its own hands (>= 0, not all 0).
+ * pot         chips in the pot before the river, half from each player.
+ * stack       chips each player can still bet.
+ * Betting: a player not facing a bet checks or bets bet_fracs[i] * pot (plus
+ * all-in if allin != 0); facing a bet it folds, calls, or raises to
+ * c_opp + bet_fracs[i] * (pot + to_call) (plus all-in) while fewer than
+ * max_raises raises followed the opening bet and the opponent is not all-in.
+ * Amounts at or above the stack become all-in; duplicates are dropped.  Check
+ * after check, or a call, is a showdown; a fold ends the hand. */
+typedef struct {
+  int32_t n_cards;
+  int32_t cards_per_hand; /* 1 or 2 */
+  int32_t n_hands;
+  const int32_t* hand_cards;
+  const int32_t* strength;
+  const double* belief[2];
+  double pot;
+  double stack;
+  int32_t n_bet_fracs;
+  const double* bet_fracs;
+  int32_t allin;
+  int32_t max_raises;
+} egt_game_desc;
+
+/* Validates the description, enumerates the betting tree, builds both
+ * players' level-ordered treeplex tables, the per-sequence terminal lists and
+ * the strength-sorted hand tables, and uploads them to the current device.
+ * Synchronises `stream`.  EGT_EINVAL on a bad description (n_hands < 1,
+ * cards_per_hand not 1 or 2, a card id out of range, a node with more than 16
+ * actions, all-zero beliefs or no compatible deal). */
+int egt_build_game(const egt_game_desc* desc, hipStream_t stream, egt_game** out);
+
+/* Releases a game (synchronises the device first).  NULL is accepted. */
+int egt_free_game(egt_game* game);
+
+/* Sizes of one player's vectors: n_seq rows of ld doubles; n_hands live
+ * slots; n_infosets = decision nodes x hands; n_nodes decision nodes.
+ * Any output pointer may be NULL. */
+int egt_game_dims(const egt_game* game, int player, int64_t* n_seq, int64_t* n_hands,
+                  int64_t* ld, int64_t* n_nodes);
+
+/* Layout export.  hand_perm[slot] (n_hands entries, may be NULL) = caller's
+ * hand index at that slot.  keys (may be NULL) receives the betting-history
+ * key of every sequence in library order, '\n'-terminated each; tokens are
+ * joined by '/': "k" check, "f" fold, "c" call, "b<m>" bet or raise to a
+ * total river contribution of m millichips.  *keys_len receives the bytes
+ * needed (including a final NUL); EGT_EINVAL if keys_cap is too small. */
+int egt_game_layout(const egt_game* game, int player, int32_t* hand_perm, char* keys,
+                    int64_t keys_cap, int64_t* keys_len);
+
+/* Total number of terminal histories (fold, showdown) of the game. */
+int egt_game_terminals(const egt_game* game, int64_t* n_fold, int64_t* n_show);
+
+/* ------------------------------------------------------------------------ */
+/* Hot-path operations                                                        */
+/* ------------------------------------------------------------------------ */
+
+/* Payoff-operator product (Section 2: grad f = A y, grad phi = A^T x).
+ * player 0: grad_out (player-1 layout) = A * strat_other (player-2 layout);
+ * player 1: grad_out (player-2 layout) = A^T * strat_other (player-1 layout).
+ * Fold terminals use per-card blocked sums (total minus the mass blocked by
+ * the hand's cards); showdown terminals use strength-sorted prefix sums with a
+ * per-card correction.  Overwrites all of grad_out; no host synchronisation. */
+int egt_gradient(const egt_game* game, int player, const double* strat_other, double* grad_out,
+                 hipStream_t stream);
+
+/* Smoothed best response (Section 4, Eq. 4): argmin over player's treeplex of
+ * <grad, q> + mu d(q), d the dilated entropy, computed bottom-up with a
+ * max-shifted log-sum-exp per information set and top-down to the sequence
+ * form.  Always the minimisation form (player 2 passes -A^T x).
+ * strat_out (device, may be NULL = value only) receives q; value_out (device
+ * pointer to one double, may be NULL) receives the optimal value.
+ * mu must be finite and > 0. */
+int egt_smoothed_br(const egt_game* game, int player, const double* grad, double mu,
+                    double* strat_out, double* value_out, hipStream_t stream);
+
+/* Best-response value min over player's treeplex of <grad, q> (the mu -> 0
+ * limit), written to the device double *value_out. */
+int egt_best_response(const egt_game* game, int player, const double* grad, double* value_out,
+                      hipStream_t stream);
+
+/* The uniform behavioural strategy x_omega (the DGF's minimiser). */
+int egt_uniform(const egt_game* game, int player, double* strat_out, hipStream_t stream);
+
+/* Saddle-point residual (Section 2): gap = max_y x^T A y - min_x x^T A y,
+ * with br_max_y and br_min_x the two terms (expected chips won by player 2).
+ * x, y are device vectors; results are written to HOST doubles (any may be
+ * NULL).  Synchronises `stream`.  Always FP64. */
+int egt_saddle_gap(const egt_game* game, const double* x, const double* y, double* gap,
+                   double* br_max_y, double* br_min_x, hipStream_t stream);
+
+/* ------------------------------------------------------------------------ */
+/* EGT driver (Algorithms 1-4)                                                */
+/* ------------------------------------------------------------------------ */
+
+typedef struct {
+  int32_t variant;    /* EGT_VARIANT_ALT (Alg. 1), _BAL (mu balancing), _AS (Alg. 3/4) */
+  int32_t precision;  /* EGT_PRECISION_FP64 */
+  double eps;         /* target saddle gap; <= 0 means 1e-3 * pot */
+  int64_t max_iters;  /* iteration cap (accepted steps) */
+  double mu0_x;       /* initial mu; <= 0 (both) means automatic with doubling search */
+  double mu0_y;
+  double tau0;        /* EGT/as initial tau; <= 0 means 0.5 */
+  int32_t gap_every;  /* test the gap every k iterations (>= 1) */
+  int32_t reserved;
+} egt_solve_opts;
+
+typedef struct {
+  int64_t iters;       /* accepted steps */
+  int64_t products;    /* payoff products performed on the device */
+  int64_t backtracks;  /* EGT/as tau halvings */
+  double gap;          /* last measured saddle gap */
+  double br_max_y;
+  double br_min_x;
+  double value_p1;     /* -(x^T A y): expected chips won by player 1 */
+  double mu_x, mu_y, tau;
+  double seconds;      /* wall time of the solve (host clock) */
+  int32_t converged;   /* gap <= eps */
+  int32_t reserved;
+} egt_result;
+
+/* Fills `opts` with defaults: AS, FP64, eps = 1e-3 * pot, 100000 iterations,
+ * automatic mu, tau0 = 0.5, gap every iteration. */
+void egt_default_opts(egt_solve_opts* opts);
+
+/* Creates a solver state on `game` (which must outlive it): allocates the
+ * device iterates and runs the start of Algorithms 1/3: y0 = SBR of -A^T x_omega,
+ * x0 = SBR of A y0, with the mu search when opts asks for automatic mu.
+ * Synchronises `stream`. */
+int egt_state_create(const egt_game* game, const egt_solve_opts* opts, hipStream_t stream,
+                     egt_state** out);
+int egt_state_destroy(egt_state* state);
+
+/* One iteration: EGT/as "Decr" (Algorithm 4) or one EGT step (Algorithm 2),
+ * on the side the variant picks (player = -1) or on `player` (0 or 1).
+ * Writes the excessive gap value after the step and the side stepped (host
+ * pointers, may be NULL).  Synchronises `stream`. */
+int egt_step(egt_state* state, int player, double* egv_out, int* player_stepped, hipStream_t stream);
+
+/* Copies the current iterates (device -> device, canonical layout) and the
+ * scalar state.  Any pointer may be NULL. */
+int egt_state_get(const egt_state* state, double* x, double* y, double* mu_x, double* mu_y,
+                  double* tau, int64_t* iters, hipStream_t stream);
+
+/* Saddle gap of the state's current iterates (host outputs; synchronises). */
+int egt_state_gap(egt_state* state, double* gap, double* br_max_y, double* br_min_x,
+                  hipStream_t stream);
+
+/* Runs EGT until gap <= eps (tested before each iteration, every gap_every
+ * iterations) or max_iters.  The final iterates stay in the state if
+ * state_out is not NULL (the caller then owns it), else they are freed.
+ * Returns EGT_OK when converged, EGT_ENOTCONV at the iteration cap (result
+ * still filled). */
+int egt_solve(const egt_game* game, const egt_solve_opts* opts, egt_result* result,
+              egt_state** state_out, hipStream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* EGT_H */

@@ -121,7 +121,7 @@ class Problem:
         q = np.zeros((t.n_seq, self.n))
         for v in reversed(t.post_order):  # parents first
             node = t.nodes[v]
-            q[node.first_seq:node.first_seq + node.n_act] = self._parent_rows(p, q, v)[None, :] / node.n_act
+            q[node.first_seq:node.first_seq + node.n_act] = self._parent_rows(p, q, v)[None, :] * (1.0 / node.n_act)
         return q
 
     def flow_residual(self, p, q):
@@ -221,6 +221,7 @@ class Problem:
         t = self.tp[p]
         V = np.zeros((len(t.nodes), self.n))
         logqbar = np.zeros((t.n_seq, self.n))
+        qbar_all = np.zeros((t.n_seq, self.n))
         for v in t.post_order:  # bottom-up
             node = t.nodes[v]
             sl = slice(node.first_seq, node.first_seq + node.n_act)
@@ -235,6 +236,7 @@ class Problem:
             w = np.exp(-(gt - shift[None, :]) / temp)
             tot = w.sum(axis=0)
             qbar = w / tot[None, :]
+            qbar_all[sl] = qbar
             logqbar[sl] = -(gt - shift[None, :]) / temp - np.log(tot)[None, :]
             i_star = np.argmax(qbar, axis=0)
             cols = np.arange(self.n)
@@ -243,7 +245,7 @@ class Problem:
         for v in reversed(t.post_order):  # top-down
             node = t.nodes[v]
             sl = slice(node.first_seq, node.first_seq + node.n_act)
-            q[sl] = self._parent_rows(p, q, v)[None, :] * np.exp(logqbar[sl])
+            q[sl] = self._parent_rows(p, q, v)[None, :] * qbar_all[sl]
         value = float(sum(V[v].sum() for v in t.roots()))
         return q, value, logqbar, V
 

@@ -1,0 +1,479 @@
+// Game builder: betting tree -> level-ordered treeplex tables, terminal lists
+// and strength-sorted hand tables, uploaded once to the device.
+//
+// Treeplex notation follows Section 3 (Definition 2 and what follows): one
+// simplex per information set (decision node of a player, private hand), the
+// parent sequence p_j, the child simplexes D_j^i after branch i, and the
+// dilation weights beta_j = 2 + sum_{k in D^j} 2 beta_k of Section 4, with D^j
+// the children over all branches.  Terminal payoffs are player 2's chips:
+// each player put pot/2 in before the river; a fold loses the folder's
+// pot/2 + river chips; a showdown moves pot/2 + c to the stronger hand and
+// nothing on a tie (Section 7's endgame structure).
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <functional>
+#include <memory>
+#include <numeric>
+#include <set>
+
+#include "egt_internal.h"
+
+namespace egt {
+
+namespace {
+
+thread_local std::string g_last_error;
+
+struct Act {
+  char kind;  // 'k' check, 'b' bet or raise, 'f' fold, 'c' call
+  double amt; // acting player's river contribution after the action
+  bool raise;
+};
+
+struct RawNode {
+  std::string key;
+  int parent_seq;  // raw sequence index of the player's previous action, -1 = empty
+  std::vector<Act> acts;
+  int first_seq;   // raw index of this node's first sequence
+};
+
+struct RawTerminal {
+  int kind;      // 0 fold, 1 showdown
+  int seq[2];    // raw sequence index per player (-1 = empty)
+  double coef;   // player 2's chips (sign of the showdown applied per deal)
+};
+
+struct Enumerator {
+  double P, S;
+  std::vector<double> fracs;
+  bool allin;
+  int max_raises;
+  std::vector<RawNode> nodes[2];
+  std::vector<std::string> seq_key[2];
+  std::vector<int> seq_node[2];
+  std::vector<RawTerminal> terms;
+
+  static std::string token(const Act& a) {
+    if (a.kind == 'k') return "k";
+    if (a.kind == 'f') return "f";
+    if (a.kind == 'c') return "c";
+    char buf[64];
+    std::snprintf(buf, sizeof buf, "b%lld", (long long)std::nearbyint(a.amt * 1000.0));
+    return buf;
+  }
+
+  std::vector<Act> actions(const double c[2], int p, int raises) const {
+    const int o = 1 - p;
+    const double to_call = c[o] - c[p];
+    const double pot_now = P + c[0] + c[1];
+    std::vector<Act> acts;
+    std::vector<double> amts;
+    if (to_call == 0.0) {
+      acts.push_back({'k', c[p], false});
+      for (double f : fracs) amts.push_back(std::min(c[p] + f * pot_now, S));
+      if (allin) amts.push_back(S);
+      std::sort(amts.begin(), amts.end());
+      amts.erase(std::unique(amts.begin(), amts.end()), amts.end());
+      for (double a : amts)
+        if (a > c[p]) acts.push_back({'b', a, false});
+    } else {
+      acts.push_back({'f', c[p], false});
+      acts.push_back({'c', c[o], false});
+      if (raises < max_raises && c[o] < S) {
+        for (double f : fracs) amts.push_back(std::min(c[o] + f * (pot_now + to_call), S));
+        if (allin) amts.push_back(S);
+        std::sort(amts.begin(), amts.end());
+        amts.erase(std::unique(amts.begin(), amts.end()), amts.end());
+        for (double a : amts)
+          if (a > c[o]) acts.push_back({'b', a, true});
+      }
+    }
+    return acts;
+  }
+
+  // hist: public history key; last[p]: raw index of p's last sequence.
+  void walk(const std::string& hist, const double c[2], int p, int raises, const int last[2]) {
+    RawNode nd;
+    nd.key = hist;
+    nd.parent_seq = last[p];
+    nd.acts = actions(c, p, raises);
+    nd.first_seq = (int)seq_key[p].size();
+    const int node_id = (int)nodes[p].size();
+    for (const Act& a : nd.acts) {
+      seq_key[p].push_back(hist.empty() ? token(a) : hist + "/" + token(a));
+      seq_node[p].push_back(node_id);
+    }
+    nodes[p].push_back(nd);
+    const std::vector<Act> acts = nd.acts;  // nodes[p] may reallocate below
+    const int first = nd.first_seq;
+    const double half = P / 2.0;
+    for (size_t i = 0; i < acts.size(); ++i) {
+      const Act& a = acts[i];
+      const std::string h2 = seq_key[p][first + i];
+      int nl[2] = {last[0], last[1]};
+      nl[p] = first + (int)i;
+      if (a.kind == 'f') {
+        terms.push_back({0, {nl[0], nl[1]}, p == 0 ? (half + c[0]) : -(half + c[1])});
+      } else if (a.kind == 'c') {
+        terms.push_back({1, {nl[0], nl[1]}, half + c[1 - p]});
+      } else if (a.kind == 'k') {
+        if (p == 0)
+          walk(h2, c, 1, raises, nl);
+        else
+          terms.push_back({1, {nl[0], nl[1]}, half + c[0]});
+      } else {
+        double nc[2] = {c[0], c[1]};
+        nc[p] = a.amt;
+        walk(h2, nc, 1 - p, raises + (a.raise ? 1 : 0), nl);
+      }
+    }
+  }
+};
+
+// Heights, level order and the final numbering of one player's treeplex.
+int finish_player(const Enumerator& en, int p, HostPlayer& hp, std::vector<int>& raw2new) {
+  const auto& nodes = en.nodes[p];
+  const int nn = (int)nodes.size();
+  const int ns = (int)en.seq_key[p].size();
+  // children of each raw sequence
+  std::vector<std::vector<int>> kids(ns);
+  for (int v = 0; v < nn; ++v)
+    if (nodes[v].parent_seq >= 0) kids[nodes[v].parent_seq].push_back(v);
+  std::vector<int> height(nn, 0);
+  std::vector<double> beta(nn, 0.0);
+  // raw nodes are in pre-order, so a reverse sweep sees children first
+  for (int v = nn - 1; v >= 0; --v) {
+    int h = 0;
+    double b = 2.0;
+    for (size_t a = 0; a < nodes[v].acts.size(); ++a)
+      for (int k : kids[nodes[v].first_seq + a]) {
+        h = std::max(h, height[k]);
+        b += 2.0 * beta[k];
+      }
+    height[v] = h + 1;
+    beta[v] = b;
+  }
+  std::vector<int> order(nn);
+  std::iota(order.begin(), order.end(), 0);
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return height[a] < height[b]; });
+  std::vector<int> node_new(nn);
+  for (int i = 0; i < nn; ++i) node_new[order[i]] = i;
+  raw2new.assign(ns, -1);
+  hp.n_nodes = nn;
+  hp.n_seq = ns;
+  hp.node_first_seq.resize(nn);
+  hp.node_nact.resize(nn);
+  hp.node_level.resize(nn);
+  hp.node_beta.resize(nn);
+  hp.node_logn.resize(nn);
+  int next = 0;
+  for (int i = 0; i < nn; ++i) {
+    const RawNode& rn = nodes[order[i]];
+    const int na = (int)rn.acts.size();
+    if (na > kMaxActions) return fail(EGT_EINVAL, "a decision node has more than 16 actions");
+    hp.node_first_seq[i] = next;
+    hp.node_nact[i] = na;
+    hp.node_level[i] = height[order[i]];
+    hp.node_beta[i] = beta[order[i]];
+    hp.node_logn[i] = std::log((double)na);
+    for (int a = 0; a < na; ++a) raw2new[rn.first_seq + a] = next + a;
+    next += na;
+  }
+  hp.n_levels = nn ? hp.node_level[nn - 1] : 0;
+  hp.level_begin.assign(hp.n_levels + 1, nn);
+  for (int i = nn - 1; i >= 0; --i) hp.level_begin[hp.node_level[i] - 1] = i;
+  for (int l = hp.n_levels - 1; l >= 0; --l)
+    hp.level_begin[l] = std::min(hp.level_begin[l], hp.level_begin[l + 1]);
+  hp.seq_keys.assign(ns, "");
+  hp.seq_parent.assign(ns, -1);
+  std::vector<std::vector<int>> kids_new(ns);
+  for (int i = 0; i < nn; ++i) {
+    const RawNode& rn = nodes[order[i]];
+    const int par = rn.parent_seq >= 0 ? raw2new[rn.parent_seq] : -1;
+    if (par < 0) hp.roots.push_back(i);
+    for (size_t a = 0; a < rn.acts.size(); ++a) {
+      const int s = hp.node_first_seq[i] + (int)a;
+      hp.seq_keys[s] = en.seq_key[p][rn.first_seq + a];
+      hp.seq_parent[s] = par;
+    }
+    if (par >= 0) kids_new[par].push_back(i);
+  }
+  hp.child_begin.assign(ns + 1, 0);
+  for (int s = 0; s < ns; ++s) hp.child_begin[s + 1] = hp.child_begin[s] + (int)kids_new[s].size();
+  hp.child.clear();
+  for (int s = 0; s < ns; ++s) hp.child.insert(hp.child.end(), kids_new[s].begin(), kids_new[s].end());
+  // longest parent chain (for the top-down pass)
+  int mx = 0;
+  for (int s = 0; s < ns; ++s) {
+    int d = 1;
+    for (int q = hp.seq_parent[s]; q >= 0; q = hp.seq_parent[q]) ++d;
+    mx = std::max(mx, d);
+  }
+  if (mx > kMaxDepth) return fail(EGT_EINVAL, "a player's sequence chain is deeper than 16");
+  hp.max_chain = mx;
+  return EGT_OK;
+}
+
+size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+}  // namespace
+
+void set_error(const std::string& msg) { g_last_error = msg; }
+int fail(int code, const std::string& msg) {
+  set_error(msg);
+  return code;
+}
+int hip_fail(hipError_t e, const char* what) {
+  return fail(EGT_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+const char* last_error_cstr() { return g_last_error.c_str(); }
+
+// Builds every table of a game on the host, then uploads them in one block.
+int build_game(const egt_game_desc* d, hipStream_t stream, egt_game** out) {
+  if (!d || !out) return fail(EGT_EINVAL, "null argument");
+  *out = nullptr;
+  const int n = d->n_hands, cph = d->cards_per_hand, nc = d->n_cards;
+  if (n < 1 || n > 2048 || (cph != 1 && cph != 2) || nc < 1 || nc > 4096)
+    return fail(EGT_EINVAL, "bad n_hands (1..2048) / cards_per_hand (1 or 2) / n_cards");
+  if (!d->hand_cards || !d->strength || !d->belief[0] || !d->belief[1])
+    return fail(EGT_EINVAL, "null hand / strength / belief array");
+  if (!(d->pot > 0) || !(d->stack >= 0) || !std::isfinite(d->pot) || !std::isfinite(d->stack))
+    return fail(EGT_EINVAL, "pot must be > 0 and stack >= 0");
+  if (d->n_bet_fracs < 0 || (d->n_bet_fracs > 0 && !d->bet_fracs) || d->max_raises < 0)
+    return fail(EGT_EINVAL, "bad betting parameters");
+  for (int i = 0; i < d->n_bet_fracs; ++i)
+    if (!(d->bet_fracs[i] > 0) || !std::isfinite(d->bet_fracs[i]))
+      return fail(EGT_EINVAL, "bet fractions must be finite and > 0");
+  std::set<std::vector<int>> seen;
+  for (int h = 0; h < n; ++h) {
+    std::vector<int> cs;
+    for (int j = 0; j < cph; ++j) {
+      const int c = d->hand_cards[h * cph + j];
+      if (c < 0 || c >= nc) return fail(EGT_EINVAL, "card id out of range");
+      cs.push_back(c);
+    }
+    std::sort(cs.begin(), cs.end());
+    if (cph == 2 && cs[0] == cs[1]) return fail(EGT_EINVAL, "a hand holds the same card twice");
+    if (!seen.insert(cs).second) return fail(EGT_EINVAL, "two hands hold the same cards");
+    for (int p = 0; p < 2; ++p)
+      if (!(d->belief[p][h] >= 0) || !std::isfinite(d->belief[p][h]))
+        return fail(EGT_EINVAL, "beliefs must be finite and >= 0");
+  }
+
+  egt_game* g = new (std::nothrow) egt_game();
+  if (!g) return fail(EGT_ENOMEM, "host allocation failed");
+  std::unique_ptr<egt_game> guard(g);
+  g->n = n;
+  g->ld = (n + 31) / 32 * 32;
+  g->cph = cph;
+  g->n_cards = nc;
+  g->pot = d->pot;
+  g->stack = d->stack;
+
+  // ---- betting tree and treeplexes ----
+  Enumerator en;
+  en.P = d->pot;
+  en.S = d->stack;
+  en.fracs.assign(d->bet_fracs, d->bet_fracs + d->n_bet_fracs);
+  en.allin = d->allin != 0;
+  en.max_raises = d->max_raises;
+  const int none[2] = {-1, -1};
+  const double c0[2] = {0.0, 0.0};
+  en.walk("", c0, 0, 0, none);
+  std::vector<int> raw2new[2];
+  for (int p = 0; p < 2; ++p) {
+    const int st = finish_player(en, p, g->hp[p], raw2new[p]);
+    if (st != EGT_OK) return st;
+    if (g->hp[p].n_seq > 65535) return fail(EGT_EINVAL, "more than 65535 sequences for one player");
+  }
+  // terminals grouped by each player's own sequence
+  for (int p = 0; p < 2; ++p) {
+    HostPlayer& hp = g->hp[p];
+    std::vector<std::vector<int>> by(hp.n_seq);
+    for (size_t t = 0; t < en.terms.size(); ++t) {
+      const int s = en.terms[t].seq[p];
+      if (s >= 0) by[raw2new[p][s]].push_back((int)t);
+    }
+    hp.term_begin.assign(hp.n_seq + 1, 0);
+    for (int s = 0; s < hp.n_seq; ++s) {
+      for (int t : by[s]) {
+        const RawTerminal& rt = en.terms[t];
+        const int os = rt.seq[1 - p];
+        hp.term_opp.push_back(os >= 0 ? raw2new[1 - p][os] : -1);
+        hp.term_kind.push_back(rt.kind);
+        hp.term_coef.push_back(rt.coef);
+      }
+      hp.term_begin[s + 1] = (int)hp.term_opp.size();
+    }
+  }
+  for (const RawTerminal& t : en.terms) (t.kind == 0 ? g->n_fold : g->n_show)++;
+  for (int p = 0; p < 2; ++p)
+    for (double b : g->hp[p].node_beta) g->max_beta = std::max(g->max_beta, b);
+
+  // ---- hands: strength order, tie groups, card lists ----
+  std::vector<int> perm(n);
+  std::iota(perm.begin(), perm.end(), 0);
+  std::stable_sort(perm.begin(), perm.end(),
+                   [&](int a, int b) { return d->strength[a] < d->strength[b]; });
+  g->perm = perm;
+  std::vector<int2> tie(n);
+  for (int i = 0; i < n;) {
+    int j = i;
+    while (j < n && d->strength[perm[j]] == d->strength[perm[i]]) ++j;
+    for (int k = i; k < j; ++k) tie[k] = make_int2(i, j);
+    i = j;
+  }
+  std::vector<std::vector<int>> lists(nc);
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < cph; ++j) lists[d->hand_cards[perm[i] * cph + j]].push_back(i);
+  std::vector<int> card_begin(nc + 1, 0), card_hands;
+  for (int c = 0; c < nc; ++c) {
+    card_begin[c + 1] = card_begin[c] + (int)lists[c].size();
+    card_hands.insert(card_hands.end(), lists[c].begin(), lists[c].end());
+  }
+  std::vector<int4> ha(n), hb(n);
+  for (int i = 0; i < n; ++i) {
+    for (int j = 0; j < 2; ++j) {
+      int4 r = make_int4(0, 0, 0, 0);
+      if (j < cph) {
+        const int c = d->hand_cards[perm[i] * cph + j];
+        const auto& L = lists[c];
+        r.x = card_begin[c] + c;
+        r.y = (int)(std::lower_bound(L.begin(), L.end(), tie[i].x) - L.begin());
+        r.z = (int)(std::lower_bound(L.begin(), L.end(), tie[i].y) - L.begin());
+        r.w = (int)L.size();
+      }
+      (j == 0 ? ha : hb)[i] = r;
+    }
+  }
+  // Z = sum over compatible deals of b1 b2
+  std::vector<double> b[2];
+  for (int p = 0; p < 2; ++p) {
+    b[p].assign(g->ld, 0.0);
+    for (int i = 0; i < n; ++i) b[p][i] = d->belief[p][perm[i]];
+  }
+  double Z = 0.0;
+  for (int i = 0; i < n; ++i) {
+    if (b[0][i] == 0.0) continue;
+    double row = 0.0;
+    for (int k = 0; k < n; ++k) {
+      bool share = false;
+      for (int a = 0; a < cph && !share; ++a)
+        for (int c = 0; c < cph; ++c)
+          if (d->hand_cards[perm[i] * cph + a] == d->hand_cards[perm[k] * cph + c]) share = true;
+      if (!share) row += b[1][k];
+    }
+    Z += b[0][i] * row;
+  }
+  if (!(Z > 0) || !std::isfinite(Z)) return fail(EGT_EINVAL, "no compatible deal has positive belief");
+  g->Z = Z;
+
+  // ---- one device block for every table ----
+  struct Piece {
+    const void* src;
+    size_t bytes;
+    size_t off;
+  };
+  std::vector<Piece> pieces;
+  size_t total = 0;
+  auto add = [&](const void* src, size_t bytes) {
+    const size_t off = total;
+    pieces.push_back({src, bytes, off});
+    total = align_up(total + std::max<size_t>(bytes, 1), 256);
+    return off;
+  };
+  struct Offs {
+    size_t first, nact, beta, logn, spar, cbeg, child, tbeg, topp, tkind, tcoef, roots, belief;
+  } po[2];
+  for (int p = 0; p < 2; ++p) {
+    HostPlayer& hp = g->hp[p];
+    po[p].first = add(hp.node_first_seq.data(), hp.node_first_seq.size() * sizeof(int));
+    po[p].nact = add(hp.node_nact.data(), hp.node_nact.size() * sizeof(int));
+    po[p].beta = add(hp.node_beta.data(), hp.node_beta.size() * sizeof(double));
+    po[p].logn = add(hp.node_logn.data(), hp.node_logn.size() * sizeof(double));
+    po[p].spar = add(hp.seq_parent.data(), hp.seq_parent.size() * sizeof(int));
+    po[p].cbeg = add(hp.child_begin.data(), hp.child_begin.size() * sizeof(int));
+    po[p].child = add(hp.child.data(), hp.child.size() * sizeof(int));
+    po[p].tbeg = add(hp.term_begin.data(), hp.term_begin.size() * sizeof(int));
+    po[p].topp = add(hp.term_opp.data(), hp.term_opp.size() * sizeof(int));
+    po[p].tkind = add(hp.term_kind.data(), hp.term_kind.size() * sizeof(int));
+    po[p].tcoef = add(hp.term_coef.data(), hp.term_coef.size() * sizeof(double));
+    po[p].roots = add(hp.roots.data(), hp.roots.size() * sizeof(int));
+    po[p].belief = add(b[p].data(), b[p].size() * sizeof(double));
+  }
+  const size_t o_cbeg = add(card_begin.data(), card_begin.size() * sizeof(int));
+  const size_t o_chands = add(card_hands.data(), card_hands.size() * sizeof(int));
+  const size_t o_ha = add(ha.data(), ha.size() * sizeof(int4));
+  const size_t o_hb = add(hb.data(), hb.size() * sizeof(int4));
+  const size_t o_tie = add(tie.data(), tie.size() * sizeof(int2));
+
+  std::vector<unsigned char> staging(total, 0);
+  for (const Piece& pc : pieces)
+    if (pc.bytes) std::memcpy(staging.data() + pc.off, pc.src, pc.bytes);
+  EGT_HIP(hipGetDevice(&g->device));
+  void* dev = nullptr;
+  hipError_t e = hipMalloc(&dev, total);
+  if (e != hipSuccess) return fail(EGT_ENOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
+  g->mem.base = dev;
+  g->mem.bytes = total;
+  e = hipMemcpyAsync(dev, staging.data(), total, hipMemcpyHostToDevice, stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(stream);
+  if (e != hipSuccess) {
+    (void)hipFree(dev);
+    g->mem.base = nullptr;
+    return hip_fail(e, "upload of game tables");
+  }
+  auto at = [&](size_t off) { return (const void*)((const unsigned char*)dev + off); };
+  for (int p = 0; p < 2; ++p) {
+    HostPlayer& hp = g->hp[p];
+    DPlayer& dp = g->dp[p];
+    dp.n_seq = hp.n_seq;
+    dp.n_nodes = hp.n_nodes;
+    dp.n_roots = (int)hp.roots.size();
+    dp.node_first_seq = (const int*)at(po[p].first);
+    dp.node_nact = (const int*)at(po[p].nact);
+    dp.node_beta = (const double*)at(po[p].beta);
+    dp.node_logn = (const double*)at(po[p].logn);
+    dp.seq_parent = (const int*)at(po[p].spar);
+    dp.child_begin = (const int*)at(po[p].cbeg);
+    dp.child = (const int*)at(po[p].child);
+    dp.term_begin = (const int*)at(po[p].tbeg);
+    dp.term_opp = (const int*)at(po[p].topp);
+    dp.term_kind = (const int*)at(po[p].tkind);
+    dp.term_coef = (const double*)at(po[p].tcoef);
+    dp.roots = (const int*)at(po[p].roots);
+    dp.belief = (const double*)at(po[p].belief);
+  }
+  DHands& dh = g->dh;
+  dh.n = n;
+  dh.ld = g->ld;
+  dh.cph = cph;
+  dh.n_cards = nc;
+  dh.n_card_slots = card_begin[nc] + nc;
+  dh.card_begin = (const int*)at(o_cbeg);
+  dh.card_hands = (const int*)at(o_chands);
+  dh.ha = (const int4*)at(o_ha);
+  dh.hb = (const int4*)at(o_hb);
+  dh.tie = (const int2*)at(o_tie);
+  dh.invZ = 1.0 / Z;
+  *out = guard.release();
+  return EGT_OK;
+}
+
+int free_game(egt_game* g) {
+  if (!g) return EGT_OK;
+  int st = EGT_OK;
+  if (g->mem.base || g->ws.block || g->ws.hscal) {
+    hipError_t e = hipDeviceSynchronize();
+    if (e == hipSuccess && g->mem.base) e = hipFree(g->mem.base);
+    if (e == hipSuccess && g->ws.block) e = hipFree(g->ws.block);
+    if (e == hipSuccess && g->ws.hscal) e = hipHostFree(g->ws.hscal);
+    if (e != hipSuccess) st = hip_fail(e, "free_game");
+  }
+  delete g;
+  return st;
+}
+
+}  // namespace egt

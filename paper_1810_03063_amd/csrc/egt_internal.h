@@ -1,0 +1,163 @@
+// Internal declarations of libegt: device tables, kernel argument blocks and
+// launchers.  Not part of the public ABI (include/egt.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "egt.h"
+
+namespace egt {
+
+constexpr int kMaxActions = 16;  // actions per decision node
+constexpr int kMaxDepth = 16;    // sequences on a root-to-leaf chain of one player
+
+// ---------------------------------------------------------------------------
+// Error plumbing: every entry point converts failures into a status code and a
+// thread-local message.
+// ---------------------------------------------------------------------------
+void set_error(const std::string& msg);
+int fail(int code, const std::string& msg);
+int hip_fail(hipError_t e, const char* what);
+
+#define EGT_HIP(call)                                   \
+  do {                                                  \
+    hipError_t _e = (call);                             \
+    if (_e != hipSuccess) return ::egt::hip_fail(_e, #call); \
+  } while (0)
+
+// ---------------------------------------------------------------------------
+// Device-side views (passed by value to kernels).
+// ---------------------------------------------------------------------------
+
+// One player's treeplex, in level order: nodes sorted by height (height 1 =
+// no own decision below), each node's sequences contiguous.
+struct DPlayer {
+  int n_seq;
+  int n_nodes;
+  int n_roots;
+  const int* node_first_seq;   // [n_nodes]
+  const int* node_nact;        // [n_nodes]
+  const double* node_beta;     // [n_nodes] dilation weight beta_j
+  const double* node_logn;     // [n_nodes] log(number of actions)
+  const int* seq_parent;       // [n_seq] parent sequence of the sequence's node, -1 at a root
+  const int* child_begin;      // [n_seq + 1] CSR: sequence -> child nodes
+  const int* child;            // child node ids
+  const int* term_begin;       // [n_seq + 1] CSR: sequence -> terminals ending there
+  const int* term_opp;         // opponent's last sequence at the terminal (-1 = empty)
+  const int* term_kind;        // 0 fold, 1 showdown
+  const double* term_coef;     // player 2's chips at the terminal (times the sign at a showdown)
+  const int* roots;            // [n_roots] root node ids
+  const double* belief;        // [ld] this player's prior in slot order, 0 in the padding
+};
+
+// Hands in strength-ascending slot order, with the card tables the O(n) leaf
+// evaluation needs.  For a hand in slot i:
+//   tie group [glo, ghi): slots with the same strength;
+//   for each of its cards c: base = card_begin[c] + c (start of the card's
+//   prefix array), len = hands holding c, lo / hi = how many of those hands sit
+//   before glo / ghi in slot order.
+struct DHands {
+  int n;
+  int ld;
+  int cph;
+  int n_cards;
+  int n_card_slots;            // card_begin[n_cards] + n_cards
+  const int* card_begin;       // [n_cards + 1]
+  const int* card_hands;       // slots holding each card, ascending
+  const int4* ha;              // [n] {base, lo, hi, len} of the first card
+  const int4* hb;              // [n] same for the second card (unused when cph == 1)
+  const int2* tie;             // [n] {glo, ghi}
+  double invZ;                 // 1 / sum of b1 b2 over compatible deals
+};
+
+// ---------------------------------------------------------------------------
+// Host-side tables kept with a game.
+// ---------------------------------------------------------------------------
+struct HostPlayer {
+  int n_seq = 0, n_nodes = 0, n_levels = 0, max_chain = 0;
+  std::vector<int> node_first_seq, node_nact, node_level;
+  std::vector<double> node_beta, node_logn;
+  std::vector<int> level_begin;  // [n_levels + 1]
+  std::vector<int> seq_parent, child_begin, child;
+  std::vector<int> term_begin, term_opp, term_kind;
+  std::vector<double> term_coef;
+  std::vector<int> roots;
+  std::vector<std::string> seq_keys;
+};
+
+struct DeviceBlock {  // one hipMalloc holding many tables
+  void* base = nullptr;
+  size_t bytes = 0;
+};
+
+// Scratch of the single-operation entry points (egt_smoothed_br,
+// egt_best_response, egt_saddle_gap): per player a gradient, a q_bar and a
+// node-value buffer, plus device scalars.  Allocated on first use, owned by
+// the game.
+struct Workspace {
+  void* block = nullptr;
+  double* grad[2] = {};
+  double* qb[2] = {};
+  double* v[2] = {};
+  double* scal = nullptr;
+  double* hscal = nullptr;  // pinned host mirror of scal
+};
+
+}  // namespace egt
+
+struct egt_game {
+  int n = 0, ld = 0, cph = 0, n_cards = 0;
+  double pot = 0, stack = 0, Z = 0;
+  int64_t n_fold = 0, n_show = 0;
+  egt::HostPlayer hp[2];
+  std::vector<int> perm;  // slot -> caller hand index
+  egt::DPlayer dp[2];
+  egt::DHands dh;
+  egt::DeviceBlock mem;
+  egt::Workspace ws;
+  int device = 0;
+  double max_beta = 0;
+};
+
+namespace egt {
+
+// ---------------------------------------------------------------------------
+// Launchers (egt_kernels.hip).  All enqueue on `s` and return hipError_t.
+// ---------------------------------------------------------------------------
+
+// grad_out = A v_opp (player 0) or A^T v_opp (player 1).
+hipError_t launch_gradient(const egt_game* g, int player, const double* v_opp, double* grad_out,
+                           hipStream_t s);
+
+// Bottom-up pass over all levels of `player`'s treeplex on the gradient
+// cA * gA + cB * gB (gB may be null).  mu > 0: smoothed (log-sum-exp) values,
+// q_bar written to QB when QB != null; mu == 0: best-response (min) values.
+hipError_t launch_bottom_up(const egt_game* g, int player, const double* gA, double cA,
+                            const double* gB, double cB, double mu, double* V, double* QB,
+                            hipStream_t s);
+
+// Top-down pass: q = product of q_bar along the sequence's chain.  Writes q to
+// q_out (may be null) and (1 - tau) x_prev + tau q to comb_out (may be null).
+hipError_t launch_top_down(const egt_game* g, int player, const double* QB, double* q_out,
+                           const double* x_prev, double tau, double* comb_out, hipStream_t s);
+
+// QB = 1 / (number of actions) everywhere (the uniform point's q_bar).
+hipError_t launch_uniform_qbar(const egt_game* g, int player, double* QB, hipStream_t s);
+
+// out[0] = cA * sum(roots of A) + cB * sum(roots of B); out[1], out[2] = the two
+// sums.  playerB < 0 disables B.
+hipError_t launch_root_sum(const egt_game* g, int playerA, const double* VA, double cA,
+                           int playerB, const double* VB, double cB, double* out, hipStream_t s);
+
+// out = a * X + b * Y over rows x ld doubles (Y may be null).
+hipError_t launch_axpby(int64_t count, double a, const double* X, double b, const double* Y,
+                        double* out, hipStream_t s);
+
+// out[0] = max |X| over count doubles.
+hipError_t launch_max_abs(int64_t count, const double* X, double* out, hipStream_t s);
+
+}  // namespace egt

@@ -1,0 +1,314 @@
+"""Python binding of libegt (the C ABI in include/egt.h).
+
+Argument marshalling only: every computation runs in the HIP kernels of
+libegt.so.  PyTorch provides device memory (float64 CUDA tensors) and the
+current HIP stream.  Importing this module fails with ImportError when the
+library has not been built (python -m paper_1810_03063_amd.build).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+import torch
+
+_LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libegt.so")
+if not os.path.exists(_LIB_PATH):
+    raise ImportError(f"{_LIB_PATH} is missing: build it with `python -m paper_1810_03063_amd.build`")
+_lib = ctypes.CDLL(_LIB_PATH)
+
+EGT_OK = 0
+ERRORS = {-1: "EGT_EINVAL", -2: "EGT_ENOMEM", -3: "EGT_EDEVICE", -4: "EGT_ENUMERIC",
+          -5: "EGT_ENOTCONV", -6: "EGT_EBUDGET"}
+VARIANTS = {"ALT": 0, "BAL": 1, "AS": 2}
+
+_p = ctypes.c_void_p
+_i32 = ctypes.c_int32
+_i64 = ctypes.c_int64
+_f64 = ctypes.c_double
+
+
+class EgtError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{ERRORS.get(code, code)}: {msg}")
+        self.code = code
+
+
+class GameDesc(ctypes.Structure):
+    _fields_ = [
+        ("n_cards", _i32), ("cards_per_hand", _i32), ("n_hands", _i32),
+        ("hand_cards", _p), ("strength", _p), ("belief", _p * 2),
+        ("pot", _f64), ("stack", _f64),
+        ("n_bet_fracs", _i32), ("bet_fracs", _p),
+        ("allin", _i32), ("max_raises", _i32),
+    ]
+
+
+class SolveOpts(ctypes.Structure):
+    _fields_ = [
+        ("variant", _i32), ("precision", _i32), ("eps", _f64), ("max_iters", _i64),
+        ("mu0_x", _f64), ("mu0_y", _f64), ("tau0", _f64), ("gap_every", _i32), ("reserved", _i32),
+    ]
+
+
+class SolveResult(ctypes.Structure):
+    _fields_ = [
+        ("iters", _i64), ("products", _i64), ("backtracks", _i64),
+        ("gap", _f64), ("br_max_y", _f64), ("br_min_x", _f64), ("value_p1", _f64),
+        ("mu_x", _f64), ("mu_y", _f64), ("tau", _f64), ("seconds", _f64),
+        ("converged", _i32), ("reserved", _i32),
+    ]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
+
+
+def _decl(name, restype, *args):
+    f = getattr(_lib, name)
+    f.restype = restype
+    f.argtypes = list(args)
+    return f
+
+
+_last_error = _decl("egt_last_error", ctypes.c_char_p)
+_default_opts = _decl("egt_default_opts", None, ctypes.POINTER(SolveOpts))
+_build_game = _decl("egt_build_game", ctypes.c_int, ctypes.POINTER(GameDesc), _p, ctypes.POINTER(_p))
+_free_game = _decl("egt_free_game", ctypes.c_int, _p)
+_game_dims = _decl("egt_game_dims", ctypes.c_int, _p, ctypes.c_int, ctypes.POINTER(_i64),
+                   ctypes.POINTER(_i64), ctypes.POINTER(_i64), ctypes.POINTER(_i64))
+_game_layout = _decl("egt_game_layout", ctypes.c_int, _p, ctypes.c_int, _p, _p, _i64, ctypes.POINTER(_i64))
+_game_terminals = _decl("egt_game_terminals", ctypes.c_int, _p, ctypes.POINTER(_i64), ctypes.POINTER(_i64))
+_gradient = _decl("egt_gradient", ctypes.c_int, _p, ctypes.c_int, _p, _p, _p)
+_smoothed_br = _decl("egt_smoothed_br", ctypes.c_int, _p, ctypes.c_int, _p, _f64, _p, _p, _p)
+_best_response = _decl("egt_best_response", ctypes.c_int, _p, ctypes.c_int, _p, _p, _p)
+_uniform = _decl("egt_uniform", ctypes.c_int, _p, ctypes.c_int, _p, _p)
+_saddle_gap = _decl("egt_saddle_gap", ctypes.c_int, _p, _p, _p, ctypes.POINTER(_f64), ctypes.POINTER(_f64),
+                    ctypes.POINTER(_f64), _p)
+_state_create = _decl("egt_state_create", ctypes.c_int, _p, ctypes.POINTER(SolveOpts), _p, ctypes.POINTER(_p))
+_state_destroy = _decl("egt_state_destroy", ctypes.c_int, _p)
+_step = _decl("egt_step", ctypes.c_int, _p, ctypes.c_int, ctypes.POINTER(_f64), ctypes.POINTER(ctypes.c_int), _p)
+_state_get = _decl("egt_state_get", ctypes.c_int, _p, _p, _p, ctypes.POINTER(_f64), ctypes.POINTER(_f64),
+                   ctypes.POINTER(_f64), ctypes.POINTER(_i64), _p)
+_state_gap = _decl("egt_state_gap", ctypes.c_int, _p, ctypes.POINTER(_f64), ctypes.POINTER(_f64),
+                   ctypes.POINTER(_f64), _p)
+_solve = _decl("egt_solve", ctypes.c_int, _p, ctypes.POINTER(SolveOpts), ctypes.POINTER(SolveResult),
+               ctypes.POINTER(_p), _p)
+
+EXPORTED = [
+    "egt_last_error", "egt_default_opts", "egt_build_game", "egt_free_game", "egt_game_dims",
+    "egt_game_layout", "egt_game_terminals", "egt_gradient", "egt_smoothed_br", "egt_best_response",
+    "egt_uniform", "egt_saddle_gap", "egt_state_create", "egt_state_destroy", "egt_step",
+    "egt_state_get", "egt_state_gap", "egt_solve",
+]
+
+
+def _check(rc, allow=()):
+    if rc != EGT_OK and rc not in allow:
+        raise EgtError(rc, (_last_error() or b"").decode())
+    return rc
+
+
+def _stream(stream=None):
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _dptr(t, shape=None):
+    if t is None:
+        return None
+    if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.float64 and t.is_contiguous()):
+        raise ValueError("expected a contiguous float64 CUDA tensor")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"expected shape {tuple(shape)}, got {tuple(t.shape)}")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class Game:
+    """A river endgame uploaded to the current device (egt_build_game)."""
+
+    def __init__(self, inst, stream=None):
+        self._h = None
+        cards = np.ascontiguousarray(inst.hand_cards, dtype=np.int32)
+        strength = np.ascontiguousarray(inst.strength, dtype=np.int32)
+        b = [np.ascontiguousarray(inst.belief[p], dtype=np.float64) for p in (0, 1)]
+        fr = np.ascontiguousarray(inst.bet_fracs, dtype=np.float64)
+        d = GameDesc()
+        d.n_cards = inst.n_cards
+        d.cards_per_hand = inst.cards_per_hand
+        d.n_hands = inst.n_hands
+        d.hand_cards = cards.ctypes.data
+        d.strength = strength.ctypes.data
+        d.belief[0] = b[0].ctypes.data
+        d.belief[1] = b[1].ctypes.data
+        d.pot = inst.pot
+        d.stack = inst.stack
+        d.n_bet_fracs = len(fr)
+        d.bet_fracs = fr.ctypes.data if len(fr) else None
+        d.allin = 1 if inst.allin else 0
+        d.max_raises = inst.max_raises
+        h = _p()
+        _check(_build_game(ctypes.byref(d), _stream(stream), ctypes.byref(h)))
+        self._h = h
+        self.inst = inst
+        self.pot = inst.pot
+        dims = [self._dims(p) for p in (0, 1)]
+        self.n_seq = [d_[0] for d_ in dims]
+        self.n = dims[0][1]
+        self.ld = dims[0][2]
+        self.n_nodes = [d_[3] for d_ in dims]
+
+    def _dims(self, p):
+        a, b, c, d = _i64(), _i64(), _i64(), _i64()
+        _check(_game_dims(self._h, p, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c), ctypes.byref(d)))
+        return a.value, b.value, c.value, d.value
+
+    @property
+    def handle(self):
+        return self._h
+
+    def layout(self, p):
+        """(sequence keys in library order, slot -> instance hand index)."""
+        need = _i64()
+        _check(_game_layout(self._h, p, None, None, 0, ctypes.byref(need)))
+        buf = ctypes.create_string_buffer(need.value)
+        perm = np.zeros(self.n, dtype=np.int32)
+        _check(_game_layout(self._h, p, ctypes.c_void_p(perm.ctypes.data), buf, need.value, ctypes.byref(need)))
+        keys = buf.value.decode().split("\n")[:-1]
+        return keys, perm
+
+    def terminals(self):
+        f, s = _i64(), _i64()
+        _check(_game_terminals(self._h, ctypes.byref(f), ctypes.byref(s)))
+        return f.value, s.value
+
+    def empty(self, p, device="cuda"):
+        return torch.zeros((self.n_seq[p], self.ld), dtype=torch.float64, device=device)
+
+    def close(self):
+        if self._h is not None:
+            _check(_free_game(self._h))
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def gradient(game: Game, player: int, strat_other, out=None, stream=None):
+    """A y (player 0) or A^T x (player 1) into out (allocated if None)."""
+    if out is None:
+        out = game.empty(player)
+    _check(_gradient(game.handle, player, _dptr(strat_other, (game.n_seq[1 - player], game.ld)),
+                     _dptr(out, (game.n_seq[player], game.ld)), _stream(stream)))
+    return out
+
+
+def smoothed_br(game: Game, player: int, grad, mu: float, strat_out=None, value_out=None, stream=None):
+    """argmin_q <grad, q> + mu d(q): returns (strategy tensor, value tensor[1])."""
+    if strat_out is None:
+        strat_out = game.empty(player)
+    if value_out is None:
+        value_out = torch.zeros(1, dtype=torch.float64, device=grad.device)
+    _check(_smoothed_br(game.handle, player, _dptr(grad, (game.n_seq[player], game.ld)), float(mu),
+                        _dptr(strat_out, (game.n_seq[player], game.ld)), _dptr(value_out), _stream(stream)))
+    return strat_out, value_out
+
+
+def best_response(game: Game, player: int, grad, value_out=None, stream=None):
+    if value_out is None:
+        value_out = torch.zeros(1, dtype=torch.float64, device=grad.device)
+    _check(_best_response(game.handle, player, _dptr(grad, (game.n_seq[player], game.ld)), _dptr(value_out),
+                          _stream(stream)))
+    return value_out
+
+
+def uniform(game: Game, player: int, out=None, stream=None):
+    if out is None:
+        out = game.empty(player)
+    _check(_uniform(game.handle, player, _dptr(out, (game.n_seq[player], game.ld)), _stream(stream)))
+    return out
+
+
+def saddle_gap(game: Game, x, y, stream=None):
+    """(gap, max_y x^T A y, min_x x^T A y) as Python floats."""
+    g, a, b = _f64(), _f64(), _f64()
+    _check(_saddle_gap(game.handle, _dptr(x, (game.n_seq[0], game.ld)), _dptr(y, (game.n_seq[1], game.ld)),
+                       ctypes.byref(g), ctypes.byref(a), ctypes.byref(b), _stream(stream)))
+    return g.value, a.value, b.value
+
+
+def make_opts(variant="AS", eps=None, max_iters=100000, mu0=None, tau0=0.5, gap_every=1):
+    o = SolveOpts()
+    _default_opts(ctypes.byref(o))
+    o.variant = VARIANTS[variant] if isinstance(variant, str) else int(variant)
+    o.eps = 0.0 if eps is None else float(eps)
+    o.max_iters = int(max_iters)
+    if mu0 is not None:
+        o.mu0_x, o.mu0_y = float(mu0[0]), float(mu0[1])
+    o.tau0 = float(tau0)
+    o.gap_every = int(gap_every)
+    return o
+
+
+class State:
+    """Device-resident EGT iterates (egt_state_create / egt_step)."""
+
+    def __init__(self, game: Game, stream=None, handle=None, **opts):
+        self.game = game
+        self._h = None
+        if handle is not None:
+            self._h = handle
+            return
+        o = make_opts(**opts)
+        h = _p()
+        _check(_state_create(game.handle, ctypes.byref(o), _stream(stream), ctypes.byref(h)))
+        self._h = h
+
+    def step(self, player=-1, stream=None):
+        egv = _f64()
+        side = ctypes.c_int()
+        _check(_step(self._h, int(player), ctypes.byref(egv), ctypes.byref(side), _stream(stream)))
+        return egv.value, side.value
+
+    def gap(self, stream=None):
+        g, a, b = _f64(), _f64(), _f64()
+        _check(_state_gap(self._h, ctypes.byref(g), ctypes.byref(a), ctypes.byref(b), _stream(stream)))
+        return g.value, a.value, b.value
+
+    def get(self, stream=None):
+        x = self.game.empty(0)
+        y = self.game.empty(1)
+        mx, my, tau = _f64(), _f64(), _f64()
+        it = _i64()
+        _check(_state_get(self._h, _dptr(x), _dptr(y), ctypes.byref(mx), ctypes.byref(my), ctypes.byref(tau),
+                          ctypes.byref(it), _stream(stream)))
+        return dict(x=x, y=y, mu_x=mx.value, mu_y=my.value, tau=tau.value, iters=it.value)
+
+    def close(self):
+        if self._h is not None:
+            _check(_state_destroy(self._h))
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def solve(game: Game, keep_state=False, stream=None, **opts):
+    """egt_solve: returns (result dict, State or None)."""
+    o = make_opts(**opts)
+    res = SolveResult()
+    h = _p()
+    rc = _solve(game.handle, ctypes.byref(o), ctypes.byref(res), ctypes.byref(h) if keep_state else None,
+                _stream(stream))
+    _check(rc, allow=(-5,))
+    out = res.as_dict()
+    out["status"] = ERRORS.get(rc, "EGT_OK") if rc else "EGT_OK"
+    st = State(game, handle=h) if keep_state and h.value else None
+    return out, st

@@ -1,0 +1,186 @@
+"""GPU parity of the single operations against the CPU FP64 oracle.
+
+Products (fold and showdown leaves with card removal), smoothed best response
+(strategy and value), best response, the uniform point and the saddle gap,
+on Kuhn poker (one-card hands), tiny endgames, the 105-hand endgame, the
+1081-hand endgame and the large 1081-hand tree.  Inputs are seeded; the
+library's layout is matched to the oracle's by sequence key and hand slot.
+"""
+import numpy as np
+import pytest
+
+from instances import make_instance
+from oracle import Problem
+from tests.layout import Layout
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def egt():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1810_03063_amd import egt as mod
+
+    return mod
+
+
+_CACHE = {}
+
+
+def setup(egt, cfg, seed=0, inst=None):
+    key = (cfg, seed) if inst is None else None
+    if key in _CACHE:
+        return _CACHE[key]
+    inst = inst if inst is not None else make_instance(cfg, seed)
+    print(f"[case] build {cfg} seed={seed} hands={inst.n_hands}", flush=True)
+    P = Problem(inst)
+    G = egt.Game(inst)
+    L = Layout(G, P)
+    out = (inst, P, G, L)
+    if key is not None:
+        _CACHE[key] = out
+    return out
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda")
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def random_point(P, p, rng, alpha=1.0):
+    t = P.tp[p]
+    q = np.zeros((t.n_seq, P.n))
+    for v in reversed(t.post_order):
+        node = t.nodes[v]
+        par = np.ones(P.n) if node.parent_seq < 0 else q[node.parent_seq]
+        q[node.first_seq:node.first_seq + node.n_act] = par[None, :] * rng.dirichlet(
+            alpha * np.ones(node.n_act), size=P.n).T
+    return q
+
+
+def grad_bound(P, p, v_opp):
+    """Per entry: (b_own(h)/Z) * sum over terminals at the sequence of
+    |u(z)| * sum_h' |b_opp(h') v_opp[sigma_opp(z), h']| -- the sum of the
+    absolute values of the terms the entry adds up."""
+    o = 1 - p
+    S = np.zeros(P.n_seq[p])
+    for z in P.game.terminals:
+        s_own, s_opp = z.seq[p], z.seq[o]
+        if s_own < 0:
+            continue
+        row = np.ones(P.n) if s_opp < 0 else v_opp[s_opp]
+        S[s_own] += abs(z.u) * np.sum(np.abs(P.b[o] * row))
+    return (P.b[p] / P.Z)[None, :] * S[:, None]
+
+
+CASES = [("kuhn", 0), ("micro", 0), ("micro", 5), ("c0", 0), ("c0", 3), ("c1", 0), ("c3", 0)]
+
+
+@pytest.mark.parametrize("cfg,seed", CASES)
+def test_gradient_parity(egt, cfg, seed):
+    inst, P, G, L = setup(egt, cfg, seed)
+    rng = np.random.default_rng(100 + seed)
+    for kind in ("treeplex", "signed"):
+        if kind == "treeplex":
+            x, y = random_point(P, 0, rng, 0.5), random_point(P, 1, rng, 0.5)
+        else:
+            x = rng.standard_normal((P.n_seq[0], P.n))
+            y = rng.standard_normal((P.n_seq[1], P.n))
+        print(f"[case] gradient {cfg} seed={seed} {kind}", flush=True)
+        gx = host(egt.gradient(G, 0, dev(L.to_lib(1, y))))
+        gy = host(egt.gradient(G, 1, dev(L.to_lib(0, x))))
+        assert np.all(gx[:, P.n:] == 0) and np.all(gy[:, P.n:] == 0)
+        want_x, want_y = P.grad_x(y), P.grad_y(x)
+        err_x = np.abs(L.from_lib(0, gx) - want_x)
+        err_y = np.abs(L.from_lib(1, gy) - want_y)
+        assert np.all(err_x <= 1e-12 * grad_bound(P, 0, y) + 1e-300)
+        assert np.all(err_y <= 1e-12 * grad_bound(P, 1, x) + 1e-300)
+
+
+@pytest.mark.parametrize("cfg,seed", CASES)
+def test_smoothed_best_response_parity(egt, cfg, seed):
+    inst, P, G, L = setup(egt, cfg, seed)
+    rng = np.random.default_rng(200 + seed)
+    for p in (0, 1):
+        g = rng.standard_normal((P.n_seq[p], P.n)) * 10.0
+        for mu in (3.0, 0.05):
+            print(f"[case] sbr {cfg} seed={seed} player={p} mu={mu}", flush=True)
+            q, val = egt.smoothed_br(G, p, dev(L.to_lib(p, g)), mu)
+            q, val = host(q), float(host(val)[0])
+            q_o, val_o, _, V = P.sbr(p, g, mu)
+            assert np.all(q[:, P.n:] == 0)
+            assert np.abs(L.from_lib(p, q) - q_o).max() <= 1e-12
+            scale = np.abs(V).sum() + 1.0
+            assert abs(val - val_o) <= 1e-13 * scale
+
+
+@pytest.mark.parametrize("cfg,seed", CASES)
+def test_best_response_uniform_and_gap_parity(egt, cfg, seed):
+    inst, P, G, L = setup(egt, cfg, seed)
+    rng = np.random.default_rng(300 + seed)
+    for p in (0, 1):
+        print(f"[case] uniform/br {cfg} seed={seed} player={p}", flush=True)
+        u = host(egt.uniform(G, p))
+        assert np.abs(L.from_lib(p, u) - P.uniform(p)).max() <= 1e-15
+        g = rng.standard_normal((P.n_seq[p], P.n))
+        v = float(host(egt.best_response(G, p, dev(L.to_lib(p, g))))[0])
+        assert abs(v - P.br(p, g)) <= 1e-13 * (np.abs(g).sum() + 1.0)
+    x, y = random_point(P, 0, rng), random_point(P, 1, rng)
+    print(f"[case] saddle gap {cfg} seed={seed}", flush=True)
+    gap, brmax, brmin = egt.saddle_gap(G, dev(L.to_lib(0, x)), dev(L.to_lib(1, y)))
+    gap_o, brmax_o, brmin_o = P.saddle_gap(x, y)
+    tol = 1e-10 * (abs(brmax_o) + abs(brmin_o)) + 1e-300
+    assert abs(gap - gap_o) <= tol and abs(brmax - brmax_o) <= tol and abs(brmin - brmin_o) <= tol
+    assert gap >= -1e-12 * (abs(brmax_o) + abs(brmin_o))
+
+
+def _edge_instances():
+    base = make_instance("c0", 7)
+    n = base.n_hands
+    b = base.belief.copy()
+    b[0, ::7] = 0.0  # hands player 1 never holds
+    b[1, 3::11] = 0.0
+    b /= b.sum(axis=1, keepdims=True)
+    from dataclasses import replace
+
+    yield "zero-beliefs", replace(base, belief=b)
+    yield "all-tied", replace(base, strength=np.zeros(n, dtype=np.int32))
+    yield "all-distinct", replace(base, strength=np.random.default_rng(1).permutation(n).astype(np.int32))
+    yield "no-raise", replace(base, max_raises=0)
+    yield "no-bets", replace(base, bet_fracs=(), allin=False)
+
+
+@pytest.mark.parametrize("name", ["zero-beliefs", "all-tied", "all-distinct", "no-raise", "no-bets"])
+def test_edge_cases(egt, name):
+    inst = dict(_edge_instances())[name]
+    _, P, G, L = setup(egt, name, 0, inst=inst)
+    rng = np.random.default_rng(5)
+    x, y = random_point(P, 0, rng), random_point(P, 1, rng)
+    gx = host(egt.gradient(G, 0, dev(L.to_lib(1, y))))
+    assert np.all(np.abs(L.from_lib(0, gx) - P.grad_x(y)) <= 1e-12 * grad_bound(P, 0, y) + 1e-300)
+    gy = host(egt.gradient(G, 1, dev(L.to_lib(0, x))))
+    assert np.all(np.abs(L.from_lib(1, gy) - P.grad_y(x)) <= 1e-12 * grad_bound(P, 1, x) + 1e-300)
+    g = rng.standard_normal((P.n_seq[0], P.n))
+    q, _ = egt.smoothed_br(G, 0, dev(L.to_lib(0, g)), 0.1)
+    assert np.abs(L.from_lib(0, host(q)) - P.sbr(0, g, 0.1)[0]).max() <= 1e-12
+
+
+def test_argument_errors(egt):
+    _, P, G, L = setup(egt, "kuhn", 0)
+    g = G.empty(0)
+    with pytest.raises(egt.EgtError) as e:
+        egt.smoothed_br(G, 0, g, 0.0)
+    assert e.value.code == -1
+    with pytest.raises(egt.EgtError):
+        egt.smoothed_br(G, 0, g, float("nan"))
+    with pytest.raises(ValueError):
+        egt.gradient(G, 0, G.empty(1).float())  # not float64
+    with pytest.raises(ValueError):
+        egt.gradient(G, 0, G.empty(1)[:, :2].contiguous())  # wrong shape
