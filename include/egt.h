@@ -212,6 +212,21 @@ int egt_step(egt_state* state, int player, double* egv_out, int* player_stepped,
 int egt_state_get(const egt_state* state, double* x, double* y, double* mu_x, double* mu_y,
                   double* tau, int64_t* iters, hipStream_t stream);
 
+/* Checkpoint export: the cached products A y (player-1 layout) and A^T x
+ * (player-2 layout) of the current iterate (device -> device).  With
+ * egt_state_get this is the whole state of the iteration. */
+int egt_state_get_products(const egt_state* state, double* ay, double* atx, hipStream_t stream);
+
+/* Checkpoint import / restart from an arbitrary point: sets the iterates
+ * (device vectors, canonical layout, copied), mu_x, mu_y > 0, tau in (0, 1)
+ * and the iteration counter.  ay / atx (may be NULL) are the products A y and
+ * A^T x of that point; when NULL they are recomputed.  Resuming from a full
+ * export (iterates, products, scalars) continues bitwise identically to the
+ * run that was exported.  Synchronises `stream`. */
+int egt_state_set(egt_state* state, const double* x, const double* y, double mu_x, double mu_y,
+                  double tau, int64_t iters, const double* ay, const double* atx,
+                  hipStream_t stream);
+
 /* Saddle gap of the state's current iterates (host outputs; synchronises). */
 int egt_state_gap(egt_state* state, double* gap, double* br_max_y, double* br_min_x,
                   hipStream_t stream);

@@ -7,4 +7,4 @@ instance generator in ``instances/``.
 """
 from .game import Game  # noqa: F401,E402
 from .problem import Problem  # noqa: F401,E402
-from .egt import EGT, Trace, solve  # noqa: F401,E402
+from .egt import EGT, Trace, iterate, solve  # noqa: F401,E402

@@ -59,8 +59,9 @@ class Trace:
 
 
 class EGT:
-    def __init__(self, prob: Problem):
+    def __init__(self, prob: Problem, literal: bool = True):
         self.P = prob
+        self.literal = literal
 
     # the gradient each player minimises against: player 1 <x, A y>,
     # player 2 <y, -A^T x> (the mirrored problem of the y-focused step)
@@ -83,7 +84,7 @@ class EGT:
     def egv(self, x, y, mu_x, mu_y):
         return self.P.egv(x, y, mu_x, mu_y)[0]
 
-    def step(self, p, mu_p, mu_o, own, other, tau, literal=True):
+    def step(self, p, mu_p, mu_o, own, other, tau):
         """Algorithm 2 focused on player p.  Returns (mu_p+, own+, other+, prox_diff)."""
         o = 1 - p
         g1 = self.G(p, other)
@@ -96,20 +97,60 @@ class EGT:
         own_til_lit = self.P.sbr(p, shifted, 1.0)[0]
         own_til_free = self.P.sbr(p, g1 + tau / (1.0 - tau) * g3, mu_p)[0]
         diff = float(np.max(np.abs(own_til_lit - own_til_free)))
-        own_til = own_til_lit if literal else own_til_free
+        own_til = own_til_lit if self.literal else own_til_free
         own_plus = (1.0 - tau) * own + tau * own_til
         return (1.0 - tau) * mu_p, own_plus, other_plus, diff
 
 
+def iterate(E: EGT, variant: str, t: int, x, y, mu_x: float, mu_y: float, tau: float, side=None,
+            tau_floor: float = 1e-30, record_egv: bool = True):
+    """One iteration of Algorithm 1 (ALT), mu-balanced EGT (BAL) or Algorithm 3
+    with the Decr of Algorithm 4 (AS), from iterate t = (x, y, mu_x, mu_y) and
+    (for AS) the current tau.  ``side`` forces the player stepped.
+    Returns dict(x, y, mu_x, mu_y, tau, side, egv, backtracks, prox_diff)."""
+    if variant in ("ALT", "BAL"):
+        tau = 2.0 / (t + 3.0)
+    if side is None:
+        if variant == "ALT":
+            side = 0 if t % 2 == 0 else 1
+        elif variant in ("BAL", "AS"):
+            side = 0 if mu_x > mu_y else 1
+        else:
+            raise ValueError(variant)
+    bt = 0
+    diff = 0.0
+    while True:
+        if side == 0:
+            mu_new, x_new, y_new, d = E.step(0, mu_x, mu_y, x, y, tau)
+            mus_new = (mu_new, mu_y)
+        else:
+            mu_new, y_new, x_new, d = E.step(1, mu_y, mu_x, y, x, tau)
+            mus_new = (mu_x, mu_new)
+        diff = max(diff, d)
+        if variant != "AS":
+            egv = E.egv(x_new, y_new, *mus_new) if record_egv else float("nan")
+            break
+        egv = E.egv(x_new, y_new, *mus_new)
+        if not egv < 0.0:
+            break
+        tau *= 0.5
+        bt += 1
+        if tau < tau_floor:
+            raise RuntimeError("tau fell below the floor")
+    return dict(x=x_new, y=y_new, mu_x=mus_new[0], mu_y=mus_new[1], tau=tau, side=side, egv=egv,
+                backtracks=bt, prox_diff=diff)
+
+
 def solve(prob: Problem, variant: str = "AS", eps: float | None = None, max_iters: int = 10000,
           mu0=None, tau0: float = 0.5, literal: bool = True, record_egv: bool = True,
-          max_doublings: int = 200, tau_floor: float = 1e-30) -> Trace:
+          max_doublings: int = 200, tau_floor: float = 1e-30, on_iterate=None) -> Trace:
     """Run EGT (``ALT``), mu-balanced EGT (``BAL``) or EGT/as (``AS``).
 
     eps defaults to 1e-3 * pot.  mu0 = None applies the automatic rule and
     doubles both mus until the excessive gap condition holds at the start;
-    an explicit (mu_x, mu_y) is used as given."""
-    E = EGT(prob)
+    an explicit (mu_x, mu_y) is used as given.  ``on_iterate(t, x, y, mu_x,
+    mu_y, tau)`` is called with every iterate before its gap test."""
+    E = EGT(prob, literal=literal)
     if eps is None:
         eps = 1e-3 * prob.inst.pot
     if mu0 is None:
@@ -130,6 +171,8 @@ def solve(prob: Problem, variant: str = "AS", eps: float | None = None, max_iter
     tau = tau0
     t = 0
     while True:
+        if on_iterate is not None:
+            on_iterate(t, x, y, mu_x, mu_y, tau)
         gap, brmax, brmin = prob.saddle_gap(x, y)
         row = dict(t=t, mu_x=mu_x, mu_y=mu_y, gap=gap, br_max_y=brmax, br_min_x=brmin)
         if gap <= eps or t >= max_iters:
@@ -137,43 +180,15 @@ def solve(prob: Problem, variant: str = "AS", eps: float | None = None, max_iter
             tr.converged = gap <= eps
             tr.gap = gap
             break
-        if variant == "ALT":
-            tau = 2.0 / (t + 3.0)
-            side = 0 if t % 2 == 0 else 1
-        elif variant == "BAL":
-            tau = 2.0 / (t + 3.0)
-            side = 0 if mu_x > mu_y else 1
-        elif variant == "AS":
-            side = 0 if mu_x > mu_y else 1
-        else:
-            raise ValueError(variant)
-        bt = 0
-        while True:
-            mus = (mu_x, mu_y)
-            if side == 0:
-                mu_new, x_new, y_new, d = E.step(0, mu_x, mu_y, x, y, tau, literal)
-                mus_new = (mu_new, mu_y)
-            else:
-                mu_new, y_new, x_new, d = E.step(1, mu_y, mu_x, y, x, tau, literal)
-                mus_new = (mu_x, mu_new)
-            tr.max_prox_diff = max(tr.max_prox_diff, d)
-            if variant != "AS":
-                egv = E.egv(x_new, y_new, *mus_new) if record_egv else float("nan")
-                break
-            egv = E.egv(x_new, y_new, *mus_new)
-            if not egv < 0.0:
-                break
-            tau *= 0.5
-            bt += 1
-            if tau < tau_floor:
-                raise RuntimeError("tau fell below the floor")
-        del mus
-        row.update(side=side, tau=tau, egv=egv, backtracks=bt)
+        r = iterate(E, variant, t, x, y, mu_x, mu_y, tau, tau_floor=tau_floor, record_egv=record_egv)
+        tr.max_prox_diff = max(tr.max_prox_diff, r["prox_diff"])
+        row.update(side=r["side"], tau=r["tau"], egv=r["egv"], backtracks=r["backtracks"])
         tr.rows.append(row)
-        tr.backtracks += bt
-        tr.products_paper += (4 + 3 * bt) if variant == "AS" else 3
-        x, y = x_new, y_new
-        mu_x, mu_y = mus_new
+        tr.backtracks += r["backtracks"]
+        tr.products_paper += (4 + 3 * r["backtracks"]) if variant == "AS" else 3
+        x, y, mu_x, mu_y = r["x"], r["y"], r["mu_x"], r["mu_y"]
+        if variant == "AS":
+            tau = r["tau"]
         t += 1
     tr.x, tr.y, tr.iters = x, y, t
     tr.value_p2 = prob.value(x, y)

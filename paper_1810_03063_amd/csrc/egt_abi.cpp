@@ -18,6 +18,9 @@ int state_step(egt_state* st, int player, double* egv_out, int* stepped, hipStre
 int state_get(const egt_state* st, double* x, double* y, double* mu_x, double* mu_y, double* tau,
               int64_t* iters, hipStream_t s);
 int state_gap(egt_state* st, double* gap, double* brmax, double* brmin, hipStream_t s);
+int state_get_products(const egt_state* st, double* ay, double* atx, hipStream_t s);
+int state_set(egt_state* st, const double* x, const double* y, double mu_x, double mu_y, double tau, int64_t iters,
+              const double* ay, const double* atx, hipStream_t s);
 int solve(const egt_game* g, const egt_solve_opts* o, egt_result* res, egt_state** state_out, hipStream_t s);
 
 namespace {
@@ -224,6 +227,15 @@ int egt_step(egt_state* st, int player, double* egv_out, int* player_stepped, hi
 int egt_state_get(const egt_state* st, double* x, double* y, double* mu_x, double* mu_y, double* tau,
                   int64_t* iters, hipStream_t stream) {
   return guarded([&]() -> int { return state_get(st, x, y, mu_x, mu_y, tau, iters, stream); });
+}
+
+int egt_state_get_products(const egt_state* st, double* ay, double* atx, hipStream_t stream) {
+  return guarded([&]() -> int { return state_get_products(st, ay, atx, stream); });
+}
+
+int egt_state_set(egt_state* st, const double* x, const double* y, double mu_x, double mu_y, double tau,
+                  int64_t iters, const double* ay, const double* atx, hipStream_t stream) {
+  return guarded([&]() -> int { return state_set(st, x, y, mu_x, mu_y, tau, iters, ay, atx, stream); });
 }
 
 int egt_state_gap(egt_state* st, double* gap, double* br_max_y, double* br_min_x, hipStream_t stream) {

@@ -354,6 +354,44 @@ int state_get(const egt_state* st, double* x, double* y, double* mu_x, double* m
   return EGT_OK;
 }
 
+int state_get_products(const egt_state* st, double* ay, double* atx, hipStream_t s) {
+  if (!st) return fail(EGT_EINVAL, "null state");
+  const egt_game* g = st->g;
+  if (ay) EGT_HIP(hipMemcpyAsync(ay, st->G[0], sizeof(double) * vec_elems(g, 0), hipMemcpyDeviceToDevice, s));
+  if (atx) EGT_HIP(hipMemcpyAsync(atx, st->G[1], sizeof(double) * vec_elems(g, 1), hipMemcpyDeviceToDevice, s));
+  return EGT_OK;
+}
+
+int state_set(egt_state* st, const double* x, const double* y, double mu_x, double mu_y, double tau, int64_t iters,
+              const double* ay, const double* atx, hipStream_t s) {
+  if (!st || !x || !y) return fail(EGT_EINVAL, "null argument");
+  if (!(mu_x > 0) || !(mu_y > 0) || !std::isfinite(mu_x) || !std::isfinite(mu_y))
+    return fail(EGT_EINVAL, "mu must be finite and > 0");
+  if (!(tau > 0) || !(tau < 1)) return fail(EGT_EINVAL, "tau must lie in (0, 1)");
+  if (iters < 0) return fail(EGT_EINVAL, "iters < 0");
+  const egt_game* g = st->g;
+  EGT_HIP(hipMemcpyAsync(st->X[0], x, sizeof(double) * vec_elems(g, 0), hipMemcpyDeviceToDevice, s));
+  EGT_HIP(hipMemcpyAsync(st->X[1], y, sizeof(double) * vec_elems(g, 1), hipMemcpyDeviceToDevice, s));
+  int rc;
+  if (ay) {
+    EGT_HIP(hipMemcpyAsync(st->G[0], ay, sizeof(double) * vec_elems(g, 0), hipMemcpyDeviceToDevice, s));
+  } else if ((rc = grad(st, 0, st->X[1], st->G[0], s))) {
+    return rc;
+  }
+  if (atx) {
+    EGT_HIP(hipMemcpyAsync(st->G[1], atx, sizeof(double) * vec_elems(g, 1), hipMemcpyDeviceToDevice, s));
+  } else if ((rc = grad(st, 1, st->X[0], st->G[1], s))) {
+    return rc;
+  }
+  EGT_HIP(hipStreamSynchronize(s));
+  st->mu[0] = mu_x;
+  st->mu[1] = mu_y;
+  st->tau = tau;
+  st->t = iters;
+  st->gap_valid = false;
+  return EGT_OK;
+}
+
 int solve(const egt_game* g, const egt_solve_opts* o, egt_result* res, egt_state** state_out, hipStream_t s) {
   if (!g || !res) return fail(EGT_EINVAL, "null argument");
   std::memset(res, 0, sizeof(*res));

@@ -90,6 +90,8 @@ _state_destroy = _decl("egt_state_destroy", ctypes.c_int, _p)
 _step = _decl("egt_step", ctypes.c_int, _p, ctypes.c_int, ctypes.POINTER(_f64), ctypes.POINTER(ctypes.c_int), _p)
 _state_get = _decl("egt_state_get", ctypes.c_int, _p, _p, _p, ctypes.POINTER(_f64), ctypes.POINTER(_f64),
                    ctypes.POINTER(_f64), ctypes.POINTER(_i64), _p)
+_state_get_products = _decl("egt_state_get_products", ctypes.c_int, _p, _p, _p, _p)
+_state_set = _decl("egt_state_set", ctypes.c_int, _p, _p, _p, _f64, _f64, _f64, _i64, _p, _p, _p)
 _state_gap = _decl("egt_state_gap", ctypes.c_int, _p, ctypes.POINTER(_f64), ctypes.POINTER(_f64),
                    ctypes.POINTER(_f64), _p)
 _solve = _decl("egt_solve", ctypes.c_int, _p, ctypes.POINTER(SolveOpts), ctypes.POINTER(SolveResult),
@@ -99,7 +101,7 @@ EXPORTED = [
     "egt_last_error", "egt_default_opts", "egt_build_game", "egt_free_game", "egt_game_dims",
     "egt_game_layout", "egt_game_terminals", "egt_gradient", "egt_smoothed_br", "egt_best_response",
     "egt_uniform", "egt_saddle_gap", "egt_state_create", "egt_state_destroy", "egt_step",
-    "egt_state_get", "egt_state_gap", "egt_solve",
+    "egt_state_get", "egt_state_get_products", "egt_state_set", "egt_state_gap", "egt_solve",
 ]
 
 
@@ -287,6 +289,19 @@ class State:
         _check(_state_get(self._h, _dptr(x), _dptr(y), ctypes.byref(mx), ctypes.byref(my), ctypes.byref(tau),
                           ctypes.byref(it), _stream(stream)))
         return dict(x=x, y=y, mu_x=mx.value, mu_y=my.value, tau=tau.value, iters=it.value)
+
+    def products(self, stream=None):
+        """(A y, A^T x) cached for the current iterate."""
+        ay, atx = self.game.empty(0), self.game.empty(1)
+        _check(_state_get_products(self._h, _dptr(ay), _dptr(atx), _stream(stream)))
+        return ay, atx
+
+    def set(self, x, y, mu_x, mu_y, tau, iters=0, ay=None, atx=None, stream=None):
+        """Restart from (x, y, mu, tau, t); products recomputed unless given."""
+        g = self.game
+        _check(_state_set(self._h, _dptr(x, (g.n_seq[0], g.ld)), _dptr(y, (g.n_seq[1], g.ld)), float(mu_x),
+                          float(mu_y), float(tau), int(iters), _dptr(ay, (g.n_seq[0], g.ld)),
+                          _dptr(atx, (g.n_seq[1], g.ld)), _stream(stream)))
 
     def close(self):
         if self._h is not None:

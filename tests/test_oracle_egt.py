@@ -101,3 +101,20 @@ def test_paper_gradient_accounting(kuhn):
     assert tr.products_paper == 4 * tr.iters + 3 * tr.backtracks
     tr = solve(kuhn, "ALT", eps=1e-3, max_iters=500)
     assert tr.products_paper == 3 * tr.iters
+
+
+def test_oracle_rounding_sensitivity():
+    """EGT/as amplifies rounding: the literal prox (through grad d) and the
+    shift-free prox agree to rounding at every step, yet the trajectories part
+    after a few dozen iterations.  This is why GPU parity is checked one step
+    at a time from the oracle's own iterates."""
+    P = Problem(make_instance("kuhn"))
+    a = solve(P, "AS", eps=0.0, max_iters=100, literal=True)
+    b = solve(P, "AS", eps=0.0, max_iters=100, literal=False)
+
+    def d(t):
+        return abs(a.rows[t]["gap"] - b.rows[t]["gap"])
+
+    assert d(5) < 1e-13
+    assert d(100) > 1e-6
+    assert a.max_prox_diff < 1e-12 and b.max_prox_diff < 1e-12
