@@ -159,7 +159,8 @@ int egt_smoothed_br(const egt_game* g, int player, const double* grad, double mu
     EGT_HIP(launch_bottom_up(g, player, grad, 1.0, nullptr, 0.0, mu, w.v[player], strat_out ? w.qb[player] : nullptr,
                              stream));
     if (strat_out) EGT_HIP(launch_top_down(g, player, w.qb[player], strat_out, nullptr, 0.0, nullptr, stream));
-    if (value_out) EGT_HIP(launch_root_sum(g, player, w.v[player], 1.0, -1, nullptr, 0.0, w.scal, stream));
+    const Pass ps{player, grad, 1.0, nullptr, 0.0, mu, w.v[player], nullptr};
+    if (value_out) EGT_HIP(launch_root_sums(g, &ps, 1, w.scal, stream));
     if (value_out)
       EGT_HIP(hipMemcpyAsync(value_out, w.scal, sizeof(double), hipMemcpyDeviceToDevice, stream));
     return EGT_OK;
@@ -173,8 +174,9 @@ int egt_best_response(const egt_game* g, int player, const double* grad, double*
     int rc = ensure_workspace(g);
     if (rc) return rc;
     const Workspace& w = g->ws;
-    EGT_HIP(launch_bottom_up(g, player, grad, 1.0, nullptr, 0.0, 0.0, w.v[player], nullptr, stream));
-    EGT_HIP(launch_root_sum(g, player, w.v[player], 1.0, -1, nullptr, 0.0, w.scal, stream));
+    const Pass ps{player, grad, 1.0, nullptr, 0.0, 0.0, w.v[player], nullptr};
+    EGT_HIP(launch_passes(g, &ps, 1, stream));
+    EGT_HIP(launch_root_sums(g, &ps, 1, w.scal, stream));
     EGT_HIP(hipMemcpyAsync(value_out, w.scal, sizeof(double), hipMemcpyDeviceToDevice, stream));
     return EGT_OK;
   });
@@ -200,14 +202,16 @@ int egt_saddle_gap(const egt_game* g, const double* x, const double* y, double* 
     const Workspace& w = g->ws;
     EGT_HIP(launch_gradient(g, 0, y, w.grad[0], stream));
     EGT_HIP(launch_gradient(g, 1, x, w.grad[1], stream));
-    EGT_HIP(launch_bottom_up(g, 0, w.grad[0], 1.0, nullptr, 0.0, 0.0, w.v[0], nullptr, stream));
-    EGT_HIP(launch_bottom_up(g, 1, w.grad[1], -1.0, nullptr, 0.0, 0.0, w.v[1], nullptr, stream));
-    EGT_HIP(launch_root_sum(g, 0, w.v[0], -1.0, 1, w.v[1], -1.0, w.scal, stream));
-    EGT_HIP(hipMemcpyAsync(w.hscal, w.scal, 3 * sizeof(double), hipMemcpyDeviceToHost, stream));
+    const Pass ps[2] = {{0, w.grad[0], 1.0, nullptr, 0.0, 0.0, w.v[0], nullptr},
+                        {1, w.grad[1], -1.0, nullptr, 0.0, 0.0, w.v[1], nullptr}};
+    EGT_HIP(launch_passes(g, ps, 2, stream));
+    EGT_HIP(launch_root_sums(g, ps, 2, w.scal, stream));
+    EGT_HIP(hipMemcpyAsync(w.hscal, w.scal, 2 * sizeof(double), hipMemcpyDeviceToHost, stream));
     EGT_HIP(hipStreamSynchronize(stream));
-    if (gap) *gap = w.hscal[0];
-    if (br_min_x) *br_min_x = w.hscal[1];
-    if (br_max_y) *br_max_y = -w.hscal[2];
+    // gap = max_y x^T A y - min_x x^T A y = -BR_y(-A^T x) - BR_x(A y)
+    if (gap) *gap = -w.hscal[1] - w.hscal[0];
+    if (br_min_x) *br_min_x = w.hscal[0];
+    if (br_max_y) *br_max_y = -w.hscal[1];
     return EGT_OK;
   });
 }

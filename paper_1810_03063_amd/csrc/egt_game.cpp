@@ -213,6 +213,9 @@ int finish_player(const Enumerator& en, int p, HostPlayer& hp, std::vector<int>&
   }
   if (mx > kMaxDepth) return fail(EGT_EINVAL, "a player's sequence chain is deeper than 16");
   hp.max_chain = mx;
+  hp.max_level_width = 0;
+  for (int l = 0; l < hp.n_levels; ++l)
+    hp.max_level_width = std::max(hp.max_level_width, hp.level_begin[l + 1] - hp.level_begin[l]);
   return EGT_OK;
 }
 
@@ -306,8 +309,10 @@ int build_game(const egt_game_desc* d, hipStream_t stream, egt_game** out) {
         hp.term_coef.push_back(rt.coef);
       }
       hp.term_begin[s + 1] = (int)hp.term_opp.size();
+      hp.max_terms_per_seq = std::max(hp.max_terms_per_seq, (int)by[s].size());
     }
   }
+  g->fused_passes = g->hp[0].max_level_width <= kFusedNodeLimit && g->hp[1].max_level_width <= kFusedNodeLimit;
   for (const RawTerminal& t : en.terms) (t.kind == 0 ? g->n_fold : g->n_show)++;
   for (int p = 0; p < 2; ++p)
     for (double b : g->hp[p].node_beta) g->max_beta = std::max(g->max_beta, b);

@@ -13,7 +13,10 @@
 namespace egt {
 
 constexpr int kMaxActions = 16;  // actions per decision node
-constexpr int kMaxDepth = 16;    // sequences on a root-to-leaf chain of one player
+constexpr int kMaxDepth = 16;    // sequences on a root-to-leaf chain of one player (and levels)
+constexpr int kMaxTrees = 4;     // trees evaluated by one bottom-up launch
+constexpr int kFusedNodeLimit = 256;       // widest level for the single-launch bottom-up pass
+constexpr size_t kGradLdsLimit = 64 * 1024;  // LDS budget of one product block
 
 // ---------------------------------------------------------------------------
 // Error plumbing: every entry point converts failures into a status code and a
@@ -74,11 +77,48 @@ struct DHands {
   double invZ;                 // 1 / sum of b1 b2 over compatible deals
 };
 
+// One bottom-up pass over one player's treeplex on the gradient
+// cA gA + cB gB (gB may be null): smoothed (mu > 0, writing q_bar to QB when
+// QB != null) or best response (mu == 0).  Node values go to V.
+struct TreePass {
+  DPlayer P;
+  const double* gA;
+  double cA;
+  const double* gB;
+  double cB;
+  double mu;
+  double* V;
+  double* QB;
+  int n_levels;
+  int level_begin[kMaxDepth + 1];
+};
+
+// Up to kMaxTrees independent passes evaluated by the same launches.
+struct PassSet {
+  TreePass t[kMaxTrees];
+  int count;
+  int n, ld;
+  int level;                  // per-level kernel: the level of this launch
+  int level_cnt[kMaxTrees];   // per-level kernel: nodes of each tree at `level`
+};
+
+// Host description of one pass (player instead of device tables).
+struct Pass {
+  int player;
+  const double* gA;
+  double cA;
+  const double* gB;
+  double cB;
+  double mu;
+  double* V;
+  double* QB;
+};
+
 // ---------------------------------------------------------------------------
 // Host-side tables kept with a game.
 // ---------------------------------------------------------------------------
 struct HostPlayer {
-  int n_seq = 0, n_nodes = 0, n_levels = 0, max_chain = 0;
+  int n_seq = 0, n_nodes = 0, n_levels = 0, max_chain = 0, max_terms_per_seq = 0, max_level_width = 0;
   std::vector<int> node_first_seq, node_nact, node_level;
   std::vector<double> node_beta, node_logn;
   std::vector<int> level_begin;  // [n_levels + 1]
@@ -121,6 +161,7 @@ struct egt_game {
   egt::Workspace ws;
   int device = 0;
   double max_beta = 0;
+  bool fused_passes = false;  // every level of both trees fits one block's node slots
 };
 
 namespace egt {
@@ -140,6 +181,13 @@ hipError_t launch_bottom_up(const egt_game* g, int player, const double* gA, dou
                             const double* gB, double cB, double mu, double* V, double* QB,
                             hipStream_t s);
 
+// count (1..kMaxTrees) independent bottom-up passes in the same launches.
+hipError_t launch_passes(const egt_game* g, const Pass* p, int count, hipStream_t s);
+
+// out[k] = value of pass k's tree (sum of its root values over hands), after
+// launch_passes with the same passes.
+hipError_t launch_root_sums(const egt_game* g, const Pass* p, int count, double* out, hipStream_t s);
+
 // Top-down pass: q = product of q_bar along the sequence's chain.  Writes q to
 // q_out (may be null) and (1 - tau) x_prev + tau q to comb_out (may be null).
 hipError_t launch_top_down(const egt_game* g, int player, const double* QB, double* q_out,
@@ -147,11 +195,6 @@ hipError_t launch_top_down(const egt_game* g, int player, const double* QB, doub
 
 // QB = 1 / (number of actions) everywhere (the uniform point's q_bar).
 hipError_t launch_uniform_qbar(const egt_game* g, int player, double* QB, hipStream_t s);
-
-// out[0] = cA * sum(roots of A) + cB * sum(roots of B); out[1], out[2] = the two
-// sums.  playerB < 0 disables B.
-hipError_t launch_root_sum(const egt_game* g, int playerA, const double* VA, double cA,
-                           int playerB, const double* VB, double cB, double* out, hipStream_t s);
 
 // out = a * X + b * Y over rows x ld doubles (Y may be null).
 hipError_t launch_axpby(int64_t count, double a, const double* X, double b, const double* Y,

@@ -22,10 +22,12 @@ namespace egt {
 
 namespace {
 
-constexpr int kGradThreads = 256;
-constexpr int kGradWaves = kGradThreads / 64;
-constexpr int kMaxHandsPerThread = 8;  // n <= 2048
-constexpr int kPassThreads = 64;       // one wavefront per (node or sequence, 64 hands)
+constexpr int kGroupThreads = 256;     // one wave group evaluates one terminal
+constexpr int kMaxHandsPerThread = 8;  // n <= 2048 = 256 threads x 8 contiguous hands
+constexpr int kPassThreads = 64;       // per-level pass: one wavefront per (node, 64 hands)
+constexpr int kFusedHands = 16;        // fused pass: hands per block
+constexpr int kFusedThreads = 1024;    // fused pass: 64 node slots x 16 hands
+constexpr int kFusedSlots = kFusedThreads / kFusedHands;
 
 __device__ inline double wave_inclusive_scan(double x, int lane) {
 #pragma unroll
@@ -37,18 +39,23 @@ __device__ inline double wave_inclusive_scan(double x, int lane) {
 }
 
 // ---------------------------------------------------------------------------
-// Payoff product.  One block per output sequence s of `own`.  For every
-// terminal z ending at s (at most a handful), the opponent's reach
-// r(h') = b_o(h') v_o[sigma_o(z)][h'] is staged in LDS; then
+// Payoff product.  One block per output sequence s of `own`; the block holds
+// `groups` wave groups of 256 threads and group g evaluates the terminals
+// tb + g, tb + g + groups, ... of s concurrently with the others.  For a
+// terminal z the opponent's reach r(h') = b_o(h') v_o[sigma_o(z)][h'] is
+// staged in LDS, each thread keeping its contiguous chunk of hands in
+// registers; then
 //   fold:     sum of r over compatible h' = T - C[a] - C[b] + r(h)
 //             (T total, C[c] the mass of hands holding card c; the hand's own
 //             slot holds both of its cards and is added back once);
 //   showdown: (compatible mass stronger) - (compatible mass weaker), from the
-//             exclusive prefix sums over strength order and, per card, over
-//             the strength-ordered hands holding that card; ties
-//             [glo, ghi) count as neither.
-// out[s][h] = b_own(h) / Z * sum_z coef(z) * op_z(h), with the showdown op
-// negated for player 2 (its gradient sums over player 1's hands).
+//             exclusive prefix sum over strength order (built in place over r)
+//             and, per card, over the strength-ordered hands holding that card
+//             (one thread walks one card's list); a tie group [glo, ghi)
+//             counts as neither.
+// out[s][h] = b_own(h) / Z * sum_z coef(z) * op_z(h), the showdown op negated
+// for player 2 (its gradient sums over player 1's hands).  Group partial sums
+// are combined in a fixed order, so the result is bitwise repeatable.
 // ---------------------------------------------------------------------------
 struct GradArgs {
   DPlayer own;
@@ -57,21 +64,27 @@ struct GradArgs {
   const double* v_opp;
   double* out;
   double show_sign;
+  int groups;
 };
 
-__global__ __launch_bounds__(kGradThreads) void gradient_kernel(GradArgs a) {
+__global__ __launch_bounds__(2 * kGroupThreads) void gradient_kernel(GradArgs a) {
   extern __shared__ double lds[];
+  __shared__ double wave_total[2][kGroupThreads / 64];
   const int n = a.H.n, ld = a.H.ld;
-  double* r = lds;                    // [ld]
-  double* G = r + ld;                 // [ld + 1]
-  double* Pc = G + ld + 1;            // [n_card_slots]
-  int* cbeg = (int*)(Pc + a.H.n_card_slots);  // [n_cards + 1]
-  int* chand = cbeg + a.H.n_cards + 1;        // [card entries]
-  __shared__ double wave_total[kGradWaves];
+  const int groups = a.groups;
+  const int per_group = (n + 1) + a.H.n_card_slots;
+  const int tid = threadIdx.x;
+  const int grp = tid / kGroupThreads, gt = tid % kGroupThreads;
+  const int lane = tid & 63, wig = gt >> 6;
+  double* R = lds + (size_t)grp * per_group;  // r, then its exclusive prefix in place [n + 1]
+  double* Pc = R + (n + 1);                   // per-card exclusive prefixes [n_card_slots]
+  int* cbeg = (int*)(lds + (size_t)groups * per_group);
+  int* chand = cbeg + a.H.n_cards + 1;
 
   const int s = blockIdx.x;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int tb = a.own.term_begin[s], te = a.own.term_begin[s + 1];
+  const int chunk = (n + kGroupThreads - 1) / kGroupThreads;
+  const int beg = min(gt * chunk, n), end = min(beg + chunk, n), cnt = end - beg;
 
   double acc[kMaxHandsPerThread];
 #pragma unroll
@@ -79,141 +92,146 @@ __global__ __launch_bounds__(kGradThreads) void gradient_kernel(GradArgs a) {
 
   if (te > tb) {
     const int n_entries = a.H.card_begin[a.H.n_cards];
-    for (int i = tid; i <= a.H.n_cards; i += kGradThreads) cbeg[i] = a.H.card_begin[i];
-    for (int i = tid; i < n_entries; i += kGradThreads) chand[i] = a.H.card_hands[i];
+    for (int i = tid; i <= a.H.n_cards; i += blockDim.x) cbeg[i] = a.H.card_begin[i];
+    for (int i = tid; i < n_entries; i += blockDim.x) chand[i] = a.H.card_hands[i];
   }
-  const int chunk = (n + kGradThreads - 1) / kGradThreads;
-
-  for (int t = tb; t < te; ++t) {
-    const int opp = a.own.term_opp[t];
-    const int kind = a.own.term_kind[t];
-    const double coef = a.own.term_coef[t];
-    const double* v = opp >= 0 ? a.v_opp + (size_t)opp * ld : nullptr;
-    for (int i = tid; i < n; i += kGradThreads) r[i] = a.b_opp[i] * (v ? v[i] : 1.0);
-    __syncthreads();
-
-    // block-wide exclusive scan of r over strength order into G[0..n]
-    {
-      const int beg = min(tid * chunk, n), end = min(beg + chunk, n);
-      double local = 0.0;
-      for (int j = beg; j < end; ++j) local += r[j];
-      const double incl = wave_inclusive_scan(local, lane);
-      if (lane == 63) wave_total[wave] = incl;
-      __syncthreads();
-      double run = incl - local;
-      for (int w = 0; w < wave; ++w) run += wave_total[w];
-      for (int j = beg; j < end; ++j) {
-        G[j] = run;
-        run += r[j];
-      }
-      if (beg < end && end == n) G[n] = run;
-      if (n == 0 && tid == 0) G[0] = 0.0;
-    }
-    // per-card exclusive scans: one wavefront per card
-    for (int c = wave; c < a.H.n_cards; c += kGradWaves) {
-      const int cb = cbeg[c], len = cbeg[c + 1] - cb, base = cb + c;
-      double carry = 0.0;
-      for (int k0 = 0; k0 < len; k0 += 64) {
-        const int k = k0 + lane;
-        const double val = k < len ? r[chand[cb + k]] : 0.0;
-        const double incl = wave_inclusive_scan(val, lane);
-        if (k < len) Pc[base + k] = carry + (incl - val);
-        carry += __shfl(incl, 63, 64);
-      }
-      if (lane == 0) Pc[base + len] = carry;
+  const int rounds = (te - tb + groups - 1) / groups;
+  for (int rd = 0; rd < rounds; ++rd) {
+    const int t = tb + rd * groups + grp;
+    const bool active = t < te;  // uniform within a group
+    int kind = 0;
+    double coef = 0.0;
+    if (active) {
+      const int opp = a.own.term_opp[t];
+      kind = a.own.term_kind[t];
+      coef = a.own.term_coef[t];
+      const double* v = opp >= 0 ? a.v_opp + (size_t)opp * ld : nullptr;
+      for (int i = gt; i < n; i += kGroupThreads) R[i] = a.b_opp[i] * (v ? v[i] : 1.0);
     }
     __syncthreads();
-
-    const double T = G[n];
+    double rloc[kMaxHandsPerThread];
+    if (active) {
 #pragma unroll
-    for (int k = 0; k < kMaxHandsPerThread; ++k) {
-      const int i = tid + k * kGradThreads;
-      if (i < n) {
-        const int4 A = a.H.ha[i];
-        double op;
-        if (kind == 0) {
-          op = T - Pc[A.x + A.w];
-          if (a.H.cph == 2) {
-            const int4 B = a.H.hb[i];
-            op = op - Pc[B.x + B.w] + r[i];
-          }
-        } else {
-          const int2 tg = a.H.tie[i];
-          double weaker = G[tg.x] - Pc[A.x + A.y];
-          double stronger = (T - G[tg.y]) - (Pc[A.x + A.w] - Pc[A.x + A.z]);
-          if (a.H.cph == 2) {
-            const int4 B = a.H.hb[i];
-            weaker -= Pc[B.x + B.y];
-            stronger -= Pc[B.x + B.w] - Pc[B.x + B.z];
-          }
-          op = a.show_sign * (stronger - weaker);
+      for (int k = 0; k < kMaxHandsPerThread; ++k) rloc[k] = k < cnt ? R[beg + k] : 0.0;
+      for (int c = gt; c < a.H.n_cards; c += kGroupThreads) {
+        const int cb = cbeg[c], len = cbeg[c + 1] - cb, base = cb + c;
+        double run = 0.0;
+        for (int k = 0; k < len; ++k) {
+          Pc[base + k] = run;
+          run += R[chand[cb + k]];
         }
-        acc[k] += coef * op;
+        Pc[base + len] = run;
       }
     }
-    __syncthreads();  // r, G and Pc are rewritten by the next terminal
-  }
-
-  double* row = a.out + (size_t)s * ld;
+    __syncthreads();  // the card walks have finished reading r
+    double local = 0.0, incl = 0.0;
+    if (active) {
 #pragma unroll
-  for (int k = 0; k < kMaxHandsPerThread; ++k) {
-    const int i = tid + k * kGradThreads;
-    if (i < ld) row[i] = i < n ? acc[k] * (a.own.belief[i] * a.H.invZ) : 0.0;
+      for (int k = 0; k < kMaxHandsPerThread; ++k) local += rloc[k];
+      incl = wave_inclusive_scan(local, lane);
+      if (lane == 63) wave_total[grp][wig] = incl;
+    }
+    __syncthreads();
+    if (active) {
+      double run = incl - local;
+      for (int w = 0; w < wig; ++w) run += wave_total[grp][w];
+#pragma unroll
+      for (int k = 0; k < kMaxHandsPerThread; ++k) {
+        if (k < cnt) {
+          R[beg + k] = run;
+          run += rloc[k];
+        }
+      }
+      if (cnt > 0 && end == n) R[n] = run;
+    }
+    __syncthreads();
+    if (active) {
+      const double T = R[n];
+#pragma unroll
+      for (int k = 0; k < kMaxHandsPerThread; ++k) {
+        if (k < cnt) {
+          const int i = beg + k;
+          const int4 A = a.H.ha[i];
+          double op;
+          if (kind == 0) {
+            op = T - Pc[A.x + A.w];
+            if (a.H.cph == 2) {
+              const int4 B = a.H.hb[i];
+              op = op - Pc[B.x + B.w] + rloc[k];
+            }
+          } else {
+            const int2 tg = a.H.tie[i];
+            double weaker = R[tg.x] - Pc[A.x + A.y];
+            double stronger = (T - R[tg.y]) - (Pc[A.x + A.w] - Pc[A.x + A.z]);
+            if (a.H.cph == 2) {
+              const int4 B = a.H.hb[i];
+              weaker -= Pc[B.x + B.y];
+              stronger -= Pc[B.x + B.w] - Pc[B.x + B.z];
+            }
+            op = a.show_sign * (stronger - weaker);
+          }
+          acc[k] += coef * op;
+        }
+      }
+    }
+    __syncthreads();  // the next round rewrites R and Pc
+  }
+  if (groups == 2) {
+    if (grp == 1) {
+#pragma unroll
+      for (int k = 0; k < kMaxHandsPerThread; ++k)
+        if (k < cnt) R[beg + k] = acc[k];
+    }
+    __syncthreads();
+    if (grp == 0) {
+      const double* R1 = lds + per_group;
+#pragma unroll
+      for (int k = 0; k < kMaxHandsPerThread; ++k)
+        if (k < cnt) acc[k] += R1[beg + k];
+    }
+  }
+  if (grp == 0) {
+    double* row = a.out + (size_t)s * ld;
+#pragma unroll
+    for (int k = 0; k < kMaxHandsPerThread; ++k)
+      if (k < cnt) row[beg + k] = acc[k] * (a.own.belief[beg + k] * a.H.invZ);
+    for (int i = n + gt; i < ld; i += kGroupThreads) row[i] = 0.0;
   }
 }
 
 // ---------------------------------------------------------------------------
-// Bottom-up pass over one level.  Block (hand block, node): each lane is one
-// information set (node v, hand h) and loops over the node's actions:
+// Bottom-up passes.  One information set (node v, hand h) of a tree:
 //   g~_a = cA gA[v,a] + cB gB[v,a] + sum_{k in D(v,a)} V[k]
-//   smoothed (temp = mu beta_v):
+//   smoothed (mu > 0, temp = mu beta_v):
 //     m = min_a g~_a,  w_a = exp(-(g~_a - m) / temp),  S = sum_a w_a
 //     V[v] = m - temp log S + temp log n_v,  q_bar_a = w_a / S
-//   best response: V[v] = min_a g~_a.
+//   best response (mu = 0): V[v] = min_a g~_a.
 // The action with the smallest g~ has the largest q_bar (weight exactly 1), so
 // V is the value g~_i + temp log q_bar_i + temp log n_v at that action, and
 // every exponent is <= 0.
 // ---------------------------------------------------------------------------
-struct UpArgs {
-  DPlayer P;
-  int n, ld;
-  const double* gA;
-  double cA;
-  const double* gB;
-  double cB;
-  double mu;
-  double* V;
-  double* QB;
-  int node_begin;
-};
-
-template <bool kBR>
-__global__ __launch_bounds__(kPassThreads) void bottom_up_kernel(UpArgs a) {
-  const int h = blockIdx.x * kPassThreads + threadIdx.x;
-  const int v = a.node_begin + blockIdx.y;
-  if (h >= a.n) return;
-  const int s0 = a.P.node_first_seq[v];
-  const int na = a.P.node_nact[v];
-  const size_t ld = a.ld;
+__device__ __forceinline__ void node_pass(const TreePass& t, int v, int h, size_t ld) {
+  const int s0 = t.P.node_first_seq[v];
+  const int na = t.P.node_nact[v];
   double gt[kMaxActions];
   double m = INFINITY;
 #pragma unroll
   for (int k = 0; k < kMaxActions; ++k) {
     if (k < na) {
       const int s = s0 + k;
-      double x = a.cA * a.gA[(size_t)s * ld + h];
-      if (a.gB) x += a.cB * a.gB[(size_t)s * ld + h];
-      const int c1 = a.P.child_begin[s + 1];
-      for (int c = a.P.child_begin[s]; c < c1; ++c) x += a.V[(size_t)a.P.child[c] * ld + h];
+      double x = t.cA * t.gA[(size_t)s * ld + h];
+      if (t.gB) x += t.cB * t.gB[(size_t)s * ld + h];
+      const int c1 = t.P.child_begin[s + 1];
+      for (int c = t.P.child_begin[s]; c < c1; ++c) x += t.V[(size_t)t.P.child[c] * ld + h];
       gt[k] = x;
       m = fmin(m, x);
     }
   }
-  if (kBR) {
-    a.V[(size_t)v * ld + h] = m;
+  if (!(t.mu > 0.0)) {
+    t.V[(size_t)v * ld + h] = m;
     return;
   }
-  const double temp = a.mu * a.P.node_beta[v];
+  const double temp = t.mu * t.P.node_beta[v];
   double sum = 0.0;
 #pragma unroll
   for (int k = 0; k < kMaxActions; ++k) {
@@ -222,12 +240,60 @@ __global__ __launch_bounds__(kPassThreads) void bottom_up_kernel(UpArgs a) {
       sum += gt[k];
     }
   }
-  a.V[(size_t)v * ld + h] = (m - temp * log(sum)) + temp * a.P.node_logn[v];
-  if (a.QB) {
+  t.V[(size_t)v * ld + h] = (m - temp * log(sum)) + temp * t.P.node_logn[v];
+  if (t.QB) {
 #pragma unroll
     for (int k = 0; k < kMaxActions; ++k)
-      if (k < na) a.QB[(size_t)(s0 + k) * ld + h] = gt[k] / sum;
+      if (k < na) t.QB[(size_t)(s0 + k) * ld + h] = gt[k] / sum;
   }
+}
+
+// Small trees: one launch covers every level.  Block = 16 hands x 64 node
+// slots of one tree; a level's nodes are spread over the slots and a block
+// barrier separates the levels (a node only needs its children's values, all
+// computed by this block for these hands).
+__global__ __launch_bounds__(kFusedThreads) void bottom_up_fused_kernel(PassSet a) {
+  const TreePass& t = a.t[blockIdx.y];
+  const int hl = threadIdx.x % kFusedHands, slot = threadIdx.x / kFusedHands;
+  const int h = blockIdx.x * kFusedHands + hl;
+  for (int l = 0; l < t.n_levels; ++l) {
+    if (h < a.n)
+      for (int v = t.level_begin[l] + slot; v < t.level_begin[l + 1]; v += kFusedSlots) node_pass(t, v, h, a.ld);
+    __syncthreads();
+  }
+}
+
+// Large trees: one launch per level over all trees of the set; block = one
+// wavefront for (node, 64 hands).
+__global__ __launch_bounds__(kPassThreads) void bottom_up_level_kernel(PassSet a) {
+  int y = blockIdx.y, k = 0;
+  while (k < a.count - 1 && y >= a.level_cnt[k]) {
+    y -= a.level_cnt[k];
+    ++k;
+  }
+  const TreePass& t = a.t[k];
+  const int h = blockIdx.x * kPassThreads + threadIdx.x;
+  if (h >= a.n) return;
+  node_pass(t, t.level_begin[a.level] + y, h, a.ld);
+}
+
+// Root sums: a treeplex is a Cartesian product over (root node, hand), so its
+// value is the sum of the root simplexes' values.  Block k sums tree k in a
+// fixed order.
+__global__ __launch_bounds__(256) void root_sums_kernel(PassSet a, double* out) {
+  __shared__ double part[4];
+  const TreePass& t = a.t[blockIdx.x];
+  const int total = t.P.n_roots * a.n;
+  double s = 0.0;
+  for (int i = threadIdx.x; i < total; i += 256) {
+    const int r = i / a.n, h = i - r * a.n;
+    s += t.V[(size_t)t.P.roots[r] * a.ld + h];
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
+  if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) out[blockIdx.x] = ((part[0] + part[1]) + part[2]) + part[3];
 }
 
 // ---------------------------------------------------------------------------
@@ -283,54 +349,7 @@ __global__ __launch_bounds__(kPassThreads) void uniform_qbar_kernel(UniformArgs 
   for (int k = 0; k < na; ++k) a.QB[(size_t)(s0 + k) * a.ld + h] = val;
 }
 
-// ---------------------------------------------------------------------------
-// Root sums: a treeplex is a Cartesian product over (root node, hand), so its
-// value is the sum of the root simplexes' values.  One block, fixed order.
-// ---------------------------------------------------------------------------
 constexpr int kRedThreads = 1024;
-
-__device__ double block_sum(double x, double* scratch) {
-  const int tid = threadIdx.x;
-  scratch[tid] = x;
-  __syncthreads();
-  for (int w = kRedThreads / 2; w > 0; w >>= 1) {
-    if (tid < w) scratch[tid] += scratch[tid + w];
-    __syncthreads();
-  }
-  const double r = scratch[0];
-  __syncthreads();
-  return r;
-}
-
-struct RootSumArgs {
-  const double* VA;
-  const int* rootsA;
-  int nA;
-  double cA;
-  const double* VB;
-  const int* rootsB;
-  int nB;
-  double cB;
-  int n, ld;
-  double* out;
-};
-
-__global__ __launch_bounds__(kRedThreads) void root_sum_kernel(RootSumArgs a) {
-  __shared__ double scratch[kRedThreads];
-  double sA = 0.0, sB = 0.0;
-  const int tot_a = a.nA * a.n, tot_b = a.nB * a.n;
-  for (int i = threadIdx.x; i < tot_a; i += kRedThreads)
-    sA += a.VA[(size_t)a.rootsA[i / a.n] * a.ld + (i % a.n)];
-  for (int i = threadIdx.x; i < tot_b; i += kRedThreads)
-    sB += a.VB[(size_t)a.rootsB[i / a.n] * a.ld + (i % a.n)];
-  sA = block_sum(sA, scratch);
-  sB = block_sum(sB, scratch);
-  if (threadIdx.x == 0) {
-    a.out[0] = a.cA * sA + a.cB * sB;
-    a.out[1] = sA;
-    a.out[2] = sB;
-  }
-}
 
 __global__ __launch_bounds__(kRedThreads) void max_abs_kernel(int64_t count, const double* X,
                                                                 double* out) {
@@ -369,40 +388,83 @@ hipError_t launch_gradient(const egt_game* g, int player, const double* v_opp, d
   a.out = grad_out;
   a.show_sign = player == 0 ? 1.0 : -1.0;
   const int n_entries = g->dh.n_card_slots - g->dh.n_cards;  // hands x cards per hand
-  const size_t lds = sizeof(double) * (size_t)(2 * g->ld + 1 + g->dh.n_card_slots) +
-                     sizeof(int) * (size_t)(g->dh.n_cards + 1 + n_entries);
-  hipLaunchKernelGGL(gradient_kernel, dim3(g->dp[player].n_seq), dim3(kGradThreads), lds, s, a);
+  const size_t per_group = sizeof(double) * (size_t)(g->n + 1 + g->dh.n_card_slots);
+  const size_t shared_ints = sizeof(int) * (size_t)(g->dh.n_cards + 1 + n_entries);
+  int groups = g->hp[player].max_terms_per_seq >= 2 ? 2 : 1;
+  if (groups == 2 && 2 * per_group + shared_ints > kGradLdsLimit) groups = 1;
+  a.groups = groups;
+  const size_t lds = groups * per_group + shared_ints;
+  hipLaunchKernelGGL(gradient_kernel, dim3(g->dp[player].n_seq), dim3(kGroupThreads * groups), lds, s, a);
+  return hipGetLastError();
+}
+
+static void fill_pass_set(const egt_game* g, const Pass* p, int count, PassSet& a) {
+  a.count = count;
+  a.n = g->n;
+  a.ld = g->ld;
+  a.level = 0;
+  for (int k = 0; k < kMaxTrees; ++k) {
+    a.level_cnt[k] = 0;
+    TreePass& t = a.t[k];
+    if (k >= count) {
+      t = a.t[0];
+      continue;
+    }
+    const HostPlayer& hp = g->hp[p[k].player];
+    t.P = g->dp[p[k].player];
+    t.gA = p[k].gA;
+    t.cA = p[k].cA;
+    t.gB = p[k].gB;
+    t.cB = p[k].cB;
+    t.mu = p[k].mu;
+    t.V = p[k].V;
+    t.QB = p[k].QB;
+    t.n_levels = hp.n_levels;
+    for (int l = 0; l <= kMaxDepth; ++l) t.level_begin[l] = hp.level_begin[std::min(l, hp.n_levels)];
+  }
+}
+
+hipError_t launch_passes(const egt_game* g, const Pass* p, int count, hipStream_t s) {
+  if (count < 1 || count > kMaxTrees) return hipErrorInvalidValue;
+  PassSet a;
+  fill_pass_set(g, p, count, a);
+  if (g->fused_passes) {
+    const unsigned bx = (unsigned)((g->n + kFusedHands - 1) / kFusedHands);
+    hipLaunchKernelGGL(bottom_up_fused_kernel, dim3(bx, count), dim3(kFusedThreads), 0, s, a);
+    return hipGetLastError();
+  }
+  int max_levels = 0;
+  for (int k = 0; k < count; ++k) max_levels = std::max(max_levels, a.t[k].n_levels);
+  const unsigned bx = (unsigned)((g->n + kPassThreads - 1) / kPassThreads);
+  for (int l = 0; l < max_levels; ++l) {
+    unsigned total = 0;
+    for (int k = 0; k < count; ++k) {
+      const TreePass& t = a.t[k];
+      a.level_cnt[k] = l < t.n_levels ? t.level_begin[l + 1] - t.level_begin[l] : 0;
+      total += (unsigned)a.level_cnt[k];
+    }
+    if (total == 0) continue;
+    a.level = l;
+    hipLaunchKernelGGL(bottom_up_level_kernel, dim3(bx, total), dim3(kPassThreads), 0, s, a);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+hipError_t launch_root_sums(const egt_game* g, const Pass* p, int count, double* out, hipStream_t s) {
+  if (count < 1 || count > kMaxTrees) return hipErrorInvalidValue;
+  PassSet a;
+  fill_pass_set(g, p, count, a);
+  hipLaunchKernelGGL(root_sums_kernel, dim3(count), dim3(256), 0, s, a, out);
   return hipGetLastError();
 }
 
 hipError_t launch_bottom_up(const egt_game* g, int player, const double* gA, double cA,
                             const double* gB, double cB, double mu, double* V, double* QB,
                             hipStream_t s) {
-  const HostPlayer& hp = g->hp[player];
-  UpArgs a;
-  a.P = g->dp[player];
-  a.n = g->n;
-  a.ld = g->ld;
-  a.gA = gA;
-  a.cA = cA;
-  a.gB = gB;
-  a.cB = cB;
-  a.mu = mu;
-  a.V = V;
-  a.QB = QB;
-  const unsigned bx = (unsigned)((g->n + kPassThreads - 1) / kPassThreads);
-  for (int l = 0; l < hp.n_levels; ++l) {
-    const int nb = hp.level_begin[l], ne = hp.level_begin[l + 1];
-    if (ne <= nb) continue;
-    a.node_begin = nb;
-    if (mu > 0.0)
-      hipLaunchKernelGGL(bottom_up_kernel<false>, dim3(bx, ne - nb), dim3(kPassThreads), 0, s, a);
-    else
-      hipLaunchKernelGGL(bottom_up_kernel<true>, dim3(bx, ne - nb), dim3(kPassThreads), 0, s, a);
-    const hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-  }
-  return hipSuccess;
+  const Pass p{player, gA, cA, gB, cB, mu, V, QB};
+  return launch_passes(g, &p, 1, s);
 }
 
 hipError_t launch_top_down(const egt_game* g, int player, const double* QB, double* q_out,
@@ -430,24 +492,6 @@ hipError_t launch_uniform_qbar(const egt_game* g, int player, double* QB, hipStr
   a.QB = QB;
   const unsigned bx = (unsigned)((g->ld + kPassThreads - 1) / kPassThreads);
   hipLaunchKernelGGL(uniform_qbar_kernel, dim3(bx, g->dp[player].n_nodes), dim3(kPassThreads), 0, s, a);
-  return hipGetLastError();
-}
-
-hipError_t launch_root_sum(const egt_game* g, int playerA, const double* VA, double cA, int playerB,
-                           const double* VB, double cB, double* out, hipStream_t s) {
-  RootSumArgs a;
-  a.VA = VA;
-  a.rootsA = g->dp[playerA].roots;
-  a.nA = g->dp[playerA].n_roots;
-  a.cA = cA;
-  a.VB = playerB >= 0 ? VB : VA;
-  a.rootsB = playerB >= 0 ? g->dp[playerB].roots : a.rootsA;
-  a.nB = playerB >= 0 ? g->dp[playerB].n_roots : 0;
-  a.cB = playerB >= 0 ? cB : 0.0;
-  a.n = g->n;
-  a.ld = g->ld;
-  a.out = out;
-  hipLaunchKernelGGL(root_sum_kernel, dim3(1), dim3(kRedThreads), 0, s, a);
   return hipGetLastError();
 }
 

@@ -47,6 +47,7 @@ struct egt_state {
   double* T2[2] = {};
   double* QB[2] = {};
   double* V[2] = {};
+  double* Vb[2] = {};       // node values of the best-response passes
   double* dscal = nullptr;  // device scalars
   double* hscal = nullptr;  // pinned host mirror
   void* block = nullptr;
@@ -95,26 +96,24 @@ int fetch(egt_state* st, int count, hipStream_t s) {
   return EGT_OK;
 }
 
-// EGV at (X, Y) with the state's G and mu -> dscal[0..2].
+// EGV at (X, Y) with the state's G and mu -> dscal[0] + dscal[1].
 int egv_current(egt_state* st, hipStream_t s) {
   const egt_game* g = st->g;
-  EGT_TRY(launch_bottom_up(g, 0, st->G[0], kSg[0], nullptr, 0.0, st->mu[0], st->V[0], nullptr, s));
-  EGT_TRY(launch_bottom_up(g, 1, st->G[1], kSg[1], nullptr, 0.0, st->mu[1], st->V[1], nullptr, s));
-  EGT_TRY(launch_root_sum(g, 0, st->V[0], 1.0, 1, st->V[1], 1.0, st->dscal, s));
+  const Pass ps[2] = {{0, st->G[0], kSg[0], nullptr, 0.0, st->mu[0], st->V[0], nullptr},
+                      {1, st->G[1], kSg[1], nullptr, 0.0, st->mu[1], st->V[1], nullptr}};
+  EGT_TRY(launch_passes(g, ps, 2, s));
+  EGT_TRY(launch_root_sums(g, ps, 2, st->dscal, s));
   return EGT_OK;
 }
 
-// Saddle gap of the point whose gradients are A y = cXA gXA + cXB gXB and
-// A^T x = cYA gYA + cYB gYB (gXB / gYB may be null) -> out[0..2] =
-// (gap, BR_x value, BR_y value).
-int gap_of(egt_state* st, const double* gXA, double cXA, const double* gXB, double cXB, const double* gYA,
-           double cYA, const double* gYB, double cYB, double* out, hipStream_t s) {
-  const egt_game* g = st->g;
-  EGT_TRY(launch_bottom_up(g, 0, gXA, kSg[0] * cXA, gXB, kSg[0] * cXB, 0.0, st->V[0], nullptr, s));
-  EGT_TRY(launch_bottom_up(g, 1, gYA, kSg[1] * cYA, gYB, kSg[1] * cYB, 0.0, st->V[1], nullptr, s));
-  // gap = max_y x^T A y - min_x x^T A y = -BR_y(-A^T x) - BR_x(A y)
-  EGT_TRY(launch_root_sum(g, 0, st->V[0], -1.0, 1, st->V[1], -1.0, out, s));
-  return EGT_OK;
+// The two best-response passes of the saddle gap at the point whose products
+// are A y = cXA gXA + cXB gXB and A^T x = cYA gYA + cYB gYB (gXB / gYB may be
+// null): tree values BR_x(A y) and BR_y(-A^T x), so that
+// gap = -BR_y - BR_x = max_y x^T A y - min_x x^T A y.
+void gap_passes(egt_state* st, const double* gXA, double cXA, const double* gXB, double cXB, const double* gYA,
+                double cYA, const double* gYB, double cYB, Pass out[2]) {
+  out[0] = Pass{0, gXA, kSg[0] * cXA, gXB, kSg[0] * cXB, 0.0, st->Vb[0], nullptr};
+  out[1] = Pass{1, gYA, kSg[1] * cYA, gYB, kSg[1] * cYB, 0.0, st->Vb[1], nullptr};
 }
 
 int init_point(egt_state* st, const double* atx_omega, hipStream_t s) {
@@ -158,7 +157,7 @@ int state_create(const egt_game* g, const egt_solve_opts* o, hipStream_t s, egt_
   st->tau = opts.tau0;
   size_t bytes = 0;
   for (int p = 0; p < 2; ++p)
-    bytes += sizeof(double) * (9 * (size_t)vec_elems(g, p) + (size_t)g->hp[p].n_nodes * g->ld);
+    bytes += sizeof(double) * (8 * (size_t)vec_elems(g, p) + 2 * (size_t)g->hp[p].n_nodes * g->ld);
   bytes += 64 * sizeof(double);
   hipError_t e = hipMalloc(&st->block, bytes);
   if (e != hipSuccess) return fail(EGT_ENOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
@@ -181,6 +180,7 @@ int state_create(const egt_game* g, const egt_solve_opts* o, hipStream_t s, egt_
     st->T2[p] = take(n);
     st->QB[p] = take(n);
     st->V[p] = take((int64_t)g->hp[p].n_nodes * g->ld);
+    st->Vb[p] = take((int64_t)g->hp[p].n_nodes * g->ld);
   }
   st->dscal = take(64);
   EGT_HIP(hipMemsetAsync(st->block, 0, bytes, s));
@@ -205,8 +205,8 @@ int state_create(const egt_game* g, const egt_solve_opts* o, hipStream_t s, egt_
     for (int k = 0;; ++k) {
       if ((rc = init_point(st, st->T2[1], s))) return rc;
       if ((rc = egv_current(st, s))) return rc;
-      if ((rc = fetch(st, 1, s))) return rc;
-      if (!(st->hscal[0] < 0.0)) break;
+      if ((rc = fetch(st, 2, s))) return rc;
+      if (!(st->hscal[0] + st->hscal[1] < 0.0)) break;
       if (k >= kMaxDoublings) return fail(EGT_ENOTCONV, "no initial mu satisfies the excessive gap condition");
       st->mu[0] *= 2.0;
       st->mu[1] *= 2.0;
@@ -239,11 +239,14 @@ int state_gap(egt_state* st, double* gap, double* brmax, double* brmin, hipStrea
   if (!st) return fail(EGT_EINVAL, "null state");
   if (!st->gap_valid) {
     int rc;
-    if ((rc = gap_of(st, st->G[0], 1.0, nullptr, 0.0, st->G[1], 1.0, nullptr, 0.0, st->dscal, s))) return rc;
-    if ((rc = fetch(st, 3, s))) return rc;
-    st->gap = st->hscal[0];
-    st->br_min_x = st->hscal[1];
-    st->br_max_y = -st->hscal[2];
+    Pass ps[2];
+    gap_passes(st, st->G[0], 1.0, nullptr, 0.0, st->G[1], 1.0, nullptr, 0.0, ps);
+    EGT_TRY(launch_passes(st->g, ps, 2, s));
+    EGT_TRY(launch_root_sums(st->g, ps, 2, st->dscal, s));
+    if ((rc = fetch(st, 2, s))) return rc;
+    st->br_min_x = st->hscal[0];
+    st->br_max_y = -st->hscal[1];
+    st->gap = -st->hscal[1] - st->hscal[0];
     st->gap_valid = true;
   }
   if (gap) *gap = st->gap;
@@ -253,8 +256,8 @@ int state_gap(egt_state* st, double* gap, double* brmax, double* brmin, hipStrea
 }
 
 // One attempt of the step focused on p at step size tau.  first = compute
-// x_bar (otherwise reuse it).  Leaves EGV and the candidate's saddle gap in
-// hscal[0..5].
+// x_bar (otherwise reuse it).  Leaves the two EGV terms and the two
+// best-response values of the candidate's saddle gap in dscal[0..3].
 static int attempt(egt_state* st, int p, double tau, bool first, hipStream_t s) {
   const egt_game* g = st->g;
   const int o = 1 - p;
@@ -275,19 +278,17 @@ static int attempt(egt_state* st, int p, double tau, bool first, hipStream_t s) 
     return rc;
   if ((rc = grad(st, o, st->Xn[p], st->T2[o], s))) return rc;
   const double mu_new = (1.0 - tau) * st->mu[p];
-  // EGV at (x_+, y_+) with mu_p+ and the unchanged mu_o
-  EGT_TRY(launch_bottom_up(g, p, st->G[p], kSg[p] * (1.0 - tau), st->T1[p], kSg[p] * tau, mu_new, st->V[p],
-                           nullptr, s));
-  EGT_TRY(launch_bottom_up(g, o, st->T2[o], kSg[o], nullptr, 0.0, st->mu[o], st->V[o], nullptr, s));
-  EGT_TRY(launch_root_sum(g, p, st->V[p], 1.0, o, st->V[o], 1.0, st->dscal, s));
-  // saddle gap of the candidate point (x_+, y_+)
-  if (p == 0) {
-    if ((rc = gap_of(st, st->G[0], 1.0 - tau, st->T1[0], tau, st->T2[1], 1.0, nullptr, 0.0, st->dscal + 3, s)))
-      return rc;
-  } else {
-    if ((rc = gap_of(st, st->T2[0], 1.0, nullptr, 0.0, st->G[1], 1.0 - tau, st->T1[1], tau, st->dscal + 3, s)))
-      return rc;
-  }
+  // one launch for the four value passes: EGV at (x_+, y_+) with mu_p+ and the
+  // unchanged mu_o, and the two best responses of the candidate's saddle gap
+  Pass ps[4];
+  ps[0] = Pass{p, st->G[p], kSg[p] * (1.0 - tau), st->T1[p], kSg[p] * tau, mu_new, st->V[p], nullptr};
+  ps[1] = Pass{o, st->T2[o], kSg[o], nullptr, 0.0, st->mu[o], st->V[o], nullptr};
+  if (p == 0)
+    gap_passes(st, st->G[0], 1.0 - tau, st->T1[0], tau, st->T2[1], 1.0, nullptr, 0.0, ps + 2);
+  else
+    gap_passes(st, st->T2[0], 1.0, nullptr, 0.0, st->G[1], 1.0 - tau, st->T1[1], tau, ps + 2);
+  EGT_TRY(launch_passes(g, ps, 4, s));
+  EGT_TRY(launch_root_sums(g, ps, 4, st->dscal, s));
   return EGT_OK;
 }
 
@@ -316,8 +317,8 @@ int state_step(egt_state* st, int player, double* egv_out, int* stepped, hipStre
   for (;;) {
     if ((rc = attempt(st, p, tau, first, s))) return rc;
     first = false;
-    if ((rc = fetch(st, 6, s))) return rc;
-    egv = st->hscal[0];
+    if ((rc = fetch(st, 4, s))) return rc;
+    egv = st->hscal[0] + st->hscal[1];
     if (variant != EGT_VARIANT_AS || !(egv < 0.0)) break;
     tau *= 0.5;
     st->backtracks++;
@@ -331,9 +332,9 @@ int state_step(egt_state* st, int player, double* egv_out, int* stepped, hipStre
   st->mu[p] *= (1.0 - tau);
   if (variant == EGT_VARIANT_AS) st->tau = tau;
   st->t++;
-  st->gap = st->hscal[3];
-  st->br_min_x = st->hscal[4];
-  st->br_max_y = -st->hscal[5];
+  st->br_min_x = st->hscal[2];
+  st->br_max_y = -st->hscal[3];
+  st->gap = -st->hscal[3] - st->hscal[2];
   st->gap_valid = true;
   st->last_egv = egv;
   if (egv_out) *egv_out = egv;
