@@ -31,7 +31,7 @@ int ensure_workspace(const egt_game* cg) {
   size_t elems = 0;
   for (int p = 0; p < 2; ++p)
     elems += 2 * (size_t)g->hp[p].n_seq * g->ld + (size_t)g->hp[p].n_nodes * g->ld;
-  elems += 16;
+  elems += 16 + (size_t)kMaxTrees * kMaxPartials;
   void* blk = nullptr;
   hipError_t e = hipMalloc(&blk, elems * sizeof(double));
   if (e != hipSuccess) return fail(EGT_ENOMEM, std::string("hipMalloc (workspace): ") + hipGetErrorString(e));
@@ -156,13 +156,13 @@ int egt_smoothed_br(const egt_game* g, int player, const double* grad, double mu
     int rc = ensure_workspace(g);
     if (rc) return rc;
     const Workspace& w = g->ws;
-    EGT_HIP(launch_bottom_up(g, player, grad, 1.0, nullptr, 0.0, mu, w.v[player], strat_out ? w.qb[player] : nullptr,
-                             stream));
-    if (strat_out) EGT_HIP(launch_top_down(g, player, w.qb[player], strat_out, nullptr, 0.0, nullptr, stream));
-    const Pass ps{player, grad, 1.0, nullptr, 0.0, mu, w.v[player], nullptr};
-    if (value_out) EGT_HIP(launch_root_sums(g, &ps, 1, w.scal, stream));
-    if (value_out)
+    const Pass ps{player, grad, 1.0, nullptr, 0.0, mu, w.v[player], w.qb[player]};
+    const Epilogue e{strat_out, nullptr, 0.0, nullptr};
+    EGT_HIP(launch_passes(g, &ps, 1, &e, value_out ? w.scal + 16 : nullptr, stream));
+    if (value_out) {
+      EGT_HIP(launch_sum_partials(g, w.scal + 16, 1, w.scal, stream));
       EGT_HIP(hipMemcpyAsync(value_out, w.scal, sizeof(double), hipMemcpyDeviceToDevice, stream));
+    }
     return EGT_OK;
   });
 }
@@ -175,8 +175,8 @@ int egt_best_response(const egt_game* g, int player, const double* grad, double*
     if (rc) return rc;
     const Workspace& w = g->ws;
     const Pass ps{player, grad, 1.0, nullptr, 0.0, 0.0, w.v[player], nullptr};
-    EGT_HIP(launch_passes(g, &ps, 1, stream));
-    EGT_HIP(launch_root_sums(g, &ps, 1, w.scal, stream));
+    EGT_HIP(launch_passes(g, &ps, 1, nullptr, w.scal + 16, stream));
+    EGT_HIP(launch_sum_partials(g, w.scal + 16, 1, w.scal, stream));
     EGT_HIP(hipMemcpyAsync(value_out, w.scal, sizeof(double), hipMemcpyDeviceToDevice, stream));
     return EGT_OK;
   });
@@ -204,8 +204,8 @@ int egt_saddle_gap(const egt_game* g, const double* x, const double* y, double* 
     EGT_HIP(launch_gradient(g, 1, x, w.grad[1], stream));
     const Pass ps[2] = {{0, w.grad[0], 1.0, nullptr, 0.0, 0.0, w.v[0], nullptr},
                         {1, w.grad[1], -1.0, nullptr, 0.0, 0.0, w.v[1], nullptr}};
-    EGT_HIP(launch_passes(g, ps, 2, stream));
-    EGT_HIP(launch_root_sums(g, ps, 2, w.scal, stream));
+    EGT_HIP(launch_passes(g, ps, 2, nullptr, w.scal + 16, stream));
+    EGT_HIP(launch_sum_partials(g, w.scal + 16, 2, w.scal, stream));
     EGT_HIP(hipMemcpyAsync(w.hscal, w.scal, 2 * sizeof(double), hipMemcpyDeviceToHost, stream));
     EGT_HIP(hipStreamSynchronize(stream));
     // gap = max_y x^T A y - min_x x^T A y = -BR_y(-A^T x) - BR_x(A y)

@@ -312,7 +312,9 @@ int build_game(const egt_game_desc* d, hipStream_t stream, egt_game** out) {
       hp.max_terms_per_seq = std::max(hp.max_terms_per_seq, (int)by[s].size());
     }
   }
-  g->fused_passes = g->hp[0].max_level_width <= kFusedNodeLimit && g->hp[1].max_level_width <= kFusedNodeLimit;
+  g->fused_passes =
+      fused_lds_bytes(std::max(g->hp[0].n_nodes, g->hp[1].n_nodes), std::max(g->hp[0].n_seq, g->hp[1].n_seq),
+                      std::max((int)g->hp[0].child.size(), (int)g->hp[1].child.size())) <= kFusedLdsLimit;
   for (const RawTerminal& t : en.terms) (t.kind == 0 ? g->n_fold : g->n_show)++;
   for (int p = 0; p < 2; ++p)
     for (double b : g->hp[p].node_beta) g->max_beta = std::max(g->max_beta, b);

@@ -15,8 +15,10 @@ namespace egt {
 constexpr int kMaxActions = 16;  // actions per decision node
 constexpr int kMaxDepth = 16;    // sequences on a root-to-leaf chain of one player (and levels)
 constexpr int kMaxTrees = 4;     // trees evaluated by one bottom-up launch
-constexpr int kFusedNodeLimit = 256;       // widest level for the single-launch bottom-up pass
-constexpr size_t kGradLdsLimit = 64 * 1024;  // LDS budget of one product block
+constexpr int kFusedHands = 16;            // hands per block of the single-launch pass
+constexpr size_t kGradLdsLimit = 64 * 1024;   // LDS budget of one product block
+constexpr size_t kFusedLdsLimit = 64 * 1024;  // LDS budget of one single-launch pass block
+constexpr int kMaxPartials = 2048 / kFusedHands;  // root partial sums per tree
 
 // ---------------------------------------------------------------------------
 // Error plumbing: every entry point converts failures into a status code and a
@@ -90,6 +92,7 @@ struct TreePass {
   double* V;
   double* QB;
   int n_levels;
+  int n_child;
   int level_begin[kMaxDepth + 1];
 };
 
@@ -100,6 +103,15 @@ struct PassSet {
   int n, ld;
   int level;                  // per-level kernel: the level of this launch
   int level_cnt[kMaxTrees];   // per-level kernel: nodes of each tree at `level`
+};
+
+// Top-down epilogue of a smoothed best response: q_out = q (may be null) and
+// comb_out = (1 - tau) x_prev + tau q (may be null).
+struct Epilogue {
+  double* q_out;
+  const double* x_prev;
+  double tau;
+  double* comb_out;
 };
 
 // Host description of one pass (player instead of device tables).
@@ -174,19 +186,19 @@ namespace egt {
 hipError_t launch_gradient(const egt_game* g, int player, const double* v_opp, double* grad_out,
                            hipStream_t s);
 
-// Bottom-up pass over all levels of `player`'s treeplex on the gradient
-// cA * gA + cB * gB (gB may be null).  mu > 0: smoothed (log-sum-exp) values,
-// q_bar written to QB when QB != null; mu == 0: best-response (min) values.
-hipError_t launch_bottom_up(const egt_game* g, int player, const double* gA, double cA,
-                            const double* gB, double cB, double mu, double* V, double* QB,
-                            hipStream_t s);
+// count (1..kMaxTrees) independent passes in as few launches as possible:
+// bottom-up over every level; when `partial` is not null, the tree values as
+// n_partials(g) partial sums per tree (partial[k * n_partials + b], to be
+// added in order of b); when epi[k] asks for it, the top-down rebuild of
+// tree k's strategy with its epilogue.  On the level path a smoothed pass
+// with an epilogue needs its QB buffer.
+hipError_t launch_passes(const egt_game* g, const Pass* p, int count, const Epilogue* epi, double* partial,
+                         hipStream_t s);
+int n_partials(const egt_game* g);
+size_t fused_lds_bytes(int cap_nodes, int cap_seqs, int cap_child);
 
-// count (1..kMaxTrees) independent bottom-up passes in the same launches.
-hipError_t launch_passes(const egt_game* g, const Pass* p, int count, hipStream_t s);
-
-// out[k] = value of pass k's tree (sum of its root values over hands), after
-// launch_passes with the same passes.
-hipError_t launch_root_sums(const egt_game* g, const Pass* p, int count, double* out, hipStream_t s);
+// out[k] = sum of the n_partials(g) partials of tree k, in order.
+hipError_t launch_sum_partials(const egt_game* g, const double* partial, int count, double* out, hipStream_t s);
 
 // Top-down pass: q = product of q_bar along the sequence's chain.  Writes q to
 // q_out (may be null) and (1 - tau) x_prev + tau q to comb_out (may be null).

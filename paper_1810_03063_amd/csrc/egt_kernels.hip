@@ -1,19 +1,23 @@
 // HIP kernels of the EGT hot path for gfx950 (CDNA4, 64-lane wavefronts).
 //
-//  * gradient_kernel  : payoff products A y / A^T x (Section 2's gradient
+//  * gradient_kernel   : payoff products A y / A^T x (Section 2's gradient
 //    operators) on fold and showdown terminals, O(n) per terminal;
-//  * bottom_up_kernel : one level of the smoothed best response (Section 4,
-//    Eq. 4 and the leaf / internal-simplex derivation), or of the best
-//    response when mu = 0;
-//  * top_down_kernel  : rebuild the sequence form q_i = q_{p_j} q_bar_i with
-//    a fused convex-combination epilogue (Algorithm 2's x_hat, y_+, x_+);
-//  * small reductions and vector combinations.
+//  * sbr_fused_kernel  : for trees whose tables fit in LDS, a whole smoothed
+//    best response (Section 4, Eq. 4 and the leaf / internal-simplex
+//    derivation) in one launch: bottom-up over every level, root-value
+//    partial sums, then the top-down rebuild q_i = q_{p_j} q_bar_i with the
+//    convex-combination epilogue of Algorithm 2 (x_hat, y_+, x_+);
+//    mu = 0 gives the best response;
+//  * bottom_up_level_kernel / top_down_kernel / root_sums_kernel : the same
+//    steps one level per launch for large trees;
+//  * small helpers (uniform point, a*x + b*y, max |x|).
 //
-// Every vector is double[rows][ld], hands (slots) fastest, so a wavefront's 64
-// lanes read 64 consecutive doubles of one row.  Reductions use a fixed order:
+// Every vector is double[rows][ld], hands (slots) fastest, so consecutive
+// lanes read consecutive doubles of one row.  Reductions use fixed orders, so
 // results are bitwise repeatable run to run.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 
 #include "egt_internal.h"
@@ -25,8 +29,7 @@ namespace {
 constexpr int kGroupThreads = 256;     // one wave group evaluates one terminal
 constexpr int kMaxHandsPerThread = 8;  // n <= 2048 = 256 threads x 8 contiguous hands
 constexpr int kPassThreads = 64;       // per-level pass: one wavefront per (node, 64 hands)
-constexpr int kFusedHands = 16;        // fused pass: hands per block
-constexpr int kFusedThreads = 1024;    // fused pass: 64 node slots x 16 hands
+constexpr int kFusedThreads = 1024;    // fused pass: kFusedSlots node slots x kFusedHands hands
 constexpr int kFusedSlots = kFusedThreads / kFusedHands;
 
 __device__ inline double wave_inclusive_scan(double x, int lane) {
@@ -90,7 +93,24 @@ __global__ __launch_bounds__(2 * kGroupThreads) void gradient_kernel(GradArgs a)
 #pragma unroll
   for (int k = 0; k < kMaxHandsPerThread; ++k) acc[k] = 0.0;
 
+  // the hand tables of this thread's chunk, loaded once
+  int4 HA[kMaxHandsPerThread], HB[kMaxHandsPerThread];
+  int2 TG[kMaxHandsPerThread];
+#pragma unroll
+  for (int k = 0; k < kMaxHandsPerThread; ++k) {
+    HA[k] = make_int4(0, 0, 0, 0);
+    HB[k] = make_int4(0, 0, 0, 0);
+    TG[k] = make_int2(0, 0);
+  }
   if (te > tb) {
+#pragma unroll
+    for (int k = 0; k < kMaxHandsPerThread; ++k) {
+      if (k < cnt) {
+        HA[k] = a.H.ha[beg + k];
+        HB[k] = a.H.hb[beg + k];
+        TG[k] = a.H.tie[beg + k];
+      }
+    }
     const int n_entries = a.H.card_begin[a.H.n_cards];
     for (int i = tid; i <= a.H.n_cards; i += blockDim.x) cbeg[i] = a.H.card_begin[i];
     for (int i = tid; i < n_entries; i += blockDim.x) chand[i] = a.H.card_hands[i];
@@ -110,13 +130,26 @@ __global__ __launch_bounds__(2 * kGroupThreads) void gradient_kernel(GradArgs a)
     }
     __syncthreads();
     double rloc[kMaxHandsPerThread];
+#pragma unroll
+    for (int k = 0; k < kMaxHandsPerThread; ++k) rloc[k] = 0.0;
     if (active) {
 #pragma unroll
       for (int k = 0; k < kMaxHandsPerThread; ++k) rloc[k] = k < cnt ? R[beg + k] : 0.0;
       for (int c = gt; c < a.H.n_cards; c += kGroupThreads) {
         const int cb = cbeg[c], len = cbeg[c + 1] - cb, base = cb + c;
         double run = 0.0;
-        for (int k = 0; k < len; ++k) {
+        int k = 0;
+        for (; k + 8 <= len; k += 8) {
+          double v[8];
+#pragma unroll
+          for (int j = 0; j < 8; ++j) v[j] = R[chand[cb + k + j]];
+#pragma unroll
+          for (int j = 0; j < 8; ++j) {
+            Pc[base + k + j] = run;
+            run += v[j];
+          }
+        }
+        for (; k < len; ++k) {
           Pc[base + k] = run;
           run += R[chand[cb + k]];
         }
@@ -150,21 +183,17 @@ __global__ __launch_bounds__(2 * kGroupThreads) void gradient_kernel(GradArgs a)
 #pragma unroll
       for (int k = 0; k < kMaxHandsPerThread; ++k) {
         if (k < cnt) {
-          const int i = beg + k;
-          const int4 A = a.H.ha[i];
+          const int4 A = HA[k];
           double op;
           if (kind == 0) {
             op = T - Pc[A.x + A.w];
-            if (a.H.cph == 2) {
-              const int4 B = a.H.hb[i];
-              op = op - Pc[B.x + B.w] + rloc[k];
-            }
+            if (a.H.cph == 2) op = op - Pc[HB[k].x + HB[k].w] + rloc[k];
           } else {
-            const int2 tg = a.H.tie[i];
+            const int2 tg = TG[k];
             double weaker = R[tg.x] - Pc[A.x + A.y];
             double stronger = (T - R[tg.y]) - (Pc[A.x + A.w] - Pc[A.x + A.z]);
             if (a.H.cph == 2) {
-              const int4 B = a.H.hb[i];
+              const int4 B = HB[k];
               weaker -= Pc[B.x + B.y];
               stronger -= Pc[B.x + B.w] - Pc[B.x + B.z];
             }
@@ -200,7 +229,7 @@ __global__ __launch_bounds__(2 * kGroupThreads) void gradient_kernel(GradArgs a)
 }
 
 // ---------------------------------------------------------------------------
-// Bottom-up passes.  One information set (node v, hand h) of a tree:
+// One information set (node v, hand h) of a bottom-up pass:
 //   g~_a = cA gA[v,a] + cB gB[v,a] + sum_{k in D(v,a)} V[k]
 //   smoothed (mu > 0, temp = mu beta_v):
 //     m = min_a g~_a,  w_a = exp(-(g~_a - m) / temp),  S = sum_a w_a
@@ -208,11 +237,14 @@ __global__ __launch_bounds__(2 * kGroupThreads) void gradient_kernel(GradArgs a)
 //   best response (mu = 0): V[v] = min_a g~_a.
 // The action with the smallest g~ has the largest q_bar (weight exactly 1), so
 // V is the value g~_i + temp log q_bar_i + temp log n_v at that action, and
-// every exponent is <= 0.
+// every exponent is <= 0.  Tables are read through the accessor `T`, the
+// child values through `getV`, results go through `putV` / `putQ`.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ void node_pass(const TreePass& t, int v, int h, size_t ld) {
-  const int s0 = t.P.node_first_seq[v];
-  const int na = t.P.node_nact[v];
+template <class Tab, class GetV, class PutV, class PutQ>
+__device__ __forceinline__ void node_pass(const TreePass& t, const Tab& T, int v, int h, size_t ld, GetV getV,
+                                          PutV putV, PutQ putQ, bool want_q) {
+  const int s0 = T.first(v);
+  const int na = T.nact(v);
   double gt[kMaxActions];
   double m = INFINITY;
 #pragma unroll
@@ -221,17 +253,17 @@ __device__ __forceinline__ void node_pass(const TreePass& t, int v, int h, size_
       const int s = s0 + k;
       double x = t.cA * t.gA[(size_t)s * ld + h];
       if (t.gB) x += t.cB * t.gB[(size_t)s * ld + h];
-      const int c1 = t.P.child_begin[s + 1];
-      for (int c = t.P.child_begin[s]; c < c1; ++c) x += t.V[(size_t)t.P.child[c] * ld + h];
+      const int c1 = T.cbeg(s + 1);
+      for (int c = T.cbeg(s); c < c1; ++c) x += getV(T.child(c));
       gt[k] = x;
       m = fmin(m, x);
     }
   }
   if (!(t.mu > 0.0)) {
-    t.V[(size_t)v * ld + h] = m;
+    putV(v, m);
     return;
   }
-  const double temp = t.mu * t.P.node_beta[v];
+  const double temp = t.mu * T.beta(v);
   double sum = 0.0;
 #pragma unroll
   for (int k = 0; k < kMaxActions; ++k) {
@@ -240,31 +272,128 @@ __device__ __forceinline__ void node_pass(const TreePass& t, int v, int h, size_
       sum += gt[k];
     }
   }
-  t.V[(size_t)v * ld + h] = (m - temp * log(sum)) + temp * t.P.node_logn[v];
-  if (t.QB) {
+  putV(v, (m - temp * log(sum)) + temp * T.logn(v));
+  if (want_q) {
 #pragma unroll
     for (int k = 0; k < kMaxActions; ++k)
-      if (k < na) t.QB[(size_t)(s0 + k) * ld + h] = gt[k] / sum;
+      if (k < na) putQ(s0 + k, gt[k] / sum);
   }
 }
 
-// Small trees: one launch covers every level.  Block = 16 hands x 64 node
-// slots of one tree; a level's nodes are spread over the slots and a block
-// barrier separates the levels (a node only needs its children's values, all
-// computed by this block for these hands).
-__global__ __launch_bounds__(kFusedThreads) void bottom_up_fused_kernel(PassSet a) {
-  const TreePass& t = a.t[blockIdx.y];
-  const int hl = threadIdx.x % kFusedHands, slot = threadIdx.x / kFusedHands;
+struct GlobalTab {
+  const DPlayer& P;
+  __device__ int first(int v) const { return P.node_first_seq[v]; }
+  __device__ int nact(int v) const { return P.node_nact[v]; }
+  __device__ double beta(int v) const { return P.node_beta[v]; }
+  __device__ double logn(int v) const { return P.node_logn[v]; }
+  __device__ int cbeg(int s) const { return P.child_begin[s]; }
+  __device__ int child(int c) const { return P.child[c]; }
+};
+
+struct LdsTab {
+  const int* f;
+  const int* na;
+  const double* b;
+  const double* ln;
+  const int* cb;
+  const int* ch;
+  __device__ int first(int v) const { return f[v]; }
+  __device__ int nact(int v) const { return na[v]; }
+  __device__ double beta(int v) const { return b[v]; }
+  __device__ double logn(int v) const { return ln[v]; }
+  __device__ int cbeg(int s) const { return cb[s]; }
+  __device__ int child(int c) const { return ch[c]; }
+};
+
+// ---------------------------------------------------------------------------
+// Fused pass for trees whose tables fit in LDS.  Block (16 hands, tree k):
+// stage the tree's tables, run every level bottom-up (node values and q_bar
+// of these hands stay in LDS; a block barrier separates the levels), write
+// the block's partial root sum (the tree value is a sum over (root, hand)),
+// then rebuild the sequence form top-down from q_bar and apply the epilogue.
+// Slots h >= n_hands (the row padding) write zeros.
+// ---------------------------------------------------------------------------
+struct FusedArgs {
+  PassSet ps;
+  Epilogue epi[kMaxTrees];
+  double* partial;  // [count][gridDim.x] or null
+  int cap_nodes, cap_seqs, cap_child;
+};
+
+__global__ __launch_bounds__(kFusedThreads) void sbr_fused_kernel(FusedArgs a) {
+  extern __shared__ double lds[];
+  const int k = blockIdx.y;
+  const TreePass& t = a.ps.t[k];
+  const Epilogue& e = a.epi[k];
+  const int N = t.P.n_nodes, S = t.P.n_seq, C = t.n_child;
+  double* Vl = lds;                                     // [cap_nodes][16]
+  double* Ql = Vl + (size_t)a.cap_nodes * kFusedHands;  // [cap_seqs][16]
+  double* beta = Ql + (size_t)a.cap_seqs * kFusedHands;
+  double* logn = beta + a.cap_nodes;
+  int* first = (int*)(logn + a.cap_nodes);
+  int* nact = first + a.cap_nodes;
+  int* cbeg = nact + a.cap_nodes;
+  int* child = cbeg + a.cap_seqs + 1;
+  int* spar = child + a.cap_child;
+  const int tid = threadIdx.x;
+  for (int i = tid; i < N; i += kFusedThreads) {
+    first[i] = t.P.node_first_seq[i];
+    nact[i] = t.P.node_nact[i];
+    beta[i] = t.P.node_beta[i];
+    logn[i] = t.P.node_logn[i];
+  }
+  for (int i = tid; i <= S; i += kFusedThreads) cbeg[i] = t.P.child_begin[i];
+  for (int i = tid; i < C; i += kFusedThreads) child[i] = t.P.child[i];
+  for (int i = tid; i < S; i += kFusedThreads) spar[i] = t.P.seq_parent[i];
+  __syncthreads();
+
+  const LdsTab T{first, nact, beta, logn, cbeg, child};
+  const int hl = tid % kFusedHands, slot = tid / kFusedHands;
   const int h = blockIdx.x * kFusedHands + hl;
+  const bool live = h < a.ps.n;
+  const bool want_q = (e.q_out || e.comb_out) && t.mu > 0.0;
+  const size_t ld = a.ps.ld;
+  auto getV = [&](int c) { return Vl[c * kFusedHands + hl]; };
+  auto putV = [&](int v, double x) { Vl[v * kFusedHands + hl] = x; };
+  auto putQ = [&](int s, double q) { Ql[s * kFusedHands + hl] = q; };
   for (int l = 0; l < t.n_levels; ++l) {
-    if (h < a.n)
-      for (int v = t.level_begin[l] + slot; v < t.level_begin[l + 1]; v += kFusedSlots) node_pass(t, v, h, a.ld);
+    if (live)
+      for (int v = t.level_begin[l] + slot; v < t.level_begin[l + 1]; v += kFusedSlots)
+        node_pass(t, T, v, h, ld, getV, putV, putQ, want_q);
     __syncthreads();
+  }
+  if (a.partial && tid < kFusedHands) {
+    double sv = 0.0;
+    if (live)
+      for (int r = 0; r < t.P.n_roots; ++r) sv += Vl[t.P.roots[r] * kFusedHands + hl];
+#pragma unroll
+    for (int off = kFusedHands / 2; off > 0; off >>= 1) sv += __shfl_down(sv, off, kFusedHands);
+    if (tid == 0) a.partial[(size_t)k * gridDim.x + blockIdx.x] = sv;
+  }
+  if (e.q_out || e.comb_out) {
+    for (int s = slot; s < S; s += kFusedSlots) {
+      const size_t idx = (size_t)s * ld + h;
+      if (!live) {
+        if (e.q_out) e.q_out[idx] = 0.0;
+        if (e.comb_out) e.comb_out[idx] = 0.0;
+        continue;
+      }
+      int depth = 0;
+      for (int q = s; q >= 0; q = spar[q]) ++depth;
+      double val = 1.0;
+      for (int j = depth - 1; j >= 0; --j) {
+        int q = s;
+        for (int i = 0; i < j; ++i) q = spar[q];
+        val *= Ql[q * kFusedHands + hl];
+      }
+      if (e.q_out) e.q_out[idx] = val;
+      if (e.comb_out) e.comb_out[idx] = (1.0 - e.tau) * e.x_prev[idx] + e.tau * val;
+    }
   }
 }
 
 // Large trees: one launch per level over all trees of the set; block = one
-// wavefront for (node, 64 hands).
+// wavefront for (node, 64 hands); node values and q_bar in global memory.
 __global__ __launch_bounds__(kPassThreads) void bottom_up_level_kernel(PassSet a) {
   int y = blockIdx.y, k = 0;
   while (k < a.count - 1 && y >= a.level_cnt[k]) {
@@ -274,20 +403,23 @@ __global__ __launch_bounds__(kPassThreads) void bottom_up_level_kernel(PassSet a
   const TreePass& t = a.t[k];
   const int h = blockIdx.x * kPassThreads + threadIdx.x;
   if (h >= a.n) return;
-  node_pass(t, t.level_begin[a.level] + y, h, a.ld);
+  const size_t ld = a.ld;
+  const GlobalTab T{t.P};
+  auto getV = [&](int c) { return t.V[(size_t)c * ld + h]; };
+  auto putV = [&](int v, double x) { t.V[(size_t)v * ld + h] = x; };
+  auto putQ = [&](int s, double q) { t.QB[(size_t)s * ld + h] = q; };
+  node_pass(t, T, t.level_begin[a.level] + y, h, ld, getV, putV, putQ, t.QB != nullptr);
 }
 
-// Root sums: a treeplex is a Cartesian product over (root node, hand), so its
-// value is the sum of the root simplexes' values.  Block k sums tree k in a
-// fixed order.
+// Root sums of the level path: block k sums tree k, roots in order, hands
+// strided over the threads, then a fixed-order reduction.
 __global__ __launch_bounds__(256) void root_sums_kernel(PassSet a, double* out) {
   __shared__ double part[4];
   const TreePass& t = a.t[blockIdx.x];
-  const int total = t.P.n_roots * a.n;
   double s = 0.0;
-  for (int i = threadIdx.x; i < total; i += 256) {
-    const int r = i / a.n, h = i - r * a.n;
-    s += t.V[(size_t)t.P.roots[r] * a.ld + h];
+  for (int r = 0; r < t.P.n_roots; ++r) {
+    const double* row = t.V + (size_t)t.P.roots[r] * a.ld;
+    for (int h = threadIdx.x; h < a.n; h += 256) s += row[h];
   }
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
@@ -296,10 +428,20 @@ __global__ __launch_bounds__(256) void root_sums_kernel(PassSet a, double* out) 
   if (threadIdx.x == 0) out[blockIdx.x] = ((part[0] + part[1]) + part[2]) + part[3];
 }
 
+// out[k] = sum of partial[k][0 .. nb) in order.
+__global__ __launch_bounds__(64) void sum_partials_kernel(const double* partial, int count, int nb, double* out) {
+  const int k = threadIdx.x;
+  if (k >= count) return;
+  double s = 0.0;
+  for (int b = 0; b < nb; ++b) s += partial[(size_t)k * nb + b];
+  out[k] = s;
+}
+
 // ---------------------------------------------------------------------------
-// Top-down pass, fully parallel: q[s] = q_bar[root] * ... * q_bar[s] along the
-// sequence's parent chain (multiplied from the root down), then the fused
-// epilogue comb = (1 - tau) x_prev + tau q.  Padding slots are written 0.
+// Top-down pass of the level path, fully parallel: q[s] = q_bar[root] * ...
+// * q_bar[s] along the sequence's parent chain (multiplied from the root
+// down), then the epilogue comb = (1 - tau) x_prev + tau q.  Padding slots are
+// written 0.
 // ---------------------------------------------------------------------------
 struct DownArgs {
   const int* seq_parent;
@@ -351,8 +493,7 @@ __global__ __launch_bounds__(kPassThreads) void uniform_qbar_kernel(UniformArgs 
 
 constexpr int kRedThreads = 1024;
 
-__global__ __launch_bounds__(kRedThreads) void max_abs_kernel(int64_t count, const double* X,
-                                                                double* out) {
+__global__ __launch_bounds__(kRedThreads) void max_abs_kernel(int64_t count, const double* X, double* out) {
   __shared__ double scratch[kRedThreads];
   double m = 0.0;
   for (int64_t i = threadIdx.x; i < count; i += kRedThreads) m = fmax(m, fabs(X[i]));
@@ -420,19 +561,38 @@ static void fill_pass_set(const egt_game* g, const Pass* p, int count, PassSet& 
     t.V = p[k].V;
     t.QB = p[k].QB;
     t.n_levels = hp.n_levels;
+    t.n_child = (int)hp.child.size();
     for (int l = 0; l <= kMaxDepth; ++l) t.level_begin[l] = hp.level_begin[std::min(l, hp.n_levels)];
   }
 }
 
-hipError_t launch_passes(const egt_game* g, const Pass* p, int count, hipStream_t s) {
+int n_partials(const egt_game* g) { return g->fused_passes ? g->ld / kFusedHands : 1; }
+
+size_t fused_lds_bytes(int cap_nodes, int cap_seqs, int cap_child) {
+  return sizeof(double) * ((size_t)(cap_nodes + cap_seqs) * kFusedHands + 2 * (size_t)cap_nodes) +
+         sizeof(int) * (2 * (size_t)cap_nodes + (cap_seqs + 1) + cap_child + cap_seqs);
+}
+
+hipError_t launch_passes(const egt_game* g, const Pass* p, int count, const Epilogue* epi, double* partial,
+                         hipStream_t s) {
   if (count < 1 || count > kMaxTrees) return hipErrorInvalidValue;
-  PassSet a;
-  fill_pass_set(g, p, count, a);
   if (g->fused_passes) {
-    const unsigned bx = (unsigned)((g->n + kFusedHands - 1) / kFusedHands);
-    hipLaunchKernelGGL(bottom_up_fused_kernel, dim3(bx, count), dim3(kFusedThreads), 0, s, a);
+    FusedArgs a;
+    fill_pass_set(g, p, count, a.ps);
+    for (int k = 0; k < kMaxTrees; ++k)
+      a.epi[k] = (epi && k < count) ? epi[k] : Epilogue{nullptr, nullptr, 0.0, nullptr};
+    a.partial = partial;
+    a.cap_nodes = std::max(g->hp[0].n_nodes, g->hp[1].n_nodes);
+    a.cap_seqs = std::max(g->hp[0].n_seq, g->hp[1].n_seq);
+    a.cap_child = std::max((int)g->hp[0].child.size(), (int)g->hp[1].child.size());
+    const size_t lds = fused_lds_bytes(a.cap_nodes, a.cap_seqs, a.cap_child);
+    hipLaunchKernelGGL(sbr_fused_kernel, dim3(g->ld / kFusedHands, count), dim3(kFusedThreads), lds, s, a);
     return hipGetLastError();
   }
+  PassSet a;
+  fill_pass_set(g, p, count, a);
+  for (int k = 0; k < count; ++k)
+    if (epi && (epi[k].q_out || epi[k].comb_out) && !p[k].QB) return hipErrorInvalidValue;
   int max_levels = 0;
   for (int k = 0; k < count; ++k) max_levels = std::max(max_levels, a.t[k].n_levels);
   const unsigned bx = (unsigned)((g->n + kPassThreads - 1) / kPassThreads);
@@ -449,22 +609,23 @@ hipError_t launch_passes(const egt_game* g, const Pass* p, int count, hipStream_
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
+  if (partial) {
+    hipLaunchKernelGGL(root_sums_kernel, dim3(count), dim3(256), 0, s, a, partial);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  for (int k = 0; epi && k < count; ++k) {
+    if (!epi[k].q_out && !epi[k].comb_out) continue;
+    const hipError_t e = launch_top_down(g, p[k].player, p[k].QB, epi[k].q_out, epi[k].x_prev, epi[k].tau,
+                                         epi[k].comb_out, s);
+    if (e != hipSuccess) return e;
+  }
   return hipSuccess;
 }
 
-hipError_t launch_root_sums(const egt_game* g, const Pass* p, int count, double* out, hipStream_t s) {
-  if (count < 1 || count > kMaxTrees) return hipErrorInvalidValue;
-  PassSet a;
-  fill_pass_set(g, p, count, a);
-  hipLaunchKernelGGL(root_sums_kernel, dim3(count), dim3(256), 0, s, a, out);
+hipError_t launch_sum_partials(const egt_game* g, const double* partial, int count, double* out, hipStream_t s) {
+  hipLaunchKernelGGL(sum_partials_kernel, dim3(1), dim3(64), 0, s, partial, count, n_partials(g), out);
   return hipGetLastError();
-}
-
-hipError_t launch_bottom_up(const egt_game* g, int player, const double* gA, double cA,
-                            const double* gB, double cB, double mu, double* V, double* QB,
-                            hipStream_t s) {
-  const Pass p{player, gA, cA, gB, cB, mu, V, QB};
-  return launch_passes(g, &p, 1, s);
 }
 
 hipError_t launch_top_down(const egt_game* g, int player, const double* QB, double* q_out,

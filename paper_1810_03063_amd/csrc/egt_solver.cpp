@@ -49,7 +49,9 @@ struct egt_state {
   double* V[2] = {};
   double* Vb[2] = {};       // node values of the best-response passes
   double* dscal = nullptr;  // device scalars
-  double* hscal = nullptr;  // pinned host mirror
+  double* hscal = nullptr;  // pinned host mirror (also the summed tree values)
+  double* dpart = nullptr;  // device root partial sums [trees][n_partials]
+  double* hpart = nullptr;  // pinned host mirror
   void* block = nullptr;
   // last saddle gap of the current iterate (valid when gap_valid)
   bool gap_valid = false;
@@ -73,18 +75,34 @@ int64_t vec_elems(const egt_game* g, int p) { return (int64_t)g->hp[p].n_seq * g
     if (_e != hipSuccess) return ::egt::hip_fail(_e, #expr);     \
   } while (0)
 
-// Smoothed best response into strat (and optionally the fused combination).
+// Smoothed best response of player p to cA gA + cB gB: q to q_out and the
+// epilogue (1 - tau) x_prev + tau q to comb_out (either may be null).
 int sbr(egt_state* st, int p, const double* gA, double cA, const double* gB, double cB, double mu,
         double* q_out, const double* x_prev, double tau, double* comb_out, hipStream_t s) {
-  const egt_game* g = st->g;
-  EGT_TRY(launch_bottom_up(g, p, gA, cA, gB, cB, mu, st->V[p], st->QB[p], s));
-  EGT_TRY(launch_top_down(g, p, st->QB[p], q_out, x_prev, tau, comb_out, s));
+  const Pass ps{p, gA, cA, gB, cB, mu, st->V[p], st->QB[p]};
+  const Epilogue e{q_out, x_prev, tau, comb_out};
+  EGT_TRY(launch_passes(st->g, &ps, 1, &e, nullptr, s));
   return EGT_OK;
 }
 
 int grad(egt_state* st, int p, const double* v_opp, double* out, hipStream_t s) {
   st->products++;
   EGT_TRY(launch_gradient(st->g, p, v_opp, out, s));
+  return EGT_OK;
+}
+
+// Copies the root partial sums of `trees` trees to the host and adds each
+// tree's partials in order into hscal[k].
+int fetch_values(egt_state* st, int trees, hipStream_t s) {
+  const int nb = n_partials(st->g);
+  EGT_TRY(hipMemcpyAsync(st->hpart, st->dpart, sizeof(double) * trees * nb, hipMemcpyDeviceToHost, s));
+  EGT_TRY(hipStreamSynchronize(s));
+  for (int k = 0; k < trees; ++k) {
+    double v = 0.0;
+    for (int b = 0; b < nb; ++b) v += st->hpart[k * nb + b];
+    if (!std::isfinite(v)) return fail(EGT_ENUMERIC, "non-finite value in the EGT driver");
+    st->hscal[k] = v;
+  }
   return EGT_OK;
 }
 
@@ -96,13 +114,12 @@ int fetch(egt_state* st, int count, hipStream_t s) {
   return EGT_OK;
 }
 
-// EGV at (X, Y) with the state's G and mu -> dscal[0] + dscal[1].
+// EGV at (X, Y) with the state's G and mu -> hscal[0] + hscal[1] after fetch_values.
 int egv_current(egt_state* st, hipStream_t s) {
   const egt_game* g = st->g;
   const Pass ps[2] = {{0, st->G[0], kSg[0], nullptr, 0.0, st->mu[0], st->V[0], nullptr},
                       {1, st->G[1], kSg[1], nullptr, 0.0, st->mu[1], st->V[1], nullptr}};
-  EGT_TRY(launch_passes(g, ps, 2, s));
-  EGT_TRY(launch_root_sums(g, ps, 2, st->dscal, s));
+  EGT_TRY(launch_passes(g, ps, 2, nullptr, st->dpart, s));
   return EGT_OK;
 }
 
@@ -158,11 +175,13 @@ int state_create(const egt_game* g, const egt_solve_opts* o, hipStream_t s, egt_
   size_t bytes = 0;
   for (int p = 0; p < 2; ++p)
     bytes += sizeof(double) * (8 * (size_t)vec_elems(g, p) + 2 * (size_t)g->hp[p].n_nodes * g->ld);
-  bytes += 64 * sizeof(double);
+  bytes += (64 + (size_t)kMaxTrees * kMaxPartials) * sizeof(double);
   hipError_t e = hipMalloc(&st->block, bytes);
   if (e != hipSuccess) return fail(EGT_ENOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
-  e = hipHostMalloc((void**)&st->hscal, 64 * sizeof(double), hipHostMallocDefault);
+  e = hipHostMalloc((void**)&st->hscal, (64 + (size_t)kMaxTrees * kMaxPartials) * sizeof(double),
+                    hipHostMallocDefault);
   if (e != hipSuccess) return fail(EGT_ENOMEM, std::string("hipHostMalloc: ") + hipGetErrorString(e));
+  st->hpart = st->hscal + 64;
   double* cur = (double*)st->block;
   auto take = [&](int64_t n) {
     double* r = cur;
@@ -183,6 +202,7 @@ int state_create(const egt_game* g, const egt_solve_opts* o, hipStream_t s, egt_
     st->Vb[p] = take((int64_t)g->hp[p].n_nodes * g->ld);
   }
   st->dscal = take(64);
+  st->dpart = take((int64_t)kMaxTrees * kMaxPartials);
   EGT_HIP(hipMemsetAsync(st->block, 0, bytes, s));
 
   // x_omega and A^T x_omega (kept in T2[1] for the mu search)
@@ -205,7 +225,7 @@ int state_create(const egt_game* g, const egt_solve_opts* o, hipStream_t s, egt_
     for (int k = 0;; ++k) {
       if ((rc = init_point(st, st->T2[1], s))) return rc;
       if ((rc = egv_current(st, s))) return rc;
-      if ((rc = fetch(st, 2, s))) return rc;
+      if ((rc = fetch_values(st, 2, s))) return rc;
       if (!(st->hscal[0] + st->hscal[1] < 0.0)) break;
       if (k >= kMaxDoublings) return fail(EGT_ENOTCONV, "no initial mu satisfies the excessive gap condition");
       st->mu[0] *= 2.0;
@@ -241,9 +261,8 @@ int state_gap(egt_state* st, double* gap, double* brmax, double* brmin, hipStrea
     int rc;
     Pass ps[2];
     gap_passes(st, st->G[0], 1.0, nullptr, 0.0, st->G[1], 1.0, nullptr, 0.0, ps);
-    EGT_TRY(launch_passes(st->g, ps, 2, s));
-    EGT_TRY(launch_root_sums(st->g, ps, 2, st->dscal, s));
-    if ((rc = fetch(st, 2, s))) return rc;
+    EGT_TRY(launch_passes(st->g, ps, 2, nullptr, st->dpart, s));
+    if ((rc = fetch_values(st, 2, s))) return rc;
     st->br_min_x = st->hscal[0];
     st->br_max_y = -st->hscal[1];
     st->gap = -st->hscal[1] - st->hscal[0];
@@ -257,7 +276,7 @@ int state_gap(egt_state* st, double* gap, double* brmax, double* brmin, hipStrea
 
 // One attempt of the step focused on p at step size tau.  first = compute
 // x_bar (otherwise reuse it).  Leaves the two EGV terms and the two
-// best-response values of the candidate's saddle gap in dscal[0..3].
+// best-response values of the candidate's saddle gap as root partials (dpart).
 static int attempt(egt_state* st, int p, double tau, bool first, hipStream_t s) {
   const egt_game* g = st->g;
   const int o = 1 - p;
@@ -287,8 +306,7 @@ static int attempt(egt_state* st, int p, double tau, bool first, hipStream_t s) 
     gap_passes(st, st->G[0], 1.0 - tau, st->T1[0], tau, st->T2[1], 1.0, nullptr, 0.0, ps + 2);
   else
     gap_passes(st, st->T2[0], 1.0, nullptr, 0.0, st->G[1], 1.0 - tau, st->T1[1], tau, ps + 2);
-  EGT_TRY(launch_passes(g, ps, 4, s));
-  EGT_TRY(launch_root_sums(g, ps, 4, st->dscal, s));
+  EGT_TRY(launch_passes(g, ps, 4, nullptr, st->dpart, s));
   return EGT_OK;
 }
 
@@ -317,7 +335,7 @@ int state_step(egt_state* st, int player, double* egv_out, int* stepped, hipStre
   for (;;) {
     if ((rc = attempt(st, p, tau, first, s))) return rc;
     first = false;
-    if ((rc = fetch(st, 4, s))) return rc;
+    if ((rc = fetch_values(st, 4, s))) return rc;
     egv = st->hscal[0] + st->hscal[1];
     if (variant != EGT_VARIANT_AS || !(egv < 0.0)) break;
     tau *= 0.5;
