@@ -160,12 +160,34 @@ int egt_saddle_gap(const egt_game* game, const double* x, const double* y, doubl
                    double* br_max_y, double* br_min_x, hipStream_t stream);
 
 /* ------------------------------------------------------------------------ */
+/* Precision form (FP32 vectors in the same canonical layout)                 */
+/* ------------------------------------------------------------------------ */
+
+/* Payoff product of the precision form (same operator as egt_gradient, Section
+ * 2): fold terminals by the O(n) per-card evaluation in FP64 arithmetic; all
+ * showdown terminals of the player stacked into one contraction W Y on the
+ * BF16 matrix cores, with W in {-1, 0, +1} (exact in BF16) over the
+ * strength-ordered hands and Y = b_o * v_o split into hi + lo BF16, FP32
+ * accumulation; FP32 output.  The first call on a game builds W (n x n BF16)
+ * and synchronises the device.  EGT_EINVAL when a sequence ends in more than
+ * one showdown terminal. */
+int egt_gradient_mixed(const egt_game* game, int player, const float* strat_other, float* grad_out,
+                       hipStream_t stream);
+
+/* Smoothed best response of the precision form (Section 4, Eq. 4): FP32
+ * gradient in, FP32 exponentials and strategy, FP64 normalisers and values.
+ * strat_out / value_out as in egt_smoothed_br (value_out is a device double). */
+int egt_smoothed_br_mixed(const egt_game* game, int player, const float* grad, double mu,
+                          float* strat_out, double* value_out, hipStream_t stream);
+
+/* ------------------------------------------------------------------------ */
 /* EGT driver (Algorithms 1-4)                                                */
 /* ------------------------------------------------------------------------ */
 
 typedef struct {
   int32_t variant;    /* EGT_VARIANT_ALT (Alg. 1), _BAL (mu balancing), _AS (Alg. 3/4) */
-  int32_t precision;  /* EGT_PRECISION_FP64 */
+  int32_t precision;  /* EGT_PRECISION_FP64, or EGT_PRECISION_MIXED: FP32 iterates and products,
+                         BF16 showdown GEMM, FP64 normalisers, mu/tau and saddle gap */
   double eps;         /* target saddle gap; <= 0 means 1e-3 * pot */
   int64_t max_iters;  /* iteration cap (accepted steps) */
   double mu0_x;       /* initial mu; <= 0 (both) means automatic with doubling search */
@@ -238,6 +260,52 @@ int egt_state_gap(egt_state* state, double* gap, double* br_max_y, double* br_mi
  * still filled). */
 int egt_solve(const egt_game* game, const egt_solve_opts* opts, egt_result* result,
               egt_state** state_out, hipStream_t stream);
+
+/* ------------------------------------------------------------------------ */
+/* Serving form: continuous batching of solves on one device                  */
+/* ------------------------------------------------------------------------ */
+
+typedef struct egt_batch egt_batch;
+
+/* Device bytes a state of `game` with `opts` (precision) allocates; the
+ * admission test of egt_batch_admit charges exactly this. */
+int egt_state_bytes(const egt_game* game, const egt_solve_opts* opts, int64_t* bytes);
+
+/* A batch of at most max_slots concurrent solves whose states together stay
+ * within budget_bytes of device memory. */
+int egt_batch_create(int64_t budget_bytes, int32_t max_slots, egt_batch** out);
+
+/* Retires every slot and frees the batch.  NULL is accepted. */
+int egt_batch_destroy(egt_batch* batch);
+
+/* Starts a solve of `game` (caller-owned; it must outlive the slot) with
+ * `opts` in a free slot, on a stream of its own: allocates its state and runs
+ * the start-up of Algorithms 1/3 (synchronising that stream).  EGT_EBUDGET
+ * when the state does not fit the remaining budget or no slot is free; the
+ * caller retries after a retire. */
+int egt_batch_admit(egt_batch* batch, const egt_game* game, const egt_solve_opts* opts,
+                    int32_t* slot);
+
+/* Advances every live solve by one phase (a saddle-gap test when due, else one
+ * attempt of an EGT step): all phases are enqueued on their streams first,
+ * then each is waited for, so solves overlap on the device.  A solve whose
+ * gap reaches its eps (or whose iteration cap is reached) becomes done.
+ * n_active: live solves after the tick; n_finished: solves done in this tick.
+ * A solve's result is bitwise the same as a lone egt_solve with the same
+ * options. */
+int egt_batch_tick(egt_batch* batch, int32_t* n_active, int32_t* n_finished);
+
+/* done = 1 once the slot's solve has finished; then status (EGT_OK,
+ * EGT_ENOTCONV or the error that stopped it) and the result are valid.
+ * result->seconds counts from admission to completion. */
+int egt_batch_poll(egt_batch* batch, int32_t slot, int32_t* done, int32_t* status,
+                   egt_result* result);
+
+/* Frees the slot's state and stream and returns its bytes to the budget. */
+int egt_batch_retire(egt_batch* batch, int32_t slot);
+
+/* Bytes charged by live and done slots, and their counts. */
+int egt_batch_usage(const egt_batch* batch, int64_t* used_bytes, int32_t* n_live, int32_t* n_done);
 
 #ifdef __cplusplus
 }

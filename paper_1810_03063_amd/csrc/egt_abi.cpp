@@ -167,6 +167,38 @@ int egt_smoothed_br(const egt_game* g, int player, const double* grad, double mu
   });
 }
 
+int egt_gradient_mixed(const egt_game* g, int player, const float* strat_other, float* grad_out,
+                       hipStream_t stream) {
+  if (!g || bad_player(player) || !strat_other || !grad_out)
+    return fail(EGT_EINVAL, "null argument or bad player");
+  if ((const void*)strat_other == (const void*)grad_out) return fail(EGT_EINVAL, "grad_out must not alias strat_other");
+  return guarded([&]() -> int {
+    const int rc = ensure_mixed_tables(g);
+    if (rc) return rc;
+    EGT_HIP(launch_gradient_mixed(g, player, strat_other, grad_out, stream));
+    return EGT_OK;
+  });
+}
+
+int egt_smoothed_br_mixed(const egt_game* g, int player, const float* grad, double mu, float* strat_out,
+                          double* value_out, hipStream_t stream) {
+  if (!g || bad_player(player) || !grad) return fail(EGT_EINVAL, "null argument or bad player");
+  if (!(mu > 0) || !std::isfinite(mu)) return fail(EGT_EINVAL, "mu must be finite and > 0");
+  return guarded([&]() -> int {
+    int rc = ensure_workspace(g);
+    if (rc) return rc;
+    const Workspace& w = g->ws;
+    const Pass ps{player, grad, 1.0, nullptr, 0.0, mu, w.v[player], w.qb[player]};
+    const Epilogue e{strat_out, nullptr, 0.0, nullptr};
+    EGT_HIP(launch_passes(g, &ps, 1, &e, value_out ? w.scal + 16 : nullptr, stream, kF32));
+    if (value_out) {
+      EGT_HIP(launch_sum_partials(g, w.scal + 16, 1, w.scal, stream));
+      EGT_HIP(hipMemcpyAsync(value_out, w.scal, sizeof(double), hipMemcpyDeviceToDevice, stream));
+    }
+    return EGT_OK;
+  });
+}
+
 int egt_best_response(const egt_game* g, int player, const double* grad, double* value_out,
                       hipStream_t stream) {
   if (!g || bad_player(player) || !grad || !value_out) return fail(EGT_EINVAL, "null argument or bad player");

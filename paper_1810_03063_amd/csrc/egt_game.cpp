@@ -312,8 +312,11 @@ int build_game(const egt_game_desc* d, hipStream_t stream, egt_game** out) {
       hp.max_terms_per_seq = std::max(hp.max_terms_per_seq, (int)by[s].size());
     }
   }
+  // enough 4-hand blocks to spread over the chip; 16-hand blocks for tiny hand counts
+  g->fused_hands = g->ld >= 512 ? 4 : 16;
   g->fused_passes =
-      fused_lds_bytes(std::max(g->hp[0].n_nodes, g->hp[1].n_nodes), std::max(g->hp[0].n_seq, g->hp[1].n_seq),
+      fused_lds_bytes(g->fused_hands, std::max(g->hp[0].n_nodes, g->hp[1].n_nodes),
+                      std::max(g->hp[0].n_seq, g->hp[1].n_seq),
                       std::max((int)g->hp[0].child.size(), (int)g->hp[1].child.size())) <= kFusedLdsLimit;
   for (const RawTerminal& t : en.terms) (t.kind == 0 ? g->n_fold : g->n_show)++;
   for (int p = 0; p < 2; ++p)
@@ -325,6 +328,12 @@ int build_game(const egt_game_desc* d, hipStream_t stream, egt_game** out) {
   std::stable_sort(perm.begin(), perm.end(),
                    [&](int a, int b) { return d->strength[a] < d->strength[b]; });
   g->perm = perm;
+  g->slot_cards.resize((size_t)n * cph);
+  g->slot_strength.resize(n);
+  for (int i = 0; i < n; ++i) {
+    g->slot_strength[i] = d->strength[perm[i]];
+    for (int j = 0; j < cph; ++j) g->slot_cards[(size_t)i * cph + j] = d->hand_cards[perm[i] * cph + j];
+  }
   std::vector<int2> tie(n);
   for (int i = 0; i < n;) {
     int j = i;
@@ -472,9 +481,10 @@ int build_game(const egt_game_desc* d, hipStream_t stream, egt_game** out) {
 int free_game(egt_game* g) {
   if (!g) return EGT_OK;
   int st = EGT_OK;
-  if (g->mem.base || g->ws.block || g->ws.hscal) {
+  if (g->mem.base || g->ws.block || g->ws.hscal || g->mx.block) {
     hipError_t e = hipDeviceSynchronize();
     if (e == hipSuccess && g->mem.base) e = hipFree(g->mem.base);
+    if (e == hipSuccess && g->mx.block) e = hipFree(g->mx.block);
     if (e == hipSuccess && g->ws.block) e = hipFree(g->ws.block);
     if (e == hipSuccess && g->ws.hscal) e = hipHostFree(g->ws.hscal);
     if (e != hipSuccess) st = hip_fail(e, "free_game");

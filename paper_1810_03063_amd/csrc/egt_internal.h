@@ -15,10 +15,9 @@ namespace egt {
 constexpr int kMaxActions = 16;  // actions per decision node
 constexpr int kMaxDepth = 16;    // sequences on a root-to-leaf chain of one player (and levels)
 constexpr int kMaxTrees = 4;     // trees evaluated by one bottom-up launch
-constexpr int kFusedHands = 16;            // hands per block of the single-launch pass
 constexpr size_t kGradLdsLimit = 64 * 1024;   // LDS budget of one product block
 constexpr size_t kFusedLdsLimit = 64 * 1024;  // LDS budget of one single-launch pass block
-constexpr int kMaxPartials = 2048 / kFusedHands;  // root partial sums per tree
+constexpr int kMaxPartials = 2048 / 4;      // root partial sums per tree (4 hands per block)
 
 // ---------------------------------------------------------------------------
 // Error plumbing: every entry point converts failures into a status code and a
@@ -84,13 +83,13 @@ struct DHands {
 // QB != null) or best response (mu == 0).  Node values go to V.
 struct TreePass {
   DPlayer P;
-  const double* gA;
+  const void* gA;  // double or float, per the launch's precision
   double cA;
-  const double* gB;
+  const void* gB;
   double cB;
   double mu;
-  double* V;
-  double* QB;
+  double* V;       // node values: always FP64
+  void* QB;        // q_bar in the launch's precision
   int n_levels;
   int n_child;
   int level_begin[kMaxDepth + 1];
@@ -108,23 +107,27 @@ struct PassSet {
 // Top-down epilogue of a smoothed best response: q_out = q (may be null) and
 // comb_out = (1 - tau) x_prev + tau q (may be null).
 struct Epilogue {
-  double* q_out;
-  const double* x_prev;
+  void* q_out;
+  const void* x_prev;
   double tau;
-  double* comb_out;
+  void* comb_out;
 };
 
 // Host description of one pass (player instead of device tables).
 struct Pass {
   int player;
-  const double* gA;
+  const void* gA;
   double cA;
-  const double* gB;
+  const void* gB;
   double cB;
   double mu;
   double* V;
-  double* QB;
+  void* QB;
 };
+
+// Element type of the gradients, q_bar and strategies of a launch: FP64, or
+// FP32 for the precision form (node values and normalisers stay FP64).
+enum Prec { kF64 = 0, kF32 = 1 };
 
 // ---------------------------------------------------------------------------
 // Host-side tables kept with a game.
@@ -159,6 +162,18 @@ struct Workspace {
   double* hscal = nullptr;  // pinned host mirror of scal
 };
 
+// Precision-form tables (built on first use): W in BF16 bits over the slot
+// order, padded to kpad x kpad, and per player the showdown columns.
+struct MixedTables {
+  void* block = nullptr;
+  int kpad = 0;
+  const unsigned short* W = nullptr;
+  int L[2] = {0, 0};
+  const int* col_own[2] = {nullptr, nullptr};
+  const int* col_opp[2] = {nullptr, nullptr};
+  const double* col_coef[2] = {nullptr, nullptr};
+};
+
 }  // namespace egt
 
 struct egt_game {
@@ -167,13 +182,16 @@ struct egt_game {
   int64_t n_fold = 0, n_show = 0;
   egt::HostPlayer hp[2];
   std::vector<int> perm;  // slot -> caller hand index
+  std::vector<int> slot_cards, slot_strength;  // cards [n * cph] and strengths [n] in slot order
   egt::DPlayer dp[2];
   egt::DHands dh;
   egt::DeviceBlock mem;
   egt::Workspace ws;
+  egt::MixedTables mx;
   int device = 0;
   double max_beta = 0;
-  bool fused_passes = false;  // every level of both trees fits one block's node slots
+  bool fused_passes = false;  // both treeplexes' tables fit one block's LDS: single-launch passes
+  int fused_hands = 4;        // hands per block of the single-launch pass (4 or 16)
 };
 
 namespace egt {
@@ -193,24 +211,39 @@ hipError_t launch_gradient(const egt_game* g, int player, const double* v_opp, d
 // tree k's strategy with its epilogue.  On the level path a smoothed pass
 // with an epilogue needs its QB buffer.
 hipError_t launch_passes(const egt_game* g, const Pass* p, int count, const Epilogue* epi, double* partial,
-                         hipStream_t s);
+                         hipStream_t s, Prec prec = kF64);
 int n_partials(const egt_game* g);
-size_t fused_lds_bytes(int cap_nodes, int cap_seqs, int cap_child);
+size_t fused_lds_bytes(int hands, int cap_nodes, int cap_seqs, int cap_child);
 
 // out[k] = sum of the n_partials(g) partials of tree k, in order.
 hipError_t launch_sum_partials(const egt_game* g, const double* partial, int count, double* out, hipStream_t s);
 
 // Top-down pass: q = product of q_bar along the sequence's chain.  Writes q to
 // q_out (may be null) and (1 - tau) x_prev + tau q to comb_out (may be null).
-hipError_t launch_top_down(const egt_game* g, int player, const double* QB, double* q_out,
-                           const double* x_prev, double tau, double* comb_out, hipStream_t s);
+hipError_t launch_top_down(const egt_game* g, int player, const void* QB, void* q_out, const void* x_prev,
+                           double tau, void* comb_out, hipStream_t s, Prec prec = kF64);
 
 // QB = 1 / (number of actions) everywhere (the uniform point's q_bar).
 hipError_t launch_uniform_qbar(const egt_game* g, int player, double* QB, hipStream_t s);
 
-// out = a * X + b * Y over rows x ld doubles (Y may be null).
-hipError_t launch_axpby(int64_t count, double a, const double* X, double b, const double* Y,
-                        double* out, hipStream_t s);
+// out = a * X + b * Y over count elements (Y may be null).
+hipError_t launch_axpby(int64_t count, double a, const void* X, double b, const void* Y, void* out, hipStream_t s,
+                        Prec prec = kF64);
+
+// out = in converted FP32 -> FP64 (in_prec kF32) or FP64 -> FP32 (in_prec kF64).
+hipError_t launch_convert(int64_t count, const void* in, Prec in_prec, void* out, hipStream_t s);
+
+// Fold part of the product in FP32 for the precision form: like
+// launch_gradient, but showdown terminals are skipped (their contribution is
+// added by launch_show_gemm) and vectors are FP32.
+hipError_t launch_gradient_fold_f32(const egt_game* g, int player, const float* v_opp, float* grad_out,
+                                    hipStream_t s);
+
+// Precision form: W and the showdown columns (once per game); the product
+// fold part (FP32 O(n)) + showdown part (BF16 hi/lo MFMA GEMM, FP32 output).
+int ensure_mixed_tables(const egt_game* g);
+hipError_t launch_show_gemm(const egt_game* g, int player, const float* v_opp, float* grad_out, hipStream_t s);
+hipError_t launch_gradient_mixed(const egt_game* g, int player, const float* v_opp, float* grad_out, hipStream_t s);
 
 // out[0] = max |X| over count doubles.
 hipError_t launch_max_abs(int64_t count, const double* X, double* out, hipStream_t s);

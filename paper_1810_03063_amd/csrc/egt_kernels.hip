@@ -19,6 +19,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <type_traits>
 
 #include "egt_internal.h"
 
@@ -29,8 +30,7 @@ namespace {
 constexpr int kGroupThreads = 256;     // one wave group evaluates one terminal
 constexpr int kMaxHandsPerThread = 8;  // n <= 2048 = 256 threads x 8 contiguous hands
 constexpr int kPassThreads = 64;       // per-level pass: one wavefront per (node, 64 hands)
-constexpr int kFusedThreads = 1024;    // fused pass: kFusedSlots node slots x kFusedHands hands
-constexpr int kFusedSlots = kFusedThreads / kFusedHands;
+constexpr int kFusedSlots = 64;        // fused pass: node slots per block (x HB hands per slot)
 
 __device__ inline double wave_inclusive_scan(double x, int lane) {
 #pragma unroll
@@ -60,17 +60,20 @@ __device__ inline double wave_inclusive_scan(double x, int lane) {
 // for player 2 (its gradient sums over player 1's hands).  Group partial sums
 // are combined in a fixed order, so the result is bitwise repeatable.
 // ---------------------------------------------------------------------------
+template <class TV, class TO>
 struct GradArgs {
   DPlayer own;
   const double* b_opp;
   DHands H;
-  const double* v_opp;
-  double* out;
+  const TV* v_opp;
+  TO* out;
   double show_sign;
   int groups;
+  int fold_only;  // skip showdown terminals (their part is added by the BF16 GEMM)
 };
 
-__global__ __launch_bounds__(2 * kGroupThreads) void gradient_kernel(GradArgs a) {
+template <class TV, class TO>
+__global__ __launch_bounds__(2 * kGroupThreads) void gradient_kernel(GradArgs<TV, TO> a) {
   extern __shared__ double lds[];
   __shared__ double wave_total[2][kGroupThreads / 64];
   const int n = a.H.n, ld = a.H.ld;
@@ -118,15 +121,16 @@ __global__ __launch_bounds__(2 * kGroupThreads) void gradient_kernel(GradArgs a)
   const int rounds = (te - tb + groups - 1) / groups;
   for (int rd = 0; rd < rounds; ++rd) {
     const int t = tb + rd * groups + grp;
-    const bool active = t < te;  // uniform within a group
+    bool active = t < te;  // uniform within a group
+    if (active && a.fold_only && a.own.term_kind[t] != 0) active = false;
     int kind = 0;
     double coef = 0.0;
     if (active) {
       const int opp = a.own.term_opp[t];
       kind = a.own.term_kind[t];
       coef = a.own.term_coef[t];
-      const double* v = opp >= 0 ? a.v_opp + (size_t)opp * ld : nullptr;
-      for (int i = gt; i < n; i += kGroupThreads) R[i] = a.b_opp[i] * (v ? v[i] : 1.0);
+      const TV* v = opp >= 0 ? a.v_opp + (size_t)opp * ld : nullptr;
+      for (int i = gt; i < n; i += kGroupThreads) R[i] = a.b_opp[i] * (v ? (double)v[i] : 1.0);
     }
     __syncthreads();
     double rloc[kMaxHandsPerThread];
@@ -220,11 +224,11 @@ __global__ __launch_bounds__(2 * kGroupThreads) void gradient_kernel(GradArgs a)
     }
   }
   if (grp == 0) {
-    double* row = a.out + (size_t)s * ld;
+    TO* row = a.out + (size_t)s * ld;
 #pragma unroll
     for (int k = 0; k < kMaxHandsPerThread; ++k)
-      if (k < cnt) row[beg + k] = acc[k] * (a.own.belief[beg + k] * a.H.invZ);
-    for (int i = n + gt; i < ld; i += kGroupThreads) row[i] = 0.0;
+      if (k < cnt) row[beg + k] = (TO)(acc[k] * (a.own.belief[beg + k] * a.H.invZ));
+    for (int i = n + gt; i < ld; i += kGroupThreads) row[i] = (TO)0;
   }
 }
 
@@ -232,7 +236,7 @@ __global__ __launch_bounds__(2 * kGroupThreads) void gradient_kernel(GradArgs a)
 // One information set (node v, hand h) of a bottom-up pass:
 //   g~_a = cA gA[v,a] + cB gB[v,a] + sum_{k in D(v,a)} V[k]
 //   smoothed (mu > 0, temp = mu beta_v):
-//     m = min_a g~_a,  w_a = exp(-(g~_a - m) / temp),  S = sum_a w_a
+//     m = min_a g~_a,  w_a = exp((m - g~_a) / temp),  S = sum_a w_a
 //     V[v] = m - temp log S + temp log n_v,  q_bar_a = w_a / S
 //   best response (mu = 0): V[v] = min_a g~_a.
 // The action with the smallest g~ has the largest q_bar (weight exactly 1), so
@@ -240,9 +244,11 @@ __global__ __launch_bounds__(2 * kGroupThreads) void gradient_kernel(GradArgs a)
 // every exponent is <= 0.  Tables are read through the accessor `T`, the
 // child values through `getV`, results go through `putV` / `putQ`.
 // ---------------------------------------------------------------------------
-template <class Tab, class GetV, class PutV, class PutQ>
+template <class TG, class Tab, class GetV, class PutV, class PutQ>
 __device__ __forceinline__ void node_pass(const TreePass& t, const Tab& T, int v, int h, size_t ld, GetV getV,
                                           PutV putV, PutQ putQ, bool want_q) {
+  const TG* gA = (const TG*)t.gA;
+  const TG* gB = (const TG*)t.gB;
   const int s0 = T.first(v);
   const int na = T.nact(v);
   double gt[kMaxActions];
@@ -251,8 +257,8 @@ __device__ __forceinline__ void node_pass(const TreePass& t, const Tab& T, int v
   for (int k = 0; k < kMaxActions; ++k) {
     if (k < na) {
       const int s = s0 + k;
-      double x = t.cA * t.gA[(size_t)s * ld + h];
-      if (t.gB) x += t.cB * t.gB[(size_t)s * ld + h];
+      double x = t.cA * (double)gA[(size_t)s * ld + h];
+      if (gB) x += t.cB * (double)gB[(size_t)s * ld + h];
       const int c1 = T.cbeg(s + 1);
       for (int c = T.cbeg(s); c < c1; ++c) x += getV(T.child(c));
       gt[k] = x;
@@ -264,19 +270,32 @@ __device__ __forceinline__ void node_pass(const TreePass& t, const Tab& T, int v
     return;
   }
   const double temp = t.mu * T.beta(v);
+  const double inv_temp = 1.0 / temp;
   double sum = 0.0;
+  if constexpr (std::is_same<TG, float>::value) {
+    // precision form: FP32 exponentials, FP64 normaliser and value
 #pragma unroll
-  for (int k = 0; k < kMaxActions; ++k) {
-    if (k < na) {
-      gt[k] = exp(-(gt[k] - m) / temp);
-      sum += gt[k];
+    for (int k = 0; k < kMaxActions; ++k) {
+      if (k < na) {
+        gt[k] = (double)expf((float)((m - gt[k]) * inv_temp));
+        sum += gt[k];
+      }
+    }
+  } else {
+#pragma unroll
+    for (int k = 0; k < kMaxActions; ++k) {
+      if (k < na) {
+        gt[k] = exp((m - gt[k]) * inv_temp);
+        sum += gt[k];
+      }
     }
   }
   putV(v, (m - temp * log(sum)) + temp * T.logn(v));
   if (want_q) {
+    const double inv_sum = 1.0 / sum;
 #pragma unroll
     for (int k = 0; k < kMaxActions; ++k)
-      if (k < na) putQ(s0 + k, gt[k] / sum);
+      if (k < na) putQ(s0 + k, (TG)(gt[k] * inv_sum));
   }
 }
 
@@ -306,12 +325,13 @@ struct LdsTab {
 };
 
 // ---------------------------------------------------------------------------
-// Fused pass for trees whose tables fit in LDS.  Block (16 hands, tree k):
-// stage the tree's tables, run every level bottom-up (node values and q_bar
-// of these hands stay in LDS; a block barrier separates the levels), write
-// the block's partial root sum (the tree value is a sum over (root, hand)),
-// then rebuild the sequence form top-down from q_bar and apply the epilogue.
-// Slots h >= n_hands (the row padding) write zeros.
+// Fused pass for trees whose tables fit in LDS.  Block (HB hands, tree k),
+// 64 node slots x HB hands: stage the tree's tables, run every level
+// bottom-up (node values and q_bar of these hands stay in LDS; a block
+// barrier separates the levels), write the block's partial root sum (the tree
+// value is a sum over (root, hand)), then rebuild the sequence form top-down
+// from q_bar and apply the epilogue.  Slots h >= n_hands (the row padding)
+// write zeros.
 // ---------------------------------------------------------------------------
 struct FusedArgs {
   PassSet ps;
@@ -320,15 +340,17 @@ struct FusedArgs {
   int cap_nodes, cap_seqs, cap_child;
 };
 
-__global__ __launch_bounds__(kFusedThreads) void sbr_fused_kernel(FusedArgs a) {
+template <int HB, class TG>
+__global__ __launch_bounds__(kFusedSlots * HB) void sbr_fused_kernel(FusedArgs a) {
+  constexpr int kThreads = kFusedSlots * HB;
   extern __shared__ double lds[];
   const int k = blockIdx.y;
   const TreePass& t = a.ps.t[k];
   const Epilogue& e = a.epi[k];
   const int N = t.P.n_nodes, S = t.P.n_seq, C = t.n_child;
-  double* Vl = lds;                                     // [cap_nodes][16]
-  double* Ql = Vl + (size_t)a.cap_nodes * kFusedHands;  // [cap_seqs][16]
-  double* beta = Ql + (size_t)a.cap_seqs * kFusedHands;
+  double* Vl = lds;                            // [cap_nodes][HB]
+  double* Ql = Vl + (size_t)a.cap_nodes * HB;  // [cap_seqs][HB]
+  double* beta = Ql + (size_t)a.cap_seqs * HB;
   double* logn = beta + a.cap_nodes;
   int* first = (int*)(logn + a.cap_nodes);
   int* nact = first + a.cap_nodes;
@@ -336,64 +358,69 @@ __global__ __launch_bounds__(kFusedThreads) void sbr_fused_kernel(FusedArgs a) {
   int* child = cbeg + a.cap_seqs + 1;
   int* spar = child + a.cap_child;
   const int tid = threadIdx.x;
-  for (int i = tid; i < N; i += kFusedThreads) {
+  for (int i = tid; i < N; i += kThreads) {
     first[i] = t.P.node_first_seq[i];
     nact[i] = t.P.node_nact[i];
     beta[i] = t.P.node_beta[i];
     logn[i] = t.P.node_logn[i];
   }
-  for (int i = tid; i <= S; i += kFusedThreads) cbeg[i] = t.P.child_begin[i];
-  for (int i = tid; i < C; i += kFusedThreads) child[i] = t.P.child[i];
-  for (int i = tid; i < S; i += kFusedThreads) spar[i] = t.P.seq_parent[i];
+  for (int i = tid; i <= S; i += kThreads) cbeg[i] = t.P.child_begin[i];
+  for (int i = tid; i < C; i += kThreads) child[i] = t.P.child[i];
+  for (int i = tid; i < S; i += kThreads) spar[i] = t.P.seq_parent[i];
   __syncthreads();
 
   const LdsTab T{first, nact, beta, logn, cbeg, child};
-  const int hl = tid % kFusedHands, slot = tid / kFusedHands;
-  const int h = blockIdx.x * kFusedHands + hl;
+  const int hl = tid % HB, slot = tid / HB;
+  const int h = blockIdx.x * HB + hl;
   const bool live = h < a.ps.n;
   const bool want_q = (e.q_out || e.comb_out) && t.mu > 0.0;
   const size_t ld = a.ps.ld;
-  auto getV = [&](int c) { return Vl[c * kFusedHands + hl]; };
-  auto putV = [&](int v, double x) { Vl[v * kFusedHands + hl] = x; };
-  auto putQ = [&](int s, double q) { Ql[s * kFusedHands + hl] = q; };
+  auto getV = [&](int c) { return Vl[c * HB + hl]; };
+  auto putV = [&](int v, double x) { Vl[v * HB + hl] = x; };
+  auto putQ = [&](int s, TG q) { Ql[s * HB + hl] = (double)q; };
   for (int l = 0; l < t.n_levels; ++l) {
     if (live)
       for (int v = t.level_begin[l] + slot; v < t.level_begin[l + 1]; v += kFusedSlots)
-        node_pass(t, T, v, h, ld, getV, putV, putQ, want_q);
+        node_pass<TG>(t, T, v, h, ld, getV, putV, putQ, want_q);
     __syncthreads();
   }
-  if (a.partial && tid < kFusedHands) {
+  if (a.partial && tid < HB) {
     double sv = 0.0;
     if (live)
-      for (int r = 0; r < t.P.n_roots; ++r) sv += Vl[t.P.roots[r] * kFusedHands + hl];
+      for (int r = 0; r < t.P.n_roots; ++r) sv += Vl[t.P.roots[r] * HB + hl];
 #pragma unroll
-    for (int off = kFusedHands / 2; off > 0; off >>= 1) sv += __shfl_down(sv, off, kFusedHands);
+    for (int off = HB / 2; off > 0; off >>= 1) sv += __shfl_down(sv, off, HB);
     if (tid == 0) a.partial[(size_t)k * gridDim.x + blockIdx.x] = sv;
   }
   if (e.q_out || e.comb_out) {
+    TG* q_out = (TG*)e.q_out;
+    TG* comb_out = (TG*)e.comb_out;
+    const TG* x_prev = (const TG*)e.x_prev;
+    const TG tau = (TG)e.tau, one_m_tau = (TG)(1.0 - e.tau);
     for (int s = slot; s < S; s += kFusedSlots) {
       const size_t idx = (size_t)s * ld + h;
       if (!live) {
-        if (e.q_out) e.q_out[idx] = 0.0;
-        if (e.comb_out) e.comb_out[idx] = 0.0;
+        if (q_out) q_out[idx] = (TG)0;
+        if (comb_out) comb_out[idx] = (TG)0;
         continue;
       }
       int depth = 0;
       for (int q = s; q >= 0; q = spar[q]) ++depth;
-      double val = 1.0;
+      TG val = (TG)1;
       for (int j = depth - 1; j >= 0; --j) {
         int q = s;
         for (int i = 0; i < j; ++i) q = spar[q];
-        val *= Ql[q * kFusedHands + hl];
+        val *= (TG)Ql[q * HB + hl];
       }
-      if (e.q_out) e.q_out[idx] = val;
-      if (e.comb_out) e.comb_out[idx] = (1.0 - e.tau) * e.x_prev[idx] + e.tau * val;
+      if (q_out) q_out[idx] = val;
+      if (comb_out) comb_out[idx] = one_m_tau * x_prev[idx] + tau * val;
     }
   }
 }
 
 // Large trees: one launch per level over all trees of the set; block = one
 // wavefront for (node, 64 hands); node values and q_bar in global memory.
+template <class TG>
 __global__ __launch_bounds__(kPassThreads) void bottom_up_level_kernel(PassSet a) {
   int y = blockIdx.y, k = 0;
   while (k < a.count - 1 && y >= a.level_cnt[k]) {
@@ -407,8 +434,8 @@ __global__ __launch_bounds__(kPassThreads) void bottom_up_level_kernel(PassSet a
   const GlobalTab T{t.P};
   auto getV = [&](int c) { return t.V[(size_t)c * ld + h]; };
   auto putV = [&](int v, double x) { t.V[(size_t)v * ld + h] = x; };
-  auto putQ = [&](int s, double q) { t.QB[(size_t)s * ld + h] = q; };
-  node_pass(t, T, t.level_begin[a.level] + y, h, ld, getV, putV, putQ, t.QB != nullptr);
+  auto putQ = [&](int s, TG q) { ((TG*)t.QB)[(size_t)s * ld + h] = q; };
+  node_pass<TG>(t, T, t.level_begin[a.level] + y, h, ld, getV, putV, putQ, t.QB != nullptr);
 }
 
 // Root sums of the level path: block k sums tree k, roots in order, hands
@@ -445,34 +472,39 @@ __global__ __launch_bounds__(64) void sum_partials_kernel(const double* partial,
 // ---------------------------------------------------------------------------
 struct DownArgs {
   const int* seq_parent;
-  const double* QB;
+  const void* QB;
   int n, ld;
-  double* q_out;
-  const double* x_prev;
+  void* q_out;
+  const void* x_prev;
   double tau;
-  double* comb_out;
+  void* comb_out;
 };
 
+template <class TS>
 __global__ __launch_bounds__(kPassThreads) void top_down_kernel(DownArgs a) {
+  const TS* QB = (const TS*)a.QB;
+  TS* q_out = (TS*)a.q_out;
+  TS* comb_out = (TS*)a.comb_out;
+  const TS* x_prev = (const TS*)a.x_prev;
   const int h = blockIdx.x * kPassThreads + threadIdx.x;
   const int s = blockIdx.y;
   if (h >= a.ld) return;
   const size_t idx = (size_t)s * a.ld + h;
   if (h >= a.n) {
-    if (a.q_out) a.q_out[idx] = 0.0;
-    if (a.comb_out) a.comb_out[idx] = 0.0;
+    if (q_out) q_out[idx] = (TS)0;
+    if (comb_out) comb_out[idx] = (TS)0;
     return;
   }
   int depth = 0;
   for (int q = s; q >= 0; q = a.seq_parent[q]) ++depth;
-  double val = 1.0;
+  TS val = (TS)1;
   for (int j = depth - 1; j >= 0; --j) {
     int q = s;
     for (int k = 0; k < j; ++k) q = a.seq_parent[q];
-    val *= a.QB[(size_t)q * a.ld + h];
+    val *= QB[(size_t)q * a.ld + h];
   }
-  if (a.q_out) a.q_out[idx] = val;
-  if (a.comb_out) a.comb_out[idx] = (1.0 - a.tau) * a.x_prev[idx] + a.tau * val;
+  if (q_out) q_out[idx] = val;
+  if (comb_out) comb_out[idx] = (TS)(1.0 - a.tau) * x_prev[idx] + (TS)a.tau * val;
 }
 
 struct UniformArgs {
@@ -506,11 +538,19 @@ __global__ __launch_bounds__(kRedThreads) void max_abs_kernel(int64_t count, con
   if (threadIdx.x == 0) out[0] = scratch[0];
 }
 
-__global__ __launch_bounds__(256) void axpby_kernel(int64_t count, double a, const double* X, double b,
-                                                    const double* Y, double* out) {
+template <class T>
+__global__ __launch_bounds__(256) void axpby_kernel(int64_t count, double a, const T* X, double b, const T* Y,
+                                                    T* out) {
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  const T ta = (T)a, tb = (T)b;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += stride)
-    out[i] = Y ? a * X[i] + b * Y[i] : a * X[i];
+    out[i] = Y ? ta * X[i] + tb * Y[i] : ta * X[i];
+}
+
+template <class TI, class TO>
+__global__ __launch_bounds__(256) void convert_kernel(int64_t count, const TI* in, TO* out) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += stride) out[i] = (TO)in[i];
 }
 
 }  // namespace
@@ -519,15 +559,17 @@ __global__ __launch_bounds__(256) void axpby_kernel(int64_t count, double a, con
 // Launchers
 // ---------------------------------------------------------------------------
 
-hipError_t launch_gradient(const egt_game* g, int player, const double* v_opp, double* grad_out,
-                           hipStream_t s) {
-  GradArgs a;
+template <class TV, class TO>
+static hipError_t gradient_launch(const egt_game* g, int player, const TV* v_opp, TO* grad_out, int fold_only,
+                                  hipStream_t s) {
+  GradArgs<TV, TO> a;
   a.own = g->dp[player];
   a.b_opp = g->dp[1 - player].belief;
   a.H = g->dh;
   a.v_opp = v_opp;
   a.out = grad_out;
   a.show_sign = player == 0 ? 1.0 : -1.0;
+  a.fold_only = fold_only;
   const int n_entries = g->dh.n_card_slots - g->dh.n_cards;  // hands x cards per hand
   const size_t per_group = sizeof(double) * (size_t)(g->n + 1 + g->dh.n_card_slots);
   const size_t shared_ints = sizeof(int) * (size_t)(g->dh.n_cards + 1 + n_entries);
@@ -535,8 +577,18 @@ hipError_t launch_gradient(const egt_game* g, int player, const double* v_opp, d
   if (groups == 2 && 2 * per_group + shared_ints > kGradLdsLimit) groups = 1;
   a.groups = groups;
   const size_t lds = groups * per_group + shared_ints;
-  hipLaunchKernelGGL(gradient_kernel, dim3(g->dp[player].n_seq), dim3(kGroupThreads * groups), lds, s, a);
+  hipLaunchKernelGGL((gradient_kernel<TV, TO>), dim3(g->dp[player].n_seq), dim3(kGroupThreads * groups), lds, s, a);
   return hipGetLastError();
+}
+
+hipError_t launch_gradient(const egt_game* g, int player, const double* v_opp, double* grad_out,
+                           hipStream_t s) {
+  return gradient_launch<double, double>(g, player, v_opp, grad_out, 0, s);
+}
+
+hipError_t launch_gradient_fold_f32(const egt_game* g, int player, const float* v_opp, float* grad_out,
+                                    hipStream_t s) {
+  return gradient_launch<float, float>(g, player, v_opp, grad_out, 1, s);
 }
 
 static void fill_pass_set(const egt_game* g, const Pass* p, int count, PassSet& a) {
@@ -566,16 +618,16 @@ static void fill_pass_set(const egt_game* g, const Pass* p, int count, PassSet& 
   }
 }
 
-int n_partials(const egt_game* g) { return g->fused_passes ? g->ld / kFusedHands : 1; }
+int n_partials(const egt_game* g) { return g->fused_passes ? g->ld / g->fused_hands : 1; }
 
-size_t fused_lds_bytes(int cap_nodes, int cap_seqs, int cap_child) {
-  return sizeof(double) * ((size_t)(cap_nodes + cap_seqs) * kFusedHands + 2 * (size_t)cap_nodes) +
+size_t fused_lds_bytes(int hands, int cap_nodes, int cap_seqs, int cap_child) {
+  return sizeof(double) * ((size_t)(cap_nodes + cap_seqs) * hands + 2 * (size_t)cap_nodes) +
          sizeof(int) * (2 * (size_t)cap_nodes + (cap_seqs + 1) + cap_child + cap_seqs);
 }
 
-hipError_t launch_passes(const egt_game* g, const Pass* p, int count, const Epilogue* epi, double* partial,
-                         hipStream_t s) {
-  if (count < 1 || count > kMaxTrees) return hipErrorInvalidValue;
+template <class TG>
+static hipError_t passes_launch(const egt_game* g, const Pass* p, int count, const Epilogue* epi, double* partial,
+                                hipStream_t s) {
   if (g->fused_passes) {
     FusedArgs a;
     fill_pass_set(g, p, count, a.ps);
@@ -585,8 +637,13 @@ hipError_t launch_passes(const egt_game* g, const Pass* p, int count, const Epil
     a.cap_nodes = std::max(g->hp[0].n_nodes, g->hp[1].n_nodes);
     a.cap_seqs = std::max(g->hp[0].n_seq, g->hp[1].n_seq);
     a.cap_child = std::max((int)g->hp[0].child.size(), (int)g->hp[1].child.size());
-    const size_t lds = fused_lds_bytes(a.cap_nodes, a.cap_seqs, a.cap_child);
-    hipLaunchKernelGGL(sbr_fused_kernel, dim3(g->ld / kFusedHands, count), dim3(kFusedThreads), lds, s, a);
+    const int hb = g->fused_hands;
+    const size_t lds = fused_lds_bytes(hb, a.cap_nodes, a.cap_seqs, a.cap_child);
+    const dim3 grid(g->ld / hb, count);
+    if (hb == 4)
+      hipLaunchKernelGGL((sbr_fused_kernel<4, TG>), grid, dim3(kFusedSlots * 4), lds, s, a);
+    else
+      hipLaunchKernelGGL((sbr_fused_kernel<16, TG>), grid, dim3(kFusedSlots * 16), lds, s, a);
     return hipGetLastError();
   }
   PassSet a;
@@ -605,7 +662,7 @@ hipError_t launch_passes(const egt_game* g, const Pass* p, int count, const Epil
     }
     if (total == 0) continue;
     a.level = l;
-    hipLaunchKernelGGL(bottom_up_level_kernel, dim3(bx, total), dim3(kPassThreads), 0, s, a);
+    hipLaunchKernelGGL(bottom_up_level_kernel<TG>, dim3(bx, total), dim3(kPassThreads), 0, s, a);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
@@ -617,10 +674,17 @@ hipError_t launch_passes(const egt_game* g, const Pass* p, int count, const Epil
   for (int k = 0; epi && k < count; ++k) {
     if (!epi[k].q_out && !epi[k].comb_out) continue;
     const hipError_t e = launch_top_down(g, p[k].player, p[k].QB, epi[k].q_out, epi[k].x_prev, epi[k].tau,
-                                         epi[k].comb_out, s);
+                                         epi[k].comb_out, s, std::is_same<TG, float>::value ? kF32 : kF64);
     if (e != hipSuccess) return e;
   }
   return hipSuccess;
+}
+
+hipError_t launch_passes(const egt_game* g, const Pass* p, int count, const Epilogue* epi, double* partial,
+                         hipStream_t s, Prec prec) {
+  if (count < 1 || count > kMaxTrees) return hipErrorInvalidValue;
+  return prec == kF32 ? passes_launch<float>(g, p, count, epi, partial, s)
+                      : passes_launch<double>(g, p, count, epi, partial, s);
 }
 
 hipError_t launch_sum_partials(const egt_game* g, const double* partial, int count, double* out, hipStream_t s) {
@@ -628,8 +692,8 @@ hipError_t launch_sum_partials(const egt_game* g, const double* partial, int cou
   return hipGetLastError();
 }
 
-hipError_t launch_top_down(const egt_game* g, int player, const double* QB, double* q_out,
-                           const double* x_prev, double tau, double* comb_out, hipStream_t s) {
+hipError_t launch_top_down(const egt_game* g, int player, const void* QB, void* q_out, const void* x_prev,
+                           double tau, void* comb_out, hipStream_t s, Prec prec) {
   DownArgs a;
   a.seq_parent = g->dp[player].seq_parent;
   a.QB = QB;
@@ -639,8 +703,11 @@ hipError_t launch_top_down(const egt_game* g, int player, const double* QB, doub
   a.x_prev = x_prev;
   a.tau = tau;
   a.comb_out = comb_out;
-  const unsigned bx = (unsigned)((g->ld + kPassThreads - 1) / kPassThreads);
-  hipLaunchKernelGGL(top_down_kernel, dim3(bx, g->dp[player].n_seq), dim3(kPassThreads), 0, s, a);
+  const dim3 grid((unsigned)((g->ld + kPassThreads - 1) / kPassThreads), g->dp[player].n_seq);
+  if (prec == kF32)
+    hipLaunchKernelGGL(top_down_kernel<float>, grid, dim3(kPassThreads), 0, s, a);
+  else
+    hipLaunchKernelGGL(top_down_kernel<double>, grid, dim3(kPassThreads), 0, s, a);
   return hipGetLastError();
 }
 
@@ -656,11 +723,28 @@ hipError_t launch_uniform_qbar(const egt_game* g, int player, double* QB, hipStr
   return hipGetLastError();
 }
 
-hipError_t launch_axpby(int64_t count, double a, const double* X, double b, const double* Y,
-                        double* out, hipStream_t s) {
+hipError_t launch_axpby(int64_t count, double a, const void* X, double b, const void* Y, void* out, hipStream_t s,
+                        Prec prec) {
   if (count <= 0) return hipSuccess;
-  const int64_t blocks = std::min<int64_t>((count + 255) / 256, 4096);
-  hipLaunchKernelGGL(axpby_kernel, dim3((unsigned)blocks), dim3(256), 0, s, count, a, X, b, Y, out);
+  const unsigned blocks = (unsigned)std::min<int64_t>((count + 255) / 256, 4096);
+  if (prec == kF32)
+    hipLaunchKernelGGL(axpby_kernel<float>, dim3(blocks), dim3(256), 0, s, count, a, (const float*)X, b,
+                       (const float*)Y, (float*)out);
+  else
+    hipLaunchKernelGGL(axpby_kernel<double>, dim3(blocks), dim3(256), 0, s, count, a, (const double*)X, b,
+                       (const double*)Y, (double*)out);
+  return hipGetLastError();
+}
+
+hipError_t launch_convert(int64_t count, const void* in, Prec in_prec, void* out, hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  const unsigned blocks = (unsigned)std::min<int64_t>((count + 255) / 256, 4096);
+  if (in_prec == kF32)
+    hipLaunchKernelGGL((convert_kernel<float, double>), dim3(blocks), dim3(256), 0, s, count, (const float*)in,
+                       (double*)out);
+  else
+    hipLaunchKernelGGL((convert_kernel<double, float>), dim3(blocks), dim3(256), 0, s, count, (const double*)in,
+                       (float*)out);
   return hipGetLastError();
 }
 

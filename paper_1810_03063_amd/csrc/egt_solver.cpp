@@ -2,7 +2,8 @@
 // Decr of Algorithm 4 and the side selection of Algorithms 1 and 3 (alternate,
 // or the player with the larger mu).  Scalars (mu, tau, the EGV sign test) are
 // FP64 on the host; one small device->host copy per step attempt carries the
-// excessive gap value and the saddle gap of the candidate point.
+// root partial sums of the excessive gap value (and, in FP64, of the
+// candidate's saddle gap).
 //
 // Notation.  G[0] = A y and G[1] = A^T x at the current iterate.  Player p
 // minimises <q, sg[p] G[p]> with sg = (+1, -1): the y-focused step is the
@@ -21,6 +22,10 @@
 //   EGV   = V_p(sg ((1-tau) G[p] + tau T1[p]), mu_p+) + V_o(sg T2[o], mu_o)
 // (grad_p at y_+ follows by linearity).  On EGV < 0 (EGT/as) tau halves and the
 // step restarts from x_hat, reusing x_bar.
+//
+// Precision form: iterates, products and q_bar are FP32, the showdown products
+// run on the BF16 matrix cores, node values and normalisers stay FP64, and the
+// saddle gap is always measured with FP64 products of the (widened) iterates.
 #include <algorithm>
 #include <chrono>
 #include <cmath>
@@ -29,34 +34,47 @@
 
 #include "egt_internal.h"
 
+using egt::Prec;
+
 struct egt_state {
   const egt_game* g = nullptr;
   egt_solve_opts opts{};
+  Prec prec = egt::kF64;
+  size_t esz = sizeof(double);
   double mu[2] = {0, 0};
   double tau = 0.5;
   int64_t t = 0;
   int64_t products = 0;
   int64_t backtracks = 0;
-  // device buffers, each [n_seq(p)][ld] (V: [n_nodes(p)][ld])
-  double* X[2] = {};
-  double* Xn[2] = {};
-  double* Xbar[2] = {};
-  double* Xhat[2] = {};
-  double* G[2] = {};
-  double* T1[2] = {};
-  double* T2[2] = {};
-  double* QB[2] = {};
-  double* V[2] = {};
+  // iterates and products in the state's precision, each [n_seq(p)][ld]
+  void* X[2] = {};
+  void* Xn[2] = {};
+  void* Xbar[2] = {};
+  void* Xhat[2] = {};
+  void* G[2] = {};
+  void* T1[2] = {};
+  void* T2[2] = {};
+  void* QB[2] = {};
+  double* V[2] = {};        // node values [n_nodes(p)][ld], FP64
   double* Vb[2] = {};       // node values of the best-response passes
+  double* X64[2] = {};      // FP64 iterates for the gap (precision form; else scratch aliases)
+  double* G64[2] = {};      // FP64 products for the gap (precision form; else scratch aliases)
+  double* S64 = nullptr;    // FP64 q_bar scratch of the start-up (precision form)
   double* dscal = nullptr;  // device scalars
   double* hscal = nullptr;  // pinned host mirror (also the summed tree values)
   double* dpart = nullptr;  // device root partial sums [trees][n_partials]
   double* hpart = nullptr;  // pinned host mirror
   void* block = nullptr;
-  // last saddle gap of the current iterate (valid when gap_valid)
+  // saddle gap of the current iterate (valid when gap_valid)
   bool gap_valid = false;
   double gap = 0, br_max_y = 0, br_min_x = 0;
   double last_egv = 0;
+  // split launch / finish interface: the iteration in progress and the
+  // value copy awaiting its finish
+  bool step_open = false;
+  int step_p = 0;
+  double step_tau = 0;
+  int pending_trees = 0;
 };
 
 namespace egt {
@@ -77,26 +95,43 @@ int64_t vec_elems(const egt_game* g, int p) { return (int64_t)g->hp[p].n_seq * g
 
 // Smoothed best response of player p to cA gA + cB gB: q to q_out and the
 // epilogue (1 - tau) x_prev + tau q to comb_out (either may be null).
-int sbr(egt_state* st, int p, const double* gA, double cA, const double* gB, double cB, double mu,
-        double* q_out, const double* x_prev, double tau, double* comb_out, hipStream_t s) {
+int sbr(egt_state* st, int p, const void* gA, double cA, const void* gB, double cB, double mu, void* q_out,
+        const void* x_prev, double tau, void* comb_out, hipStream_t s) {
   const Pass ps{p, gA, cA, gB, cB, mu, st->V[p], st->QB[p]};
   const Epilogue e{q_out, x_prev, tau, comb_out};
-  EGT_TRY(launch_passes(st->g, &ps, 1, &e, nullptr, s));
+  EGT_TRY(launch_passes(st->g, &ps, 1, &e, nullptr, s, st->prec));
   return EGT_OK;
 }
 
-int grad(egt_state* st, int p, const double* v_opp, double* out, hipStream_t s) {
+// Product of player p's gradient at the opponent's strategy, in the state's precision.
+int grad(egt_state* st, int p, const void* v_opp, void* out, hipStream_t s) {
   st->products++;
-  EGT_TRY(launch_gradient(st->g, p, v_opp, out, s));
+  if (st->prec == kF64)
+    EGT_TRY(launch_gradient(st->g, p, (const double*)v_opp, (double*)out, s));
+  else
+    EGT_TRY(launch_gradient_mixed(st->g, p, (const float*)v_opp, (float*)out, s));
   return EGT_OK;
 }
 
-// Copies the root partial sums of `trees` trees to the host and adds each
-// tree's partials in order into hscal[k].
-int fetch_values(egt_state* st, int trees, hipStream_t s) {
+int axpby(egt_state* st, int p, double a, const void* X, double b, const void* Y, void* out, hipStream_t s) {
+  EGT_TRY(launch_axpby(vec_elems(st->g, p), a, X, b, Y, out, s, st->prec));
+  return EGT_OK;
+}
+
+// Enqueues the copy of the root partial sums of `trees` trees to the host.
+int enqueue_values(egt_state* st, int trees, hipStream_t s) {
   const int nb = n_partials(st->g);
   EGT_TRY(hipMemcpyAsync(st->hpart, st->dpart, sizeof(double) * trees * nb, hipMemcpyDeviceToHost, s));
+  st->pending_trees = trees;
+  return EGT_OK;
+}
+
+// Waits for the enqueued copy and adds each tree's partials in order into hscal[k].
+int finish_values(egt_state* st, hipStream_t s) {
   EGT_TRY(hipStreamSynchronize(s));
+  const int nb = n_partials(st->g);
+  const int trees = st->pending_trees;
+  st->pending_trees = 0;
   for (int k = 0; k < trees; ++k) {
     double v = 0.0;
     for (int b = 0; b < nb; ++b) v += st->hpart[k * nb + b];
@@ -104,6 +139,11 @@ int fetch_values(egt_state* st, int trees, hipStream_t s) {
     st->hscal[k] = v;
   }
   return EGT_OK;
+}
+
+int fetch_values(egt_state* st, int trees, hipStream_t s) {
+  int rc = enqueue_values(st, trees, s);
+  return rc ? rc : finish_values(st, s);
 }
 
 int fetch(egt_state* st, int count, hipStream_t s) {
@@ -114,12 +154,11 @@ int fetch(egt_state* st, int count, hipStream_t s) {
   return EGT_OK;
 }
 
-// EGV at (X, Y) with the state's G and mu -> hscal[0] + hscal[1] after fetch_values.
+// EGV at (X, Y) with the state's G and mu: root partials of the two trees.
 int egv_current(egt_state* st, hipStream_t s) {
-  const egt_game* g = st->g;
   const Pass ps[2] = {{0, st->G[0], kSg[0], nullptr, 0.0, st->mu[0], st->V[0], nullptr},
                       {1, st->G[1], kSg[1], nullptr, 0.0, st->mu[1], st->V[1], nullptr}};
-  EGT_TRY(launch_passes(g, ps, 2, nullptr, st->dpart, s));
+  EGT_TRY(launch_passes(st->g, ps, 2, nullptr, st->dpart, s, st->prec));
   return EGT_OK;
 }
 
@@ -127,13 +166,13 @@ int egv_current(egt_state* st, hipStream_t s) {
 // are A y = cXA gXA + cXB gXB and A^T x = cYA gYA + cYB gYB (gXB / gYB may be
 // null): tree values BR_x(A y) and BR_y(-A^T x), so that
 // gap = -BR_y - BR_x = max_y x^T A y - min_x x^T A y.
-void gap_passes(egt_state* st, const double* gXA, double cXA, const double* gXB, double cXB, const double* gYA,
-                double cYA, const double* gYB, double cYB, Pass out[2]) {
+void gap_passes(egt_state* st, const void* gXA, double cXA, const void* gXB, double cXB, const void* gYA,
+                double cYA, const void* gYB, double cYB, Pass out[2]) {
   out[0] = Pass{0, gXA, kSg[0] * cXA, gXB, kSg[0] * cXB, 0.0, st->Vb[0], nullptr};
   out[1] = Pass{1, gYA, kSg[1] * cYA, gYB, kSg[1] * cYB, 0.0, st->Vb[1], nullptr};
 }
 
-int init_point(egt_state* st, const double* atx_omega, hipStream_t s) {
+int init_point(egt_state* st, const void* atx_omega, hipStream_t s) {
   // y0 = y_{mu_y}(x_omega) = SBR_y(-A^T x_omega); x0 = x_{mu_x}(y0) = SBR_x(A y0)
   int rc;
   if ((rc = sbr(st, 1, atx_omega, kSg[1], nullptr, 0.0, st->mu[1], st->X[1], nullptr, 0.0, nullptr, s))) return rc;
@@ -143,7 +182,28 @@ int init_point(egt_state* st, const double* atx_omega, hipStream_t s) {
   return EGT_OK;
 }
 
+// FP64 copy of a state-precision vector into dst (a plain copy in FP64).
+int widen(egt_state* st, int p, const void* src, double* dst, hipStream_t s) {
+  if (st->prec == kF64) {
+    if (src != dst)
+      EGT_TRY(hipMemcpyAsync(dst, src, sizeof(double) * vec_elems(st->g, p), hipMemcpyDeviceToDevice, s));
+  } else {
+    EGT_TRY(launch_convert(vec_elems(st->g, p), src, kF32, dst, s));
+  }
+  return EGT_OK;
+}
+
+int narrow(egt_state* st, int p, const double* src, void* dst, hipStream_t s) {
+  if (st->prec == kF64)
+    EGT_TRY(hipMemcpyAsync(dst, src, sizeof(double) * vec_elems(st->g, p), hipMemcpyDeviceToDevice, s));
+  else
+    EGT_TRY(launch_convert(vec_elems(st->g, p), src, kF64, dst, s));
+  return EGT_OK;
+}
+
 }  // namespace
+
+int64_t state_bytes(const egt_game* g, bool mixed);
 
 int state_create(const egt_game* g, const egt_solve_opts* o, hipStream_t s, egt_state** out) {
   if (!g || !out) return fail(EGT_EINVAL, "null argument");
@@ -153,7 +213,8 @@ int state_create(const egt_game* g, const egt_solve_opts* o, hipStream_t s, egt_
   if (o) opts = *o;
   if (opts.variant < EGT_VARIANT_ALT || opts.variant > EGT_VARIANT_AS)
     return fail(EGT_EINVAL, "unknown variant");
-  if (opts.precision != EGT_PRECISION_FP64) return fail(EGT_EINVAL, "this state supports FP64 only");
+  if (opts.precision != EGT_PRECISION_FP64 && opts.precision != EGT_PRECISION_MIXED)
+    return fail(EGT_EINVAL, "unknown precision");
   if (opts.eps <= 0) opts.eps = 1e-3 * g->pot;
   if (opts.tau0 <= 0) opts.tau0 = 0.5;
   if (!(opts.tau0 < 1.0)) return fail(EGT_EINVAL, "tau0 must be < 1");
@@ -163,6 +224,11 @@ int state_create(const egt_game* g, const egt_solve_opts* o, hipStream_t s, egt_
   if (!auto_mu && (!(opts.mu0_x > 0) || !(opts.mu0_y > 0) || !std::isfinite(opts.mu0_x) ||
                    !std::isfinite(opts.mu0_y)))
     return fail(EGT_EINVAL, "mu0_x and mu0_y must both be > 0 (or both <= 0 for automatic)");
+  const bool mixed = opts.precision == EGT_PRECISION_MIXED;
+  if (mixed) {
+    const int rc = ensure_mixed_tables(g);
+    if (rc) return rc;
+  }
 
   egt_state* st = new (std::nothrow) egt_state();
   if (!st) return fail(EGT_ENOMEM, "host allocation failed");
@@ -172,56 +238,76 @@ int state_create(const egt_game* g, const egt_solve_opts* o, hipStream_t s, egt_
   st->g = g;
   st->opts = opts;
   st->tau = opts.tau0;
-  size_t bytes = 0;
-  for (int p = 0; p < 2; ++p)
-    bytes += sizeof(double) * (8 * (size_t)vec_elems(g, p) + 2 * (size_t)g->hp[p].n_nodes * g->ld);
-  bytes += (64 + (size_t)kMaxTrees * kMaxPartials) * sizeof(double);
+  st->prec = mixed ? kF32 : kF64;
+  st->esz = mixed ? sizeof(float) : sizeof(double);
+  const size_t bytes = (size_t)state_bytes(g, mixed);
   hipError_t e = hipMalloc(&st->block, bytes);
   if (e != hipSuccess) return fail(EGT_ENOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
   e = hipHostMalloc((void**)&st->hscal, (64 + (size_t)kMaxTrees * kMaxPartials) * sizeof(double),
                     hipHostMallocDefault);
   if (e != hipSuccess) return fail(EGT_ENOMEM, std::string("hipHostMalloc: ") + hipGetErrorString(e));
   st->hpart = st->hscal + 64;
-  double* cur = (double*)st->block;
-  auto take = [&](int64_t n) {
-    double* r = cur;
-    cur += n;
+  unsigned char* cur = (unsigned char*)st->block;
+  auto take = [&](size_t nbytes) {
+    void* r = cur;
+    cur += (nbytes + 255) / 256 * 256;
     return r;
   };
   for (int p = 0; p < 2; ++p) {
-    const int64_t n = vec_elems(g, p);
-    st->X[p] = take(n);
-    st->Xn[p] = take(n);
-    st->Xbar[p] = take(n);
-    st->Xhat[p] = take(n);
-    st->G[p] = take(n);
-    st->T1[p] = take(n);
-    st->T2[p] = take(n);
-    st->QB[p] = take(n);
-    st->V[p] = take((int64_t)g->hp[p].n_nodes * g->ld);
-    st->Vb[p] = take((int64_t)g->hp[p].n_nodes * g->ld);
+    const size_t vb = st->esz * (size_t)vec_elems(g, p);
+    st->X[p] = take(vb);
+    st->Xn[p] = take(vb);
+    st->Xbar[p] = take(vb);
+    st->Xhat[p] = take(vb);
+    st->G[p] = take(vb);
+    st->T1[p] = take(vb);
+    st->T2[p] = take(vb);
+    st->QB[p] = take(vb);
+    st->V[p] = (double*)take(sizeof(double) * (size_t)g->hp[p].n_nodes * g->ld);
+    st->Vb[p] = (double*)take(sizeof(double) * (size_t)g->hp[p].n_nodes * g->ld);
+    if (mixed) {
+      st->X64[p] = (double*)take(sizeof(double) * (size_t)vec_elems(g, p));
+      st->G64[p] = (double*)take(sizeof(double) * (size_t)vec_elems(g, p));
+    }
   }
-  st->dscal = take(64);
-  st->dpart = take((int64_t)kMaxTrees * kMaxPartials);
+  if (mixed) {
+    st->S64 = (double*)take(sizeof(double) * (size_t)std::max(vec_elems(g, 0), vec_elems(g, 1)));
+  } else {  // FP64: the start-up scratch lives in buffers that are free then
+    for (int p = 0; p < 2; ++p) {
+      st->X64[p] = (double*)st->Xbar[p];
+      st->G64[p] = (double*)st->Xhat[p];
+    }
+  }
+  // FP64 q_bar scratch of player p during the start-up
+  auto qscratch = [&](int p) { return mixed ? st->S64 : (double*)st->T1[p]; };
+  st->dscal = (double*)take(64 * sizeof(double));
+  st->dpart = (double*)take((size_t)kMaxTrees * kMaxPartials * sizeof(double));
   EGT_HIP(hipMemsetAsync(st->block, 0, bytes, s));
 
-  // x_omega and A^T x_omega (kept in T2[1] for the mu search)
+  // x_omega and A^T x_omega with the FP64 operator: the start of Algorithms 1/3
   int rc;
-  EGT_TRY(launch_uniform_qbar(g, 0, st->QB[0], s));
-  EGT_TRY(launch_top_down(g, 0, st->QB[0], st->Xbar[0], nullptr, 0.0, nullptr, s));
-  if ((rc = grad(st, 1, st->Xbar[0], st->T2[1], s))) return rc;
+  EGT_TRY(launch_uniform_qbar(g, 0, qscratch(0), s));
+  EGT_TRY(launch_top_down(g, 0, qscratch(0), st->X64[0], nullptr, 0.0, nullptr, s));
+  EGT_TRY(launch_gradient(g, 1, st->X64[0], st->G64[1], s));
   if (auto_mu) {
     // mu0 = 1e-3 max(|A y_omega|_inf, |A^T x_omega|_inf) / max beta, then double
     // both until the excessive gap condition holds at (x0, y0).
-    EGT_TRY(launch_uniform_qbar(g, 1, st->QB[1], s));
-    EGT_TRY(launch_top_down(g, 1, st->QB[1], st->Xbar[1], nullptr, 0.0, nullptr, s));
-    if ((rc = grad(st, 0, st->Xbar[1], st->T2[0], s))) return rc;
-    EGT_TRY(launch_max_abs(vec_elems(g, 0), st->T2[0], st->dscal, s));
-    EGT_TRY(launch_max_abs(vec_elems(g, 1), st->T2[1], st->dscal + 1, s));
+    EGT_TRY(launch_uniform_qbar(g, 1, qscratch(1), s));
+    EGT_TRY(launch_top_down(g, 1, qscratch(1), st->X64[1], nullptr, 0.0, nullptr, s));
+    EGT_TRY(launch_gradient(g, 0, st->X64[1], st->G64[0], s));
+    EGT_TRY(launch_max_abs(vec_elems(g, 0), st->G64[0], st->dscal, s));
+    EGT_TRY(launch_max_abs(vec_elems(g, 1), st->G64[1], st->dscal + 1, s));
     if ((rc = fetch(st, 2, s))) return rc;
     const double m0 = 1e-3 * std::max(st->hscal[0], st->hscal[1]) / g->max_beta;
     if (!(m0 > 0)) return fail(EGT_ENUMERIC, "automatic mu is zero (all-zero payoffs?)");
     st->mu[0] = st->mu[1] = m0;
+  } else {
+    st->mu[0] = opts.mu0_x;
+    st->mu[1] = opts.mu0_y;
+  }
+  // A^T x_omega in the state's precision, kept in T2[1] during the mu search
+  if ((rc = narrow(st, 1, st->G64[1], st->T2[1], s))) return rc;
+  if (auto_mu) {
     for (int k = 0;; ++k) {
       if ((rc = init_point(st, st->T2[1], s))) return rc;
       if ((rc = egv_current(st, s))) return rc;
@@ -232,8 +318,6 @@ int state_create(const egt_game* g, const egt_solve_opts* o, hipStream_t s, egt_
       st->mu[1] *= 2.0;
     }
   } else {
-    st->mu[0] = opts.mu0_x;
-    st->mu[1] = opts.mu0_y;
     if ((rc = init_point(st, st->T2[1], s))) return rc;
     EGT_HIP(hipStreamSynchronize(s));
   }
@@ -255,19 +339,43 @@ int state_destroy(egt_state* st) {
   return rc;
 }
 
-int state_gap(egt_state* st, double* gap, double* brmax, double* brmin, hipStream_t s) {
+// Enqueues the saddle-gap evaluation of the current iterate (nothing when it
+// is already known); gap_finish completes it.
+int gap_launch(egt_state* st, hipStream_t s) {
   if (!st) return fail(EGT_EINVAL, "null state");
-  if (!st->gap_valid) {
-    int rc;
-    Pass ps[2];
+  if (st->gap_valid) return EGT_OK;
+  int rc;
+  Pass ps[2];
+  if (st->prec == kF64) {
     gap_passes(st, st->G[0], 1.0, nullptr, 0.0, st->G[1], 1.0, nullptr, 0.0, ps);
-    EGT_TRY(launch_passes(st->g, ps, 2, nullptr, st->dpart, s));
-    if ((rc = fetch_values(st, 2, s))) return rc;
-    st->br_min_x = st->hscal[0];
-    st->br_max_y = -st->hscal[1];
-    st->gap = -st->hscal[1] - st->hscal[0];
-    st->gap_valid = true;
+  } else {
+    // always FP64: widen the iterates, FP64 products, FP64 best responses
+    if ((rc = widen(st, 0, st->X[0], st->X64[0], s))) return rc;
+    if ((rc = widen(st, 1, st->X[1], st->X64[1], s))) return rc;
+    EGT_TRY(launch_gradient(st->g, 0, st->X64[1], st->G64[0], s));
+    EGT_TRY(launch_gradient(st->g, 1, st->X64[0], st->G64[1], s));
+    gap_passes(st, st->G64[0], 1.0, nullptr, 0.0, st->G64[1], 1.0, nullptr, 0.0, ps);
   }
+  EGT_TRY(launch_passes(st->g, ps, 2, nullptr, st->dpart, s, kF64));
+  return enqueue_values(st, 2, s);
+}
+
+int gap_finish(egt_state* st, hipStream_t s) {
+  if (!st) return fail(EGT_EINVAL, "null state");
+  if (st->gap_valid) return EGT_OK;
+  int rc;
+  if ((rc = finish_values(st, s))) return rc;
+  st->br_min_x = st->hscal[0];
+  st->br_max_y = -st->hscal[1];
+  st->gap = -st->hscal[1] - st->hscal[0];
+  st->gap_valid = true;
+  return EGT_OK;
+}
+
+int state_gap(egt_state* st, double* gap, double* brmax, double* brmin, hipStream_t s) {
+  int rc;
+  if ((rc = gap_launch(st, s))) return rc;
+  if ((rc = gap_finish(st, s))) return rc;
   if (gap) *gap = st->gap;
   if (brmax) *brmax = st->br_max_y;
   if (brmin) *brmin = st->br_min_x;
@@ -275,18 +383,17 @@ int state_gap(egt_state* st, double* gap, double* brmax, double* brmin, hipStrea
 }
 
 // One attempt of the step focused on p at step size tau.  first = compute
-// x_bar (otherwise reuse it).  Leaves the two EGV terms and the two
-// best-response values of the candidate's saddle gap as root partials (dpart).
+// x_bar (otherwise reuse it).  Leaves the two EGV terms (and in FP64 the two
+// best-response values of the candidate's saddle gap) as root partials.
 static int attempt(egt_state* st, int p, double tau, bool first, hipStream_t s) {
   const egt_game* g = st->g;
   const int o = 1 - p;
   int rc;
   if (first) {
-    if ((rc = sbr(st, p, st->G[p], kSg[p], nullptr, 0.0, st->mu[p], st->Xbar[p], st->X[p], tau,
-                  st->Xhat[p], s)))
+    if ((rc = sbr(st, p, st->G[p], kSg[p], nullptr, 0.0, st->mu[p], st->Xbar[p], st->X[p], tau, st->Xhat[p], s)))
       return rc;
   } else {
-    EGT_TRY(launch_axpby(vec_elems(g, p), 1.0 - tau, st->X[p], tau, st->Xbar[p], st->Xhat[p], s));
+    if ((rc = axpby(st, p, 1.0 - tau, st->X[p], tau, st->Xbar[p], st->Xhat[p], s))) return rc;
   }
   if ((rc = grad(st, o, st->Xhat[p], st->T1[o], s))) return rc;
   if ((rc = sbr(st, o, st->T1[o], kSg[o], nullptr, 0.0, st->mu[o], st->Xbar[o], st->X[o], tau, st->Xn[o], s)))
@@ -297,75 +404,117 @@ static int attempt(egt_state* st, int p, double tau, bool first, hipStream_t s) 
     return rc;
   if ((rc = grad(st, o, st->Xn[p], st->T2[o], s))) return rc;
   const double mu_new = (1.0 - tau) * st->mu[p];
-  // one launch for the four value passes: EGV at (x_+, y_+) with mu_p+ and the
-  // unchanged mu_o, and the two best responses of the candidate's saddle gap
+  // one launch for the value passes: EGV at (x_+, y_+) with mu_p+ and the
+  // unchanged mu_o, and (FP64) the two best responses of the candidate's gap
   Pass ps[4];
   ps[0] = Pass{p, st->G[p], kSg[p] * (1.0 - tau), st->T1[p], kSg[p] * tau, mu_new, st->V[p], nullptr};
   ps[1] = Pass{o, st->T2[o], kSg[o], nullptr, 0.0, st->mu[o], st->V[o], nullptr};
-  if (p == 0)
-    gap_passes(st, st->G[0], 1.0 - tau, st->T1[0], tau, st->T2[1], 1.0, nullptr, 0.0, ps + 2);
-  else
-    gap_passes(st, st->T2[0], 1.0, nullptr, 0.0, st->G[1], 1.0 - tau, st->T1[1], tau, ps + 2);
-  EGT_TRY(launch_passes(g, ps, 4, nullptr, st->dpart, s));
+  int trees = 2;
+  if (st->prec == kF64) {
+    if (p == 0)
+      gap_passes(st, st->G[0], 1.0 - tau, st->T1[0], tau, st->T2[1], 1.0, nullptr, 0.0, ps + 2);
+    else
+      gap_passes(st, st->T2[0], 1.0, nullptr, 0.0, st->G[1], 1.0 - tau, st->T1[1], tau, ps + 2);
+    trees = 4;
+  }
+  EGT_TRY(launch_passes(g, ps, trees, nullptr, st->dpart, s, st->prec));
   return EGT_OK;
 }
 
-int state_step(egt_state* st, int player, double* egv_out, int* stepped, hipStream_t s) {
+// Enqueues the next attempt of the current iteration, opening one (side and
+// tau from the variant, or `player`) if none is open; step_finish completes it.
+int step_launch(egt_state* st, int player, hipStream_t s) {
   if (!st) return fail(EGT_EINVAL, "null state");
   if (player < -1 || player > 1) return fail(EGT_EINVAL, "player must be -1, 0 or 1");
-  const egt_game* g = st->g;
-  const int variant = st->opts.variant;
-  int p;
-  double tau;
-  if (variant == EGT_VARIANT_ALT) {
-    tau = 2.0 / ((double)st->t + 3.0);
-    p = (st->t % 2 == 0) ? 0 : 1;
-  } else if (variant == EGT_VARIANT_BAL) {
-    tau = 2.0 / ((double)st->t + 3.0);
-    p = st->mu[0] > st->mu[1] ? 0 : 1;
-  } else {
-    tau = st->tau;
-    p = st->mu[0] > st->mu[1] ? 0 : 1;
+  bool first = false;
+  if (!st->step_open) {
+    const int variant = st->opts.variant;
+    int p;
+    double tau;
+    if (variant == EGT_VARIANT_ALT) {
+      tau = 2.0 / ((double)st->t + 3.0);
+      p = (st->t % 2 == 0) ? 0 : 1;
+    } else if (variant == EGT_VARIANT_BAL) {
+      tau = 2.0 / ((double)st->t + 3.0);
+      p = st->mu[0] > st->mu[1] ? 0 : 1;
+    } else {
+      tau = st->tau;
+      p = st->mu[0] > st->mu[1] ? 0 : 1;
+    }
+    if (player >= 0) p = player;
+    st->step_open = true;
+    st->step_p = p;
+    st->step_tau = tau;
+    first = true;
   }
-  if (player >= 0) p = player;
-  const int o = 1 - p;
   int rc;
-  bool first = true;
-  double egv = 0;
-  for (;;) {
-    if ((rc = attempt(st, p, tau, first, s))) return rc;
-    first = false;
-    if ((rc = fetch_values(st, 4, s))) return rc;
-    egv = st->hscal[0] + st->hscal[1];
-    if (variant != EGT_VARIANT_AS || !(egv < 0.0)) break;
+  if ((rc = attempt(st, st->step_p, st->step_tau, first, s))) return rc;
+  return enqueue_values(st, st->prec == kF64 ? 4 : 2, s);
+}
+
+// Waits for the enqueued attempt.  EGT/as with EGV < 0: tau halves and
+// *accepted = 0 (launch again).  Otherwise the step is accepted.
+int step_finish(egt_state* st, hipStream_t s, int* accepted, double* egv_out, int* stepped) {
+  if (!st || !st->step_open) return fail(EGT_EINVAL, "no step in progress");
+  const int trees = st->pending_trees;
+  int rc;
+  if ((rc = finish_values(st, s))) return rc;
+  const double egv = st->hscal[0] + st->hscal[1];
+  const int p = st->step_p, o = 1 - p;
+  double tau = st->step_tau;
+  if (st->opts.variant == EGT_VARIANT_AS && egv < 0.0) {
     tau *= 0.5;
     st->backtracks++;
     if (tau < kTauFloor) return fail(EGT_ENOTCONV, "tau fell below 1e-30 in the EGT/as backtracking");
+    st->step_tau = tau;
+    *accepted = 0;
+    return EGT_OK;
   }
   // accept: G[p] <- (1-tau) G[p] + tau T1[p] (linearity), G[o] <- T2[o]
-  EGT_TRY(launch_axpby(vec_elems(g, p), 1.0 - tau, st->G[p], tau, st->T1[p], st->G[p], s));
+  if ((rc = axpby(st, p, 1.0 - tau, st->G[p], tau, st->T1[p], st->G[p], s))) return rc;
   std::swap(st->G[o], st->T2[o]);
   std::swap(st->X[p], st->Xn[p]);
   std::swap(st->X[o], st->Xn[o]);
   st->mu[p] *= (1.0 - tau);
-  if (variant == EGT_VARIANT_AS) st->tau = tau;
+  if (st->opts.variant == EGT_VARIANT_AS) st->tau = tau;
   st->t++;
-  st->br_min_x = st->hscal[2];
-  st->br_max_y = -st->hscal[3];
-  st->gap = -st->hscal[3] - st->hscal[2];
-  st->gap_valid = true;
+  if (trees == 4) {
+    st->br_min_x = st->hscal[2];
+    st->br_max_y = -st->hscal[3];
+    st->gap = -st->hscal[3] - st->hscal[2];
+    st->gap_valid = true;
+  } else {
+    st->gap_valid = false;
+  }
   st->last_egv = egv;
+  st->step_open = false;
+  *accepted = 1;
   if (egv_out) *egv_out = egv;
   if (stepped) *stepped = p;
   return EGT_OK;
 }
 
-int state_get(const egt_state* st, double* x, double* y, double* mu_x, double* mu_y, double* tau, int64_t* iters,
-              hipStream_t s) {
+int state_step(egt_state* st, int player, double* egv_out, int* stepped, hipStream_t s) {
   if (!st) return fail(EGT_EINVAL, "null state");
-  const egt_game* g = st->g;
-  if (x) EGT_HIP(hipMemcpyAsync(x, st->X[0], sizeof(double) * vec_elems(g, 0), hipMemcpyDeviceToDevice, s));
-  if (y) EGT_HIP(hipMemcpyAsync(y, st->X[1], sizeof(double) * vec_elems(g, 1), hipMemcpyDeviceToDevice, s));
+  if (st->step_open) return fail(EGT_EINVAL, "a split step is in progress");
+  int rc, accepted = 0;
+  while (!accepted) {
+    if ((rc = step_launch(st, player, s))) return rc;
+    if ((rc = step_finish(st, s, &accepted, egv_out, stepped))) {
+      st->step_open = false;
+      return rc;
+    }
+  }
+  return EGT_OK;
+}
+
+int state_get(const egt_state* cst, double* x, double* y, double* mu_x, double* mu_y, double* tau, int64_t* iters,
+              hipStream_t s) {
+  if (!cst) return fail(EGT_EINVAL, "null state");
+  egt_state* st = const_cast<egt_state*>(cst);
+  int rc;
+  if (x && (rc = widen(st, 0, st->X[0], x, s))) return rc;
+  if (y && (rc = widen(st, 1, st->X[1], y, s))) return rc;
   if (mu_x) *mu_x = st->mu[0];
   if (mu_y) *mu_y = st->mu[1];
   if (tau) *tau = st->tau;
@@ -373,11 +522,12 @@ int state_get(const egt_state* st, double* x, double* y, double* mu_x, double* m
   return EGT_OK;
 }
 
-int state_get_products(const egt_state* st, double* ay, double* atx, hipStream_t s) {
-  if (!st) return fail(EGT_EINVAL, "null state");
-  const egt_game* g = st->g;
-  if (ay) EGT_HIP(hipMemcpyAsync(ay, st->G[0], sizeof(double) * vec_elems(g, 0), hipMemcpyDeviceToDevice, s));
-  if (atx) EGT_HIP(hipMemcpyAsync(atx, st->G[1], sizeof(double) * vec_elems(g, 1), hipMemcpyDeviceToDevice, s));
+int state_get_products(const egt_state* cst, double* ay, double* atx, hipStream_t s) {
+  if (!cst) return fail(EGT_EINVAL, "null state");
+  egt_state* st = const_cast<egt_state*>(cst);
+  int rc;
+  if (ay && (rc = widen(st, 0, st->G[0], ay, s))) return rc;
+  if (atx && (rc = widen(st, 1, st->G[1], atx, s))) return rc;
   return EGT_OK;
 }
 
@@ -388,17 +538,16 @@ int state_set(egt_state* st, const double* x, const double* y, double mu_x, doub
     return fail(EGT_EINVAL, "mu must be finite and > 0");
   if (!(tau > 0) || !(tau < 1)) return fail(EGT_EINVAL, "tau must lie in (0, 1)");
   if (iters < 0) return fail(EGT_EINVAL, "iters < 0");
-  const egt_game* g = st->g;
-  EGT_HIP(hipMemcpyAsync(st->X[0], x, sizeof(double) * vec_elems(g, 0), hipMemcpyDeviceToDevice, s));
-  EGT_HIP(hipMemcpyAsync(st->X[1], y, sizeof(double) * vec_elems(g, 1), hipMemcpyDeviceToDevice, s));
   int rc;
+  if ((rc = narrow(st, 0, x, st->X[0], s))) return rc;
+  if ((rc = narrow(st, 1, y, st->X[1], s))) return rc;
   if (ay) {
-    EGT_HIP(hipMemcpyAsync(st->G[0], ay, sizeof(double) * vec_elems(g, 0), hipMemcpyDeviceToDevice, s));
+    if ((rc = narrow(st, 0, ay, st->G[0], s))) return rc;
   } else if ((rc = grad(st, 0, st->X[1], st->G[0], s))) {
     return rc;
   }
   if (atx) {
-    EGT_HIP(hipMemcpyAsync(st->G[1], atx, sizeof(double) * vec_elems(g, 1), hipMemcpyDeviceToDevice, s));
+    if ((rc = narrow(st, 1, atx, st->G[1], s))) return rc;
   } else if ((rc = grad(st, 1, st->X[0], st->G[1], s))) {
     return rc;
   }
@@ -408,6 +557,40 @@ int state_set(egt_state* st, const double* x, const double* y, double mu_x, doub
   st->tau = tau;
   st->t = iters;
   st->gap_valid = false;
+  return EGT_OK;
+}
+
+// Fills the scalar result of a finished run (value from FP64 copies of x and
+// A y: the precision form's last gap evaluation left them in X64 / G64).
+int fill_result(egt_state* st, bool converged, double seconds, egt_result* res, hipStream_t s) {
+  std::memset(res, 0, sizeof(*res));
+  res->iters = st->t;
+  res->products = st->products;
+  res->backtracks = st->backtracks;
+  res->gap = st->gap;
+  res->br_max_y = st->br_max_y;
+  res->br_min_x = st->br_min_x;
+  res->mu_x = st->mu[0];
+  res->mu_y = st->mu[1];
+  res->tau = st->tau;
+  res->converged = converged ? 1 : 0;
+  res->seconds = seconds;
+  const int64_t n0 = vec_elems(st->g, 0);
+  double* hx = (double*)std::malloc(sizeof(double) * n0 * 2);
+  if (!hx) return fail(EGT_ENOMEM, "host allocation failed");
+  const double* dx = st->prec == kF64 ? (const double*)st->X[0] : st->X64[0];
+  const double* dg = st->prec == kF64 ? (const double*)st->G[0] : st->G64[0];
+  hipError_t e = hipMemcpyAsync(hx, dx, sizeof(double) * n0, hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(hx + n0, dg, sizeof(double) * n0, hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) {
+    std::free(hx);
+    return hip_fail(e, "copy of the final iterate");
+  }
+  double v = 0.0;  // x^T A y = <x, A y>
+  for (int64_t i = 0; i < n0; ++i) v += hx[i] * hx[n0 + i];
+  res->value_p1 = -v;
+  std::free(hx);
   return EGT_OK;
 }
 
@@ -434,38 +617,7 @@ int solve(const egt_game* g, const egt_solve_opts* o, egt_result* res, egt_state
   }
   if (rc == EGT_OK && !st->gap_valid) rc = state_gap(st, nullptr, nullptr, nullptr, s);
   const auto t1 = std::chrono::steady_clock::now();
-  res->iters = st->t;
-  res->products = st->products;
-  res->backtracks = st->backtracks;
-  res->gap = st->gap;
-  res->br_max_y = st->br_max_y;
-  res->br_min_x = st->br_min_x;
-  res->mu_x = st->mu[0];
-  res->mu_y = st->mu[1];
-  res->tau = st->tau;
-  res->converged = converged ? 1 : 0;
-  res->seconds = std::chrono::duration<double>(t1 - t0).count();
-  if (rc == EGT_OK) {
-    // value to player 1 = -(x^T A y) = -<x, G[0]>: a dot product via root sums
-    // is not needed; compute it on the host from one copy of two small sums.
-    double v = 0.0;
-    const int64_t n0 = vec_elems(g, 0);
-    double* hx = (double*)std::malloc(sizeof(double) * n0 * 2);
-    if (!hx) {
-      rc = fail(EGT_ENOMEM, "host allocation failed");
-    } else {
-      hipError_t e = hipMemcpyAsync(hx, st->X[0], sizeof(double) * n0, hipMemcpyDeviceToHost, s);
-      if (e == hipSuccess) e = hipMemcpyAsync(hx + n0, st->G[0], sizeof(double) * n0, hipMemcpyDeviceToHost, s);
-      if (e == hipSuccess) e = hipStreamSynchronize(s);
-      if (e != hipSuccess) {
-        rc = hip_fail(e, "copy of the final iterate");
-      } else {
-        for (int64_t i = 0; i < n0; ++i) v += hx[i] * hx[n0 + i];
-        res->value_p1 = -v;
-      }
-      std::free(hx);
-    }
-  }
+  if (rc == EGT_OK) rc = fill_result(st, converged, std::chrono::duration<double>(t1 - t0).count(), res, s);
   if (rc == EGT_OK && !converged) rc = fail(EGT_ENOTCONV, "iteration cap reached before the target gap");
   if (state_out && (rc == EGT_OK || rc == EGT_ENOTCONV)) {
     *state_out = st;
@@ -474,5 +626,24 @@ int solve(const egt_game* g, const egt_solve_opts* o, egt_result* res, egt_state
   }
   return rc;
 }
+
+// Bytes of device memory a state of this game and precision allocates.
+int64_t state_bytes(const egt_game* g, bool mixed) {
+  const size_t esz = mixed ? sizeof(float) : sizeof(double);
+  size_t bytes = 0;
+  for (int p = 0; p < 2; ++p) {
+    bytes += esz * 8 * (size_t)vec_elems(g, p) + sizeof(double) * 2 * (size_t)g->hp[p].n_nodes * g->ld;
+    if (mixed) bytes += sizeof(double) * 3 * (size_t)vec_elems(g, p);
+    bytes += 12 * 256;
+  }
+  bytes += (64 + (size_t)kMaxTrees * kMaxPartials) * sizeof(double) + 2 * 256;
+  return (int64_t)bytes;
+}
+
+// Accessors for the batch engine.
+const egt_solve_opts& state_opts(const egt_state* st) { return st->opts; }
+int64_t state_iters(const egt_state* st) { return st->t; }
+bool state_gap_known(const egt_state* st) { return st->gap_valid; }
+double state_gap_value(const egt_state* st) { return st->gap; }
 
 }  // namespace egt

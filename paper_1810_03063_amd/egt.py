@@ -81,6 +81,8 @@ _game_layout = _decl("egt_game_layout", ctypes.c_int, _p, ctypes.c_int, _p, _p, 
 _game_terminals = _decl("egt_game_terminals", ctypes.c_int, _p, ctypes.POINTER(_i64), ctypes.POINTER(_i64))
 _gradient = _decl("egt_gradient", ctypes.c_int, _p, ctypes.c_int, _p, _p, _p)
 _smoothed_br = _decl("egt_smoothed_br", ctypes.c_int, _p, ctypes.c_int, _p, _f64, _p, _p, _p)
+_gradient_mixed = _decl("egt_gradient_mixed", ctypes.c_int, _p, ctypes.c_int, _p, _p, _p)
+_smoothed_br_mixed = _decl("egt_smoothed_br_mixed", ctypes.c_int, _p, ctypes.c_int, _p, _f64, _p, _p, _p)
 _best_response = _decl("egt_best_response", ctypes.c_int, _p, ctypes.c_int, _p, _p, _p)
 _uniform = _decl("egt_uniform", ctypes.c_int, _p, ctypes.c_int, _p, _p)
 _saddle_gap = _decl("egt_saddle_gap", ctypes.c_int, _p, _p, _p, ctypes.POINTER(_f64), ctypes.POINTER(_f64),
@@ -97,11 +99,25 @@ _state_gap = _decl("egt_state_gap", ctypes.c_int, _p, ctypes.POINTER(_f64), ctyp
 _solve = _decl("egt_solve", ctypes.c_int, _p, ctypes.POINTER(SolveOpts), ctypes.POINTER(SolveResult),
                ctypes.POINTER(_p), _p)
 
+_state_bytes = _decl("egt_state_bytes", ctypes.c_int, _p, ctypes.POINTER(SolveOpts), ctypes.POINTER(_i64))
+_batch_create = _decl("egt_batch_create", ctypes.c_int, _i64, _i32, ctypes.POINTER(_p))
+_batch_destroy = _decl("egt_batch_destroy", ctypes.c_int, _p)
+_batch_admit = _decl("egt_batch_admit", ctypes.c_int, _p, _p, ctypes.POINTER(SolveOpts), ctypes.POINTER(_i32))
+_batch_tick = _decl("egt_batch_tick", ctypes.c_int, _p, ctypes.POINTER(_i32), ctypes.POINTER(_i32))
+_batch_poll = _decl("egt_batch_poll", ctypes.c_int, _p, _i32, ctypes.POINTER(_i32), ctypes.POINTER(_i32),
+                    ctypes.POINTER(SolveResult))
+_batch_retire = _decl("egt_batch_retire", ctypes.c_int, _p, _i32)
+_batch_usage = _decl("egt_batch_usage", ctypes.c_int, _p, ctypes.POINTER(_i64), ctypes.POINTER(_i32),
+                     ctypes.POINTER(_i32))
+
 EXPORTED = [
     "egt_last_error", "egt_default_opts", "egt_build_game", "egt_free_game", "egt_game_dims",
     "egt_game_layout", "egt_game_terminals", "egt_gradient", "egt_smoothed_br", "egt_best_response",
+    "egt_gradient_mixed", "egt_smoothed_br_mixed",
     "egt_uniform", "egt_saddle_gap", "egt_state_create", "egt_state_destroy", "egt_step",
     "egt_state_get", "egt_state_get_products", "egt_state_set", "egt_state_gap", "egt_solve",
+    "egt_state_bytes", "egt_batch_create", "egt_batch_destroy", "egt_batch_admit", "egt_batch_tick",
+    "egt_batch_poll", "egt_batch_retire", "egt_batch_usage",
 ]
 
 
@@ -117,11 +133,11 @@ def _stream(stream=None):
     return ctypes.c_void_p(stream.cuda_stream)
 
 
-def _dptr(t, shape=None):
+def _dptr(t, shape=None, dtype=torch.float64):
     if t is None:
         return None
-    if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.float64 and t.is_contiguous()):
-        raise ValueError("expected a contiguous float64 CUDA tensor")
+    if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == dtype and t.is_contiguous()):
+        raise ValueError(f"expected a contiguous {dtype} CUDA tensor")
     if shape is not None and tuple(t.shape) != tuple(shape):
         raise ValueError(f"expected shape {tuple(shape)}, got {tuple(t.shape)}")
     return ctypes.c_void_p(t.data_ptr())
@@ -185,8 +201,8 @@ class Game:
         _check(_game_terminals(self._h, ctypes.byref(f), ctypes.byref(s)))
         return f.value, s.value
 
-    def empty(self, p, device="cuda"):
-        return torch.zeros((self.n_seq[p], self.ld), dtype=torch.float64, device=device)
+    def empty(self, p, device="cuda", dtype=torch.float64):
+        return torch.zeros((self.n_seq[p], self.ld), dtype=dtype, device=device)
 
     def close(self):
         if self._h is not None:
@@ -220,6 +236,29 @@ def smoothed_br(game: Game, player: int, grad, mu: float, strat_out=None, value_
     return strat_out, value_out
 
 
+def gradient_mixed(game: Game, player: int, strat_other, out=None, stream=None):
+    """Precision-form product (FP32 in/out, BF16 hi+lo showdown GEMM)."""
+    f32 = torch.float32
+    if out is None:
+        out = game.empty(player, dtype=f32)
+    _check(_gradient_mixed(game.handle, player, _dptr(strat_other, (game.n_seq[1 - player], game.ld), f32),
+                           _dptr(out, (game.n_seq[player], game.ld), f32), _stream(stream)))
+    return out
+
+
+def smoothed_br_mixed(game: Game, player: int, grad, mu: float, strat_out=None, value_out=None, stream=None):
+    """Precision-form smoothed best response: FP32 strategy, FP64 value."""
+    f32 = torch.float32
+    if strat_out is None:
+        strat_out = game.empty(player, dtype=f32)
+    if value_out is None:
+        value_out = torch.zeros(1, dtype=torch.float64, device=grad.device)
+    _check(_smoothed_br_mixed(game.handle, player, _dptr(grad, (game.n_seq[player], game.ld), f32), float(mu),
+                              _dptr(strat_out, (game.n_seq[player], game.ld), f32), _dptr(value_out),
+                              _stream(stream)))
+    return strat_out, value_out
+
+
 def best_response(game: Game, player: int, grad, value_out=None, stream=None):
     if value_out is None:
         value_out = torch.zeros(1, dtype=torch.float64, device=grad.device)
@@ -243,10 +282,14 @@ def saddle_gap(game: Game, x, y, stream=None):
     return g.value, a.value, b.value
 
 
-def make_opts(variant="AS", eps=None, max_iters=100000, mu0=None, tau0=0.5, gap_every=1):
+PRECISIONS = {"fp64": 0, "mixed": 1}
+
+
+def make_opts(variant="AS", eps=None, max_iters=100000, mu0=None, tau0=0.5, gap_every=1, precision="fp64"):
     o = SolveOpts()
     _default_opts(ctypes.byref(o))
     o.variant = VARIANTS[variant] if isinstance(variant, str) else int(variant)
+    o.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
     o.eps = 0.0 if eps is None else float(eps)
     o.max_iters = int(max_iters)
     if mu0 is not None:
@@ -327,3 +370,63 @@ def solve(game: Game, keep_state=False, stream=None, **opts):
     out["status"] = ERRORS.get(rc, "EGT_OK") if rc else "EGT_OK"
     st = State(game, handle=h) if keep_state and h.value else None
     return out, st
+
+
+def state_bytes(game: Game, **opts):
+    o = make_opts(**opts)
+    b = _i64()
+    _check(_state_bytes(game.handle, ctypes.byref(o), ctypes.byref(b)))
+    return b.value
+
+
+class Batch:
+    """Continuous batching of solves (egt_batch_*): admit / tick / poll / retire."""
+
+    def __init__(self, budget_bytes: int, max_slots: int = 64):
+        h = _p()
+        _check(_batch_create(int(budget_bytes), int(max_slots), ctypes.byref(h)))
+        self._h = h
+
+    def admit(self, game: Game, **opts):
+        """Slot index, or None when the solve does not fit the budget / slots now."""
+        o = make_opts(**opts)
+        slot = _i32()
+        rc = _batch_admit(self._h, game.handle, ctypes.byref(o), ctypes.byref(slot))
+        if rc == -6:
+            return None
+        _check(rc)
+        return slot.value
+
+    def tick(self):
+        """(live solves, solves finished in this tick)."""
+        a, f = _i32(), _i32()
+        _check(_batch_tick(self._h, ctypes.byref(a), ctypes.byref(f)))
+        return a.value, f.value
+
+    def poll(self, slot: int):
+        """None while running, else (status name, result dict)."""
+        d, st = _i32(), _i32()
+        res = SolveResult()
+        _check(_batch_poll(self._h, int(slot), ctypes.byref(d), ctypes.byref(st), ctypes.byref(res)))
+        if not d.value:
+            return None
+        return (ERRORS.get(st.value, "EGT_OK") if st.value else "EGT_OK"), res.as_dict()
+
+    def retire(self, slot: int):
+        _check(_batch_retire(self._h, int(slot)))
+
+    def usage(self):
+        u, live, done = _i64(), _i32(), _i32()
+        _check(_batch_usage(self._h, ctypes.byref(u), ctypes.byref(live), ctypes.byref(done)))
+        return u.value, live.value, done.value
+
+    def close(self):
+        if self._h is not None:
+            _check(_batch_destroy(self._h))
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

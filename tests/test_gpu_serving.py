@@ -1,0 +1,113 @@
+"""Serving form on the GPU: continuous batching with HBM-budget admission.
+
+* Each result is bitwise the same alone (egt_solve) and in a mix of
+  concurrently running solves of different sizes and precisions.
+* Admission respects the budget: a solve that does not fit waits, and is
+  admitted once a finished solve is retired.
+* A solve admitted while others are running joins the running batch and
+  can finish before them.
+* The request loop serves a Poisson trace end to end.
+"""
+import numpy as np
+import pytest
+
+from instances import make_instance
+from instances.endgames import serving_trace
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def egt():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1810_03063_amd import egt as mod
+
+    return mod
+
+
+MIX = [("kuhn", 0, "fp64", 1), ("c0", 0, "fp64", 1), ("c0", 1, "mixed", 10), ("c0", 2, "fp64", 1),
+       ("c1", 0, "mixed", 10), ("c0", 3, "mixed", 5)]
+
+
+def test_alone_and_in_the_mix_are_bitwise_equal(egt):
+    games = [egt.Game(make_instance(c, s)) for c, s, _, _ in MIX]
+    alone = []
+    for G, (c, s, prec, ge) in zip(games, MIX):
+        print(f"[case] alone {c} seed={s} {prec}", flush=True)
+        r, _ = egt.solve(G, precision=prec, gap_every=ge)
+        alone.append(r)
+    print("[case] mixed batch", flush=True)
+    b = egt.Batch(budget_bytes=8 << 30, max_slots=16)
+    slots = [b.admit(G, precision=prec, gap_every=ge) for G, (c, s, prec, ge) in zip(games, MIX)]
+    assert None not in slots
+    ticks = 0
+    while b.usage()[1] > 0:
+        b.tick()
+        ticks += 1
+        assert ticks < 200000
+    for slot, r, (c, s, prec, _) in zip(slots, alone, MIX):
+        status, m = b.poll(slot)
+        assert status == r["status"] == "EGT_OK"
+        for k in ("iters", "backtracks", "products", "gap", "br_max_y", "br_min_x", "value_p1", "mu_x", "mu_y",
+                  "tau"):
+            assert m[k] == r[k], (c, s, prec, k, m[k], r[k])
+        b.retire(slot)
+    assert b.usage() == (0, 0, 0)
+    b.close()
+
+
+def test_budget_admission_and_release(egt):
+    G = egt.Game(make_instance("c0", 0))
+    need = egt.state_bytes(G)
+    b = egt.Batch(budget_bytes=2 * need, max_slots=8)
+    s0 = b.admit(G)
+    s1 = b.admit(G)
+    assert s0 is not None and s1 is not None
+    assert b.admit(G) is None  # a third state does not fit
+    used, live, done = b.usage()
+    assert used == 2 * need and live == 2 and done == 0
+    while b.poll(s0) is None:
+        b.tick()
+    b.retire(s0)
+    s2 = b.admit(G)
+    assert s2 is not None
+    while b.usage()[1] > 0:
+        b.tick()
+    for s in (s1, s2):
+        assert b.poll(s)[0] == "EGT_OK"
+        b.retire(s)
+    b.close()
+
+
+def test_solve_joins_a_running_batch(egt):
+    big = egt.Game(make_instance("c1", 1))
+    small = egt.Game(make_instance("c0", 5))
+    b = egt.Batch(budget_bytes=4 << 30, max_slots=4)
+    sb = b.admit(big)
+    for _ in range(30):
+        b.tick()
+    assert b.poll(sb) is None
+    ss = b.admit(small)
+    while b.poll(ss) is None:
+        b.tick()
+    assert b.poll(sb) is None  # the small solve finished while the big one runs
+    while b.poll(sb) is None:
+        b.tick()
+    assert b.poll(sb)[0] == "EGT_OK"
+    b.close()
+
+
+def test_request_loop_serves_a_poisson_trace(egt):
+    from paper_1810_03063_amd.serve import LibEngine, Request, serve, summarize
+
+    trace = serving_trace(24, rate=40.0, seed=3, shapes=("c0", "c1"))
+    reqs = [Request(i, a, make_instance(shape, seed)) for i, (a, shape, seed) in enumerate(trace)]
+    eng = LibEngine(egt, budget_bytes=2 << 30, max_slots=16, precision="mixed", gap_every=10)
+    out, wall = serve(eng, reqs)
+    s = summarize(out, wall)
+    print(f"  served {s['requests']} in {wall:.2f} s: p50 {s['p50_ms']:.1f} ms, p99 {s['p99_ms']:.1f} ms")
+    assert s["converged"] == len(reqs)
+    assert all(r.result["gap"] <= 1e-3 * r.payload.pot for r in out)
+    eng.close()
