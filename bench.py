@@ -38,6 +38,12 @@ def parse():
     ap.add_argument("--cpu-sample-iters", type=int, default=60)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--kernel-reps", type=int, default=200)
+    ap.add_argument("--mixed-steps", type=int, default=5, help="precision-form solves of the same endgame")
+    ap.add_argument("--serve-requests", type=int, default=48, help="requests of the serving trace (0 = skip)")
+    ap.add_argument("--serve-shapes", default="c0,c1,c2,c3")
+    ap.add_argument("--serve-budget-gb", type=float, default=16.0)
+    ap.add_argument("--copy-calibration-mb", type=float, default=0.0,
+                    help="run 5 plain device copies of this many MB first (scales HBM counters)")
     return ap.parse_args()
 
 
@@ -75,6 +81,89 @@ def kernel_roofline(egt, torch, G, reps):
                 algorithmic_bytes=int(bytes_))
 
 
+def precision_form(egt, torch, G, steps, fp64_ms, fp64_value, reps):
+    """The same endgame in the precision form: FP32 iterates, BF16 hi+lo
+    showdown GEMM, FP32 prox with FP64 normalisers, FP64 gap every 10 iters."""
+    egt.solve(G, precision="mixed", gap_every=10)  # warm-up (builds W)
+    lat, iters, res = [], 0, None
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        ts = time.perf_counter()
+        res, _ = egt.solve(G, precision="mixed", gap_every=10)
+        lat.append(time.perf_counter() - ts)
+        iters += res["iters"]
+        if res["converged"] != 1:
+            raise RuntimeError(f"precision-form solve did not converge: {res}")
+    elapsed = time.perf_counter() - t0
+    # product launch of the precision form: fold kernel + BF16 GEMM
+    y32 = egt.uniform(G, 1).float().contiguous()
+    out32 = G.empty(0, dtype=torch.float32)
+    for _ in range(10):
+        egt.gradient_mixed(G, 0, y32, out32)
+    s = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(s)
+    for _ in range(reps):
+        egt.gradient_mixed(G, 0, y32, out32)
+    e1.record(s)
+    e1.synchronize()
+    prod_us = e0.elapsed_time(e1) / reps * 1e3
+    n_fold, n_show = G.terminals()
+    kpad = (G.n + 63) // 64 * 64
+    flops = 2.0 * kpad * kpad * n_show * 2  # hi and lo
+    ms = elapsed / steps * 1e3
+    return dict(
+        solves_per_sec=steps / elapsed, iters_per_sec=iters / elapsed, ms_per_solve=ms,
+        iters_per_solve=iters / steps, p50_ms=percentile(lat, 50) * 1e3, p99_ms=percentile(lat, 99) * 1e3,
+        speedup_vs_fp64=fp64_ms / ms, final_gap_fp64=res["gap"],
+        value_minus_fp64=res["value_p1"] - fp64_value,
+        product_us=round(prod_us, 3), gemm_dense_gflop=flops / 1e9,
+        mfma_util_lower_bound=flops / (prod_us * 1e-6) / 2.5e15,
+        note="gap re-measured with FP64 products; mfma_util_lower_bound charges the whole product "
+             "launch (fold kernel + GEMM) to the GEMM",
+    )
+
+
+def serving(egt, args):
+    """Poisson trace of solve requests (shapes drawn uniformly), continuously
+    batched in the precision form under an HBM budget, against the same trace
+    served one at a time in FP64."""
+    from instances import make_instance
+    from instances.endgames import serving_trace
+    from paper_1810_03063_amd.serve import LibEngine, Request, serve, serve_sequential, summarize
+
+    shapes = tuple(args.serve_shapes.split(","))
+    n = args.serve_requests
+    budget = int(args.serve_budget_gb * (1 << 30))
+
+    def reqs_for(rate):
+        tr = serving_trace(n, rate=rate, seed=11, shapes=shapes)
+        return [Request(i, a, make_instance(shape, seed)) for i, (a, shape, seed) in enumerate(tr)]
+
+    def run(rate):
+        eng = LibEngine(egt, budget, max_slots=64, precision="mixed", gap_every=10)
+        out, wall = serve(eng, reqs_for(rate))
+        eng.close()
+        return summarize(out, wall)
+
+    saturated = run(0.0)  # every request at t = 0: the batched throughput R
+    rate = 0.7 * saturated["solves_per_sec"]
+    loaded = run(rate)
+
+    def solve_one(r):
+        G = egt.Game(r.payload)
+        res, _ = egt.solve(G)
+        G.close()
+        return res.get("status", "EGT_OK"), res
+
+    seq_out, seq_wall = serve_sequential(solve_one, reqs_for(rate))
+    baseline = summarize(seq_out, seq_wall)
+    return dict(shapes=list(shapes), requests=n, budget_gb=args.serve_budget_gb, saturated=saturated,
+                poisson_rate_per_s=rate, batched=loaded, sequential_fp64=baseline,
+                throughput_vs_sequential=loaded["solves_per_sec"] / baseline["solves_per_sec"])
+
+
 def cpu_baseline(inst, sample_iters, iters_per_solve, variant):
     import numpy as np  # noqa: F401
     from threadpoolctl import threadpool_info
@@ -105,6 +194,16 @@ def main():
     from paper_1810_03063_amd import egt
 
     torch.cuda.set_device(0)
+    if args.copy_calibration_mb > 0:
+        # a plain copy of known size: its FETCH_SIZE / WRITE_SIZE per dispatch
+        # calibrate the counters of the other kernels
+        nbytes = int(args.copy_calibration_mb * (1 << 20)) // 8 * 8
+        src = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     inst = make_instance(args.config, args.seed)
     G = egt.Game(inst)
     torch.cuda.synchronize()
@@ -157,6 +256,14 @@ def main():
         "final_gap": res["gap"],
         "roofline": roof,
     }
+    if args.mixed_steps > 0:
+        out["precision_form"] = precision_form(egt, torch, G, args.mixed_steps, out["ms_per_step"], res["value_p1"],
+                                               args.kernel_reps)
+        print(f"precision form: {out['precision_form']['ms_per_solve']:.1f} ms per solve", file=sys.stderr,
+              flush=True)
+    if args.serve_requests > 0:
+        out["serving"] = serving(egt, args)
+        print("serving done", file=sys.stderr, flush=True)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(inst, args.cpu_sample_iters, iters_per_solve, args.variant)
     print(json.dumps(out), flush=True)
