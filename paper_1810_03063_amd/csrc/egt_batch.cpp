@@ -1,51 +1,60 @@
 // Serving form: continuous batching of endgame solves on one device.
 //
-// A batch holds up to max_slots solves, each with its own device-resident
-// state (iterates, products, q_bar, node values) and its own HIP stream, and
-// admits a new solve only while the bytes of all live states fit the budget.
-// egt_batch_tick advances every live solve by one phase -- a saddle-gap
-// evaluation when the solve is due for one, else one attempt of an EGT step --
-// by first enqueueing the phase of every solve on its stream and only then
-// waiting for each, so the kernels of different solves overlap on the device.
-// A solve that reaches its gap target (or its iteration cap) finishes and
-// keeps its result until it is retired, which frees its memory for new
-// admissions.  Each solve's arithmetic is the same kernels in the same order
-// as a lone egt_solve, so its result does not depend on the mix.
+// A batch reserves its device-memory budget once (one arena) plus a pinned
+// host buffer and a HIP stream per slot.  Admitting a solve charges the
+// bytes of its state against the budget -- it takes a first-fit range of the
+// arena, or is refused (EGT_EBUDGET) until a finished solve is retired -- and
+// queues it for a pool of host worker threads.  A worker creates the state in
+// its arena range and runs the solve (the same loop and kernels as
+// egt_solve) on the slot's stream; solves on different workers run
+// concurrently, so requests that arrive while others are running start as
+// soon as memory and a worker are free, and their kernels overlap on the
+// device.  No step of a solve depends on the other solves, so a result is
+// bitwise the same alone and in the mix.  The hot path allocates nothing:
+// no hipMalloc, no host pinning and no device-wide synchronisation after the
+// batch is created.
+#include <algorithm>
+#include <atomic>
 #include <chrono>
+#include <condition_variable>
 #include <cstring>
+#include <deque>
+#include <mutex>
 #include <new>
+#include <thread>
 #include <vector>
 
 #include "egt_internal.h"
 
 namespace egt {
-int state_create(const egt_game* g, const egt_solve_opts* o, hipStream_t s, egt_state** out);
+int state_create_in(const egt_game* g, const egt_solve_opts* o, hipStream_t s, void* dev_mem, double* host_mem,
+                    egt_state** out);
 int state_destroy(egt_state* st);
-int gap_launch(egt_state* st, hipStream_t s);
-int gap_finish(egt_state* st, hipStream_t s);
-int step_launch(egt_state* st, int player, hipStream_t s);
-int step_finish(egt_state* st, hipStream_t s, int* accepted, double* egv_out, int* stepped);
+int solve_loop(egt_state* st, hipStream_t s, const volatile bool* stop, bool* converged);
 int fill_result(egt_state* st, bool converged, double seconds, egt_result* res, hipStream_t s);
 int64_t state_bytes(const egt_game* g, bool mixed);
-const egt_solve_opts& state_opts(const egt_state* st);
-int64_t state_iters(const egt_state* st);
-bool state_gap_known(const egt_state* st);
-double state_gap_value(const egt_state* st);
+size_t state_host_doubles();
 }  // namespace egt
 
 namespace {
 
-enum Phase { kFree = 0, kNeedGap, kNeedStep, kDone };
+enum Phase { kFree = 0, kQueued, kRunning, kDone };
 
 struct Slot {
   Phase phase = kFree;
-  bool pending = false;  // a launched phase awaits its finish
+  const egt_game* g = nullptr;
+  egt_solve_opts opts{};
   egt_state* st = nullptr;
-  hipStream_t stream = nullptr;
-  int64_t bytes = 0;
+  hipStream_t stream = nullptr;  // created with the batch, default priority
+  double* host = nullptr;        // pinned, created with the batch
+  int64_t off = 0, bytes = 0;    // arena range
   int status = EGT_OK;
   egt_result res{};
   std::chrono::steady_clock::time_point t0;
+};
+
+struct Range {
+  int64_t off, len;
 };
 
 }  // namespace
@@ -53,32 +62,95 @@ struct Slot {
 struct egt_batch {
   int64_t budget = 0;
   int64_t used = 0;
+  void* arena = nullptr;
+  std::vector<Range> free_list;  // sorted by offset, coalesced
   std::vector<Slot> slots;
+  std::deque<int> queue;
+  std::vector<std::thread> workers;
+  std::mutex mu;
+  std::condition_variable work_cv, done_cv;
+  volatile bool stop = false;
+  int64_t finished_total = 0, finished_seen = 0;
+  int device = 0;
 };
 
 using namespace egt;
 
 namespace {
 
-void finish_slot(Slot& sl, bool converged) {
-  const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - sl.t0).count();
-  const int rc = fill_result(sl.st, converged, secs, &sl.res, sl.stream);
-  sl.status = rc ? rc : (converged ? EGT_OK : EGT_ENOTCONV);
-  sl.phase = kDone;
+constexpr int64_t kAlign = 256;
+
+bool arena_take(egt_batch* b, int64_t need, int64_t* off) {
+  for (size_t i = 0; i < b->free_list.size(); ++i) {
+    Range& r = b->free_list[i];
+    if (r.len >= need) {
+      *off = r.off;
+      r.off += need;
+      r.len -= need;
+      if (r.len == 0) b->free_list.erase(b->free_list.begin() + (long)i);
+      return true;
+    }
+  }
+  return false;
 }
 
-void fail_slot(Slot& sl, int rc) {
-  std::memset(&sl.res, 0, sizeof(sl.res));
-  sl.res.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - sl.t0).count();
+void arena_give(egt_batch* b, int64_t off, int64_t len) {
+  auto it = std::lower_bound(b->free_list.begin(), b->free_list.end(), off,
+                             [](const Range& r, int64_t o) { return r.off < o; });
+  it = b->free_list.insert(it, Range{off, len});
+  // coalesce with the neighbours
+  size_t i = (size_t)(it - b->free_list.begin());
+  if (i + 1 < b->free_list.size() && b->free_list[i].off + b->free_list[i].len == b->free_list[i + 1].off) {
+    b->free_list[i].len += b->free_list[i + 1].len;
+    b->free_list.erase(b->free_list.begin() + (long)i + 1);
+  }
+  if (i > 0 && b->free_list[i - 1].off + b->free_list[i - 1].len == b->free_list[i].off) {
+    b->free_list[i - 1].len += b->free_list[i].len;
+    b->free_list.erase(b->free_list.begin() + (long)i);
+  }
+}
+
+void run_slot(egt_batch* b, Slot& sl) {
+  hipError_t e = hipSetDevice(b->device);
+  int rc = e == hipSuccess ? EGT_OK : hip_fail(e, "hipSetDevice");
+  egt_state* st = nullptr;
+  if (rc == EGT_OK)
+    rc = state_create_in(sl.g, &sl.opts, sl.stream, (unsigned char*)b->arena + sl.off, sl.host, &st);
+  bool converged = false;
+  if (rc == EGT_OK) rc = solve_loop(st, sl.stream, &b->stop, &converged);
+  egt_result res{};
+  if (rc == EGT_OK) {
+    const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - sl.t0).count();
+    rc = fill_result(st, converged, secs, &res, sl.stream);
+    if (rc == EGT_OK && !converged) rc = EGT_ENOTCONV;
+  } else {
+    res.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - sl.t0).count();
+  }
+  if (st) {
+    (void)hipStreamSynchronize(sl.stream);
+    state_destroy(st);  // the memory stays with the batch
+  }
+  std::lock_guard<std::mutex> lk(b->mu);
+  sl.res = res;
   sl.status = rc;
   sl.phase = kDone;
+  ++b->finished_total;
+  b->done_cv.notify_all();
 }
 
-// After an accepted step or at admission: due for a gap test, or step on.
-Phase next_phase(const egt_state* st) {
-  const egt_solve_opts& op = state_opts(st);
-  const int64_t t = state_iters(st);
-  return (t % op.gap_every == 0 || t >= op.max_iters) ? kNeedGap : kNeedStep;
+void worker_main(egt_batch* b) {
+  for (;;) {
+    int k;
+    {
+      std::unique_lock<std::mutex> lk(b->mu);
+      b->work_cv.wait(lk, [&] { return b->stop || !b->queue.empty(); });
+      if (b->stop && b->queue.empty()) return;
+      k = b->queue.front();
+      b->queue.pop_front();
+      b->slots[(size_t)k].phase = kRunning;
+    }
+    run_slot(b, b->slots[(size_t)k]);
+  }
 }
 
 }  // namespace
@@ -88,44 +160,78 @@ extern "C" {
 int egt_state_bytes(const egt_game* g, const egt_solve_opts* opts, int64_t* bytes) {
   if (!g || !bytes) return fail(EGT_EINVAL, "null argument");
   const bool mixed = opts && opts->precision == EGT_PRECISION_MIXED;
-  *bytes = state_bytes(g, mixed);
+  *bytes = (state_bytes(g, mixed) + kAlign - 1) / kAlign * kAlign;
   return EGT_OK;
 }
 
 int egt_batch_create(int64_t budget_bytes, int32_t max_slots, egt_batch** out) {
-  if (!out || budget_bytes <= 0 || max_slots < 1 || max_slots > 4096)
-    return fail(EGT_EINVAL, "budget must be > 0 and max_slots in 1..4096");
+  if (!out || budget_bytes <= 0 || max_slots < 1 || max_slots > 1024)
+    return fail(EGT_EINVAL, "budget must be > 0 and max_slots in 1..1024");
+  *out = nullptr;
   egt_batch* b = new (std::nothrow) egt_batch();
   if (!b) return fail(EGT_ENOMEM, "host allocation failed");
-  b->budget = budget_bytes;
+  b->budget = (budget_bytes + kAlign - 1) / kAlign * kAlign;
+  EGT_HIP(hipGetDevice(&b->device));
+  hipError_t e = hipMalloc(&b->arena, (size_t)b->budget);
+  if (e != hipSuccess) {
+    delete b;
+    return fail(EGT_ENOMEM, std::string("hipMalloc (batch arena): ") + hipGetErrorString(e));
+  }
+  b->free_list.push_back(Range{0, b->budget});
   b->slots.resize((size_t)max_slots);
+  for (Slot& sl : b->slots) {
+    e = hipStreamCreate(&sl.stream);
+    if (e == hipSuccess)
+      e = hipHostMalloc((void**)&sl.host, sizeof(double) * state_host_doubles(), hipHostMallocDefault);
+    if (e != hipSuccess) {
+      egt_batch_destroy(b);
+      return fail(EGT_ENOMEM, std::string("batch slot resources: ") + hipGetErrorString(e));
+    }
+  }
+  const int n_workers = std::min<int>(max_slots, 16);
+  try {
+    for (int i = 0; i < n_workers; ++i) b->workers.emplace_back(worker_main, b);
+  } catch (...) {
+    egt_batch_destroy(b);
+    return fail(EGT_ENOMEM, "could not start the batch workers");
+  }
   *out = b;
   return EGT_OK;
 }
 
 int egt_batch_retire(egt_batch* b, int32_t slot) {
   if (!b || slot < 0 || slot >= (int32_t)b->slots.size()) return fail(EGT_EINVAL, "bad batch or slot");
+  std::lock_guard<std::mutex> lk(b->mu);
   Slot& sl = b->slots[(size_t)slot];
-  if (sl.phase == kFree) return fail(EGT_EINVAL, "slot is free");
-  int rc = EGT_OK;
-  if (sl.st) rc = state_destroy(sl.st);
-  if (sl.stream) {
-    const hipError_t e = hipStreamDestroy(sl.stream);
-    if (e != hipSuccess && rc == EGT_OK) rc = hip_fail(e, "hipStreamDestroy");
-  }
+  if (sl.phase != kDone) return fail(EGT_EINVAL, "only a finished solve can be retired");
+  arena_give(b, sl.off, sl.bytes);
   b->used -= sl.bytes;
+  hipStream_t stream = sl.stream;
+  double* host = sl.host;
   sl = Slot();
-  return rc;
+  sl.stream = stream;
+  sl.host = host;
+  return EGT_OK;
 }
 
 int egt_batch_destroy(egt_batch* b) {
   if (!b) return EGT_OK;
+  {
+    std::lock_guard<std::mutex> lk(b->mu);
+    b->stop = true;
+    b->queue.clear();
+  }
+  b->work_cv.notify_all();
+  for (std::thread& t : b->workers) t.join();
   int rc = EGT_OK;
-  for (size_t i = 0; i < b->slots.size(); ++i)
-    if (b->slots[i].phase != kFree) {
-      const int r = egt_batch_retire(b, (int32_t)i);
-      if (r && rc == EGT_OK) rc = r;
+  for (Slot& sl : b->slots) {
+    if (sl.stream) {
+      const hipError_t e = hipStreamDestroy(sl.stream);
+      if (e != hipSuccess && rc == EGT_OK) rc = hip_fail(e, "hipStreamDestroy");
     }
+    if (sl.host) (void)hipHostFree(sl.host);
+  }
+  if (b->arena) (void)hipFree(b->arena);
   delete b;
   return rc;
 }
@@ -133,85 +239,57 @@ int egt_batch_destroy(egt_batch* b) {
 int egt_batch_admit(egt_batch* b, const egt_game* g, const egt_solve_opts* opts, int32_t* slot) {
   if (!b || !g || !slot) return fail(EGT_EINVAL, "null argument");
   *slot = -1;
-  const bool mixed = opts && opts->precision == EGT_PRECISION_MIXED;
-  const int64_t need = state_bytes(g, mixed);
-  if (b->used + need > b->budget) return fail(EGT_EBUDGET, "the solve does not fit the memory budget now");
+  egt_solve_opts o;
+  egt_default_opts(&o);
+  if (opts) o = *opts;
+  const bool mixed = o.precision == EGT_PRECISION_MIXED;
+  if (mixed) {  // build the shared precision-form tables here, not on a worker
+    const int rc = ensure_mixed_tables(g);
+    if (rc) return rc;
+  }
+  const int64_t need = (state_bytes(g, mixed) + kAlign - 1) / kAlign * kAlign;
+  std::lock_guard<std::mutex> lk(b->mu);
   size_t k = 0;
   while (k < b->slots.size() && b->slots[k].phase != kFree) ++k;
   if (k == b->slots.size()) return fail(EGT_EBUDGET, "no free slot");
+  int64_t off = 0;
+  if (b->used + need > b->budget || !arena_take(b, need, &off))
+    return fail(EGT_EBUDGET, "the solve does not fit the memory budget now");
   Slot& sl = b->slots[k];
-  sl = Slot();
-  sl.t0 = std::chrono::steady_clock::now();
-  EGT_HIP(hipStreamCreate(&sl.stream));  // default priority
-  const int rc = state_create(g, opts, sl.stream, &sl.st);
-  if (rc) {
-    (void)hipStreamDestroy(sl.stream);
-    sl = Slot();
-    return rc;
-  }
+  sl.phase = kQueued;
+  sl.g = g;
+  sl.opts = o;
+  sl.off = off;
   sl.bytes = need;
+  sl.status = EGT_OK;
+  sl.t0 = std::chrono::steady_clock::now();
   b->used += need;
-  sl.phase = next_phase(sl.st);
+  b->queue.push_back((int)k);
+  b->work_cv.notify_one();
   *slot = (int32_t)k;
   return EGT_OK;
 }
 
 int egt_batch_tick(egt_batch* b, int32_t* n_active, int32_t* n_finished) {
   if (!b) return fail(EGT_EINVAL, "null batch");
-  int32_t finished = 0;
-  // 1: enqueue one phase of every live solve
-  for (Slot& sl : b->slots) {
-    if (sl.phase != kNeedGap && sl.phase != kNeedStep) continue;
-    const int rc = sl.phase == kNeedGap ? gap_launch(sl.st, sl.stream) : step_launch(sl.st, -1, sl.stream);
-    if (rc) {
-      fail_slot(sl, rc);
-      ++finished;
-      continue;
-    }
-    sl.pending = true;
-  }
-  // 2: finish them in slot order
-  for (Slot& sl : b->slots) {
-    if (!sl.pending) continue;
-    sl.pending = false;
-    if (sl.phase == kNeedGap) {
-      const int rc = gap_finish(sl.st, sl.stream);
-      if (rc) {
-        fail_slot(sl, rc);
-        ++finished;
-        continue;
-      }
-      const egt_solve_opts& op = state_opts(sl.st);
-      if (state_gap_value(sl.st) <= op.eps) {
-        finish_slot(sl, true);
-        ++finished;
-      } else if (state_iters(sl.st) >= op.max_iters) {
-        finish_slot(sl, false);
-        ++finished;
-      } else {
-        sl.phase = kNeedStep;
-      }
-    } else {
-      int accepted = 0;
-      const int rc = step_finish(sl.st, sl.stream, &accepted, nullptr, nullptr);
-      if (rc) {
-        fail_slot(sl, rc);
-        ++finished;
-        continue;
-      }
-      if (accepted) sl.phase = next_phase(sl.st);
-    }
-  }
-  int32_t active = 0;
-  for (const Slot& sl : b->slots)
-    if (sl.phase == kNeedGap || sl.phase == kNeedStep) ++active;
-  if (n_active) *n_active = active;
-  if (n_finished) *n_finished = finished;
+  std::unique_lock<std::mutex> lk(b->mu);
+  auto live = [&] {
+    int32_t a = 0;
+    for (const Slot& sl : b->slots)
+      if (sl.phase == kQueued || sl.phase == kRunning) ++a;
+    return a;
+  };
+  if (b->finished_total == b->finished_seen && live() > 0)
+    b->done_cv.wait_for(lk, std::chrono::milliseconds(2), [&] { return b->finished_total != b->finished_seen; });
+  if (n_finished) *n_finished = (int32_t)(b->finished_total - b->finished_seen);
+  b->finished_seen = b->finished_total;
+  if (n_active) *n_active = live();
   return EGT_OK;
 }
 
 int egt_batch_poll(egt_batch* b, int32_t slot, int32_t* done, int32_t* status, egt_result* res) {
   if (!b || slot < 0 || slot >= (int32_t)b->slots.size()) return fail(EGT_EINVAL, "bad batch or slot");
+  std::lock_guard<std::mutex> lk(b->mu);
   const Slot& sl = b->slots[(size_t)slot];
   if (sl.phase == kFree) return fail(EGT_EINVAL, "slot is free");
   const bool d = sl.phase == kDone;
@@ -221,11 +299,13 @@ int egt_batch_poll(egt_batch* b, int32_t slot, int32_t* done, int32_t* status, e
   return EGT_OK;
 }
 
-int egt_batch_usage(const egt_batch* b, int64_t* used_bytes, int32_t* n_live, int32_t* n_done) {
-  if (!b) return fail(EGT_EINVAL, "null batch");
+int egt_batch_usage(const egt_batch* cb, int64_t* used_bytes, int32_t* n_live, int32_t* n_done) {
+  if (!cb) return fail(EGT_EINVAL, "null batch");
+  egt_batch* b = const_cast<egt_batch*>(cb);
+  std::lock_guard<std::mutex> lk(b->mu);
   int32_t live = 0, dn = 0;
   for (const Slot& sl : b->slots) {
-    if (sl.phase == kNeedGap || sl.phase == kNeedStep) ++live;
+    if (sl.phase == kQueued || sl.phase == kRunning) ++live;
     if (sl.phase == kDone) ++dn;
   }
   if (used_bytes) *used_bytes = b->used;

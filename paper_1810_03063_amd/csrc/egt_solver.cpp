@@ -65,6 +65,7 @@ struct egt_state {
   double* dpart = nullptr;  // device root partial sums [trees][n_partials]
   double* hpart = nullptr;  // pinned host mirror
   void* block = nullptr;
+  bool owns_memory = true;  // false: block and hscal belong to a serving batch
   // saddle gap of the current iterate (valid when gap_valid)
   bool gap_valid = false;
   double gap = 0, br_max_y = 0, br_min_x = 0;
@@ -205,7 +206,18 @@ int narrow(egt_state* st, int p, const double* src, void* dst, hipStream_t s) {
 
 int64_t state_bytes(const egt_game* g, bool mixed);
 
+int state_create_in(const egt_game* g, const egt_solve_opts* o, hipStream_t s, void* dev_mem, double* host_mem,
+                    egt_state** out);
+
 int state_create(const egt_game* g, const egt_solve_opts* o, hipStream_t s, egt_state** out) {
+  return state_create_in(g, o, s, nullptr, nullptr, out);
+}
+
+// dev_mem (state_bytes(g, mixed) bytes, 256-byte aligned) and host_mem
+// (pinned, state_host_doubles() doubles) may be given by the caller, who then
+// keeps ownership; otherwise the state allocates them.
+int state_create_in(const egt_game* g, const egt_solve_opts* o, hipStream_t s, void* dev_mem, double* host_mem,
+                    egt_state** out) {
   if (!g || !out) return fail(EGT_EINVAL, "null argument");
   *out = nullptr;
   egt_solve_opts opts;
@@ -241,11 +253,18 @@ int state_create(const egt_game* g, const egt_solve_opts* o, hipStream_t s, egt_
   st->prec = mixed ? kF32 : kF64;
   st->esz = mixed ? sizeof(float) : sizeof(double);
   const size_t bytes = (size_t)state_bytes(g, mixed);
-  hipError_t e = hipMalloc(&st->block, bytes);
-  if (e != hipSuccess) return fail(EGT_ENOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
-  e = hipHostMalloc((void**)&st->hscal, (64 + (size_t)kMaxTrees * kMaxPartials) * sizeof(double),
-                    hipHostMallocDefault);
-  if (e != hipSuccess) return fail(EGT_ENOMEM, std::string("hipHostMalloc: ") + hipGetErrorString(e));
+  if (dev_mem || host_mem) {
+    if (!dev_mem || !host_mem) return fail(EGT_EINVAL, "device and host state memory go together");
+    st->owns_memory = false;
+    st->block = dev_mem;
+    st->hscal = host_mem;
+  } else {
+    hipError_t e = hipMalloc(&st->block, bytes);
+    if (e != hipSuccess) return fail(EGT_ENOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
+    e = hipHostMalloc((void**)&st->hscal, (64 + (size_t)kMaxTrees * kMaxPartials) * sizeof(double),
+                      hipHostMallocDefault);
+    if (e != hipSuccess) return fail(EGT_ENOMEM, std::string("hipHostMalloc: ") + hipGetErrorString(e));
+  }
   st->hpart = st->hscal + 64;
   unsigned char* cur = (unsigned char*)st->block;
   auto take = [&](size_t nbytes) {
@@ -329,7 +348,7 @@ int state_create(const egt_game* g, const egt_solve_opts* o, hipStream_t s, egt_
 int state_destroy(egt_state* st) {
   if (!st) return EGT_OK;
   int rc = EGT_OK;
-  if (st->block || st->hscal) {
+  if (st->owns_memory && (st->block || st->hscal)) {
     hipError_t e = hipDeviceSynchronize();
     if (st->block && e == hipSuccess) e = hipFree(st->block);
     if (st->hscal && e == hipSuccess) e = hipHostFree(st->hscal);
@@ -594,6 +613,28 @@ int fill_result(egt_state* st, bool converged, double seconds, egt_result* res, 
   return EGT_OK;
 }
 
+// The iteration of egt_solve: gap test before every gap_every-th iteration,
+// stop at gap <= eps or max_iters (or when *stop becomes true).
+int solve_loop(egt_state* st, hipStream_t s, const volatile bool* stop, bool* converged) {
+  const egt_solve_opts& op = st->opts;
+  *converged = false;
+  int rc = EGT_OK;
+  for (;;) {
+    const bool check = (st->t % op.gap_every == 0) || st->t >= op.max_iters;
+    if (check) {
+      if ((rc = state_gap(st, nullptr, nullptr, nullptr, s))) return rc;
+      if (st->gap <= op.eps) {
+        *converged = true;
+        return EGT_OK;
+      }
+    }
+    if (st->t >= op.max_iters || (stop && *stop)) break;
+    if ((rc = state_step(st, -1, nullptr, nullptr, s))) return rc;
+  }
+  if (!st->gap_valid) rc = state_gap(st, nullptr, nullptr, nullptr, s);
+  return rc;
+}
+
 int solve(const egt_game* g, const egt_solve_opts* o, egt_result* res, egt_state** state_out, hipStream_t s) {
   if (!g || !res) return fail(EGT_EINVAL, "null argument");
   std::memset(res, 0, sizeof(*res));
@@ -601,21 +642,8 @@ int solve(const egt_game* g, const egt_solve_opts* o, egt_result* res, egt_state
   egt_state* st = nullptr;
   int rc = state_create(g, o, s, &st);
   if (rc) return rc;
-  const egt_solve_opts& op = st->opts;
   bool converged = false;
-  for (;;) {
-    const bool check = (st->t % op.gap_every == 0) || st->t >= op.max_iters;
-    if (check) {
-      if ((rc = state_gap(st, nullptr, nullptr, nullptr, s))) break;
-      if (st->gap <= op.eps) {
-        converged = true;
-        break;
-      }
-    }
-    if (st->t >= op.max_iters) break;
-    if ((rc = state_step(st, -1, nullptr, nullptr, s))) break;
-  }
-  if (rc == EGT_OK && !st->gap_valid) rc = state_gap(st, nullptr, nullptr, nullptr, s);
+  rc = solve_loop(st, s, nullptr, &converged);
   const auto t1 = std::chrono::steady_clock::now();
   if (rc == EGT_OK) rc = fill_result(st, converged, std::chrono::duration<double>(t1 - t0).count(), res, s);
   if (rc == EGT_OK && !converged) rc = fail(EGT_ENOTCONV, "iteration cap reached before the target gap");
@@ -639,6 +667,8 @@ int64_t state_bytes(const egt_game* g, bool mixed) {
   bytes += (64 + (size_t)kMaxTrees * kMaxPartials) * sizeof(double) + 2 * 256;
   return (int64_t)bytes;
 }
+
+size_t state_host_doubles() { return 64 + (size_t)kMaxTrees * kMaxPartials; }
 
 // Accessors for the batch engine.
 const egt_solve_opts& state_opts(const egt_state* st) { return st->opts; }

@@ -86,7 +86,7 @@ def test_solve_joins_a_running_batch(egt):
     small = egt.Game(make_instance("c0", 5))
     b = egt.Batch(budget_bytes=4 << 30, max_slots=4)
     sb = b.admit(big)
-    for _ in range(30):
+    for _ in range(3):
         b.tick()
     assert b.poll(sb) is None
     ss = b.admit(small)
