@@ -172,7 +172,7 @@ int finish_player(const Enumerator& en, int p, HostPlayer& hp, std::vector<int>&
   for (int i = 0; i < nn; ++i) {
     const RawNode& rn = nodes[order[i]];
     const int na = (int)rn.acts.size();
-    if (na > kMaxActions) return fail(EGT_EINVAL, "a decision node has more than 16 actions");
+    if (na < 1 || na > kMaxActions) return fail(EGT_EINVAL, "a decision node needs 1 to 16 actions");
     hp.node_first_seq[i] = next;
     hp.node_nact[i] = na;
     hp.node_level[i] = height[order[i]];
@@ -216,6 +216,21 @@ int finish_player(const Enumerator& en, int p, HostPlayer& hp, std::vector<int>&
   hp.max_level_width = 0;
   for (int l = 0; l < hp.n_levels; ++l)
     hp.max_level_width = std::max(hp.max_level_width, hp.level_begin[l + 1] - hp.level_begin[l]);
+  // table image of the single-launch pass
+  const FusedTabLayout L = fused_tab_layout(nn, ns);
+  hp.fused_tab.assign((size_t)L.bytes, 0);
+  std::vector<int> vslot(nn, -1);
+  for (size_t j = 0; j < hp.child.size(); ++j) vslot[hp.child[j]] = (int)j;
+  for (size_t r = 0; r < hp.roots.size(); ++r) vslot[hp.roots[r]] = (int)(hp.child.size() + r);
+  unsigned char* img = hp.fused_tab.data();
+  for (int i = 0; i < nn; ++i) {
+    const int rec[4] = {hp.node_first_seq[i], hp.node_nact[i], vslot[i], 0};
+    const double prm[4] = {hp.node_beta[i], 1.0 / hp.node_beta[i], hp.node_logn[i], 0.0};
+    std::memcpy(img + L.rec + 16 * (size_t)i, rec, sizeof(rec));
+    std::memcpy(img + L.prm + 32 * (size_t)i, prm, sizeof(prm));
+  }
+  std::memcpy(img + L.cbeg, hp.child_begin.data(), sizeof(int) * (size_t)(ns + 1));
+  if (ns) std::memcpy(img + L.spar, hp.seq_parent.data(), sizeof(int) * (size_t)ns);
   return EGT_OK;
 }
 
@@ -311,13 +326,18 @@ int build_game(const egt_game_desc* d, hipStream_t stream, egt_game** out) {
       hp.term_begin[s + 1] = (int)hp.term_opp.size();
       hp.max_terms_per_seq = std::max(hp.max_terms_per_seq, (int)by[s].size());
     }
+    const int stride = std::max(1, hp.max_terms_per_seq);
+    hp.term_rec.assign((size_t)hp.n_seq * stride, TermRec{-1, -1, 0.0});
+    for (int s = 0; s < hp.n_seq; ++s)
+      for (int t = hp.term_begin[s]; t < hp.term_begin[s + 1]; ++t)
+        hp.term_rec[(size_t)s * stride + (t - hp.term_begin[s])] = TermRec{hp.term_opp[t], hp.term_kind[t], hp.term_coef[t]};
   }
   // enough 4-hand blocks to spread over the chip; 16-hand blocks for tiny hand counts
   g->fused_hands = g->ld >= 512 ? 4 : 16;
   g->fused_passes =
-      fused_lds_bytes(g->fused_hands, std::max(g->hp[0].n_nodes, g->hp[1].n_nodes),
-                      std::max(g->hp[0].n_seq, g->hp[1].n_seq),
-                      std::max((int)g->hp[0].child.size(), (int)g->hp[1].child.size())) <= kFusedLdsLimit;
+      fused_lds_bytes(g->fused_hands, (int)std::max(g->hp[0].fused_tab.size(), g->hp[1].fused_tab.size()),
+                      std::max(g->hp[0].n_nodes, g->hp[1].n_nodes),
+                      std::max(g->hp[0].n_seq, g->hp[1].n_seq)) <= kFusedLdsLimit;
   for (const RawTerminal& t : en.terms) (t.kind == 0 ? g->n_fold : g->n_show)++;
   for (int p = 0; p < 2; ++p)
     for (double b : g->hp[p].node_beta) g->max_beta = std::max(g->max_beta, b);
@@ -401,7 +421,7 @@ int build_game(const egt_game_desc* d, hipStream_t stream, egt_game** out) {
     return off;
   };
   struct Offs {
-    size_t first, nact, beta, logn, spar, cbeg, child, tbeg, topp, tkind, tcoef, roots, belief;
+    size_t first, nact, beta, logn, spar, cbeg, child, tbeg, topp, tkind, tcoef, roots, belief, ftab, trec;
   } po[2];
   for (int p = 0; p < 2; ++p) {
     HostPlayer& hp = g->hp[p];
@@ -418,9 +438,17 @@ int build_game(const egt_game_desc* d, hipStream_t stream, egt_game** out) {
     po[p].tcoef = add(hp.term_coef.data(), hp.term_coef.size() * sizeof(double));
     po[p].roots = add(hp.roots.data(), hp.roots.size() * sizeof(int));
     po[p].belief = add(b[p].data(), b[p].size() * sizeof(double));
+    po[p].ftab = add(hp.fused_tab.data(), hp.fused_tab.size());
+    po[p].trec = add(hp.term_rec.data(), hp.term_rec.size() * sizeof(TermRec));
   }
   const size_t o_cbeg = add(card_begin.data(), card_begin.size() * sizeof(int));
   const size_t o_chands = add(card_hands.data(), card_hands.size() * sizeof(int));
+  // card image for 16-byte staging: card_begin padded to 4 ints, then card_hands padded to 4 ints
+  const int chand_off = (nc + 1 + 3) / 4 * 4;
+  std::vector<int> card_img((size_t)chand_off + (card_hands.size() + 3) / 4 * 4, 0);
+  std::copy(card_begin.begin(), card_begin.end(), card_img.begin());
+  std::copy(card_hands.begin(), card_hands.end(), card_img.begin() + chand_off);
+  const size_t o_cimg = add(card_img.data(), card_img.size() * sizeof(int));
   const size_t o_ha = add(ha.data(), ha.size() * sizeof(int4));
   const size_t o_hb = add(hb.data(), hb.size() * sizeof(int4));
   const size_t o_tie = add(tie.data(), tie.size() * sizeof(int2));
@@ -461,6 +489,10 @@ int build_game(const egt_game_desc* d, hipStream_t stream, egt_game** out) {
     dp.term_coef = (const double*)at(po[p].tcoef);
     dp.roots = (const int*)at(po[p].roots);
     dp.belief = (const double*)at(po[p].belief);
+    dp.fused_tab = at(po[p].ftab);
+    dp.fused_tab16 = (int)(hp.fused_tab.size() / 16);
+    dp.term_rec = (const TermRec*)at(po[p].trec);
+    dp.term_stride = std::max(1, hp.max_terms_per_seq);
   }
   DHands& dh = g->dh;
   dh.n = n;
@@ -468,6 +500,9 @@ int build_game(const egt_game_desc* d, hipStream_t stream, egt_game** out) {
   dh.cph = cph;
   dh.n_cards = nc;
   dh.n_card_slots = card_begin[nc] + nc;
+  dh.card_img = at(o_cimg);
+  dh.card_img16 = (int)(card_img.size() / 4);
+  dh.chand_off = chand_off;
   dh.card_begin = (const int*)at(o_cbeg);
   dh.card_hands = (const int*)at(o_chands);
   dh.ha = (const int4*)at(o_ha);

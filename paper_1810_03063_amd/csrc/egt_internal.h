@@ -17,6 +17,28 @@ constexpr int kMaxDepth = 16;    // sequences on a root-to-leaf chain of one pla
 constexpr int kMaxTrees = 4;     // trees evaluated by one bottom-up launch
 constexpr size_t kGradLdsLimit = 64 * 1024;   // LDS budget of one product block
 constexpr size_t kFusedLdsLimit = 64 * 1024;  // LDS budget of one single-launch pass block
+
+// Table image of one player's treeplex for the single-launch pass, staged
+// into LDS verbatim with 16-byte copies:
+//   rec  int4[N]    {first sequence, number of actions, value slot, 0}
+//   prm  double4[N] {beta, 1 / beta, log(number of actions), 0}
+//   cbeg int[S + 1] child-slot range of each sequence (CSR over child nodes)
+//   spar int[S]     parent sequence (-1 at a root node)
+// A node's value slot is its position in the child CSR; the r-th root node
+// takes slot C + r (C = number of non-root nodes), so a sequence's children
+// occupy the contiguous slots [cbeg[s], cbeg[s + 1]).
+struct FusedTabLayout {
+  int rec, prm, cbeg, spar, bytes;
+};
+__host__ __device__ inline FusedTabLayout fused_tab_layout(int n_nodes, int n_seq) {
+  FusedTabLayout L;
+  L.rec = 0;
+  L.prm = 16 * n_nodes;
+  L.cbeg = 48 * n_nodes;
+  L.spar = L.cbeg + 4 * ((n_seq + 1 + 3) / 4 * 4);
+  L.bytes = L.spar + 4 * ((n_seq + 3) / 4 * 4);
+  return L;
+}
 constexpr int kMaxPartials = 2048 / 4;      // root partial sums per tree (4 hands per block)
 
 // ---------------------------------------------------------------------------
@@ -39,6 +61,15 @@ int hip_fail(hipError_t e, const char* what);
 
 // One player's treeplex, in level order: nodes sorted by height (height 1 =
 // no own decision below), each node's sequences contiguous.
+// One terminal of a sequence's fixed-stride terminal list: the opponent's
+// last sequence (-1 = empty), the kind (0 fold, 1 showdown, -1 = no terminal)
+// and player 2's chips there (times the sign at a showdown).
+struct TermRec {
+  int opp;
+  int kind;
+  double coef;
+};
+
 struct DPlayer {
   int n_seq;
   int n_nodes;
@@ -56,6 +87,10 @@ struct DPlayer {
   const double* term_coef;     // player 2's chips at the terminal (times the sign at a showdown)
   const int* roots;            // [n_roots] root node ids
   const double* belief;        // [ld] this player's prior in slot order, 0 in the padding
+  const void* fused_tab;       // the single-launch pass's table image (FusedTabLayout), 16-byte units
+  const TermRec* term_rec;     // [n_seq][term_stride] terminals of each sequence, padded with kind -1
+  int term_stride;             // max terminals per sequence (>= 1)
+  int fused_tab16;             // its size in 16-byte units
 };
 
 // Hands in strength-ascending slot order, with the card tables the O(n) leaf
@@ -75,6 +110,9 @@ struct DHands {
   const int4* ha;              // [n] {base, lo, hi, len} of the first card
   const int4* hb;              // [n] same for the second card (unused when cph == 1)
   const int2* tie;             // [n] {glo, ghi}
+  const void* card_img;        // card_begin (padded to 4 ints) then card_hands, for 16-byte staging
+  int card_img16;              // its size in 16-byte units
+  int chand_off;               // offset of card_hands in the image, in ints
   double invZ;                 // 1 / sum of b1 b2 over compatible deals
 };
 
@@ -93,6 +131,7 @@ struct TreePass {
   int n_levels;
   int n_child;
   int level_begin[kMaxDepth + 1];
+  int seq_level_begin[kMaxDepth + 1];  // first sequence of each level's nodes (n_seq past the end)
 };
 
 // Up to kMaxTrees independent passes evaluated by the same launches.
@@ -141,6 +180,8 @@ struct HostPlayer {
   std::vector<int> term_begin, term_opp, term_kind;
   std::vector<double> term_coef;
   std::vector<int> roots;
+  std::vector<unsigned char> fused_tab;  // table image of the single-launch pass
+  std::vector<TermRec> term_rec;         // [n_seq][max(1, max_terms_per_seq)]
   std::vector<std::string> seq_keys;
 };
 
@@ -213,7 +254,7 @@ hipError_t launch_gradient(const egt_game* g, int player, const double* v_opp, d
 hipError_t launch_passes(const egt_game* g, const Pass* p, int count, const Epilogue* epi, double* partial,
                          hipStream_t s, Prec prec = kF64);
 int n_partials(const egt_game* g);
-size_t fused_lds_bytes(int hands, int cap_nodes, int cap_seqs, int cap_child);
+size_t fused_lds_bytes(int hands, int cap_tab_bytes, int cap_nodes, int cap_seqs);
 
 // out[k] = sum of the n_partials(g) partials of tree k, in order.
 hipError_t launch_sum_partials(const egt_game* g, const double* partial, int count, double* out, hipStream_t s);

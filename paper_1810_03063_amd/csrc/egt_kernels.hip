@@ -44,7 +44,8 @@ __device__ inline double wave_inclusive_scan(double x, int lane) {
 // ---------------------------------------------------------------------------
 // Payoff product.  One block per output sequence s of `own`; the block holds
 // `groups` wave groups of 256 threads and group g evaluates the terminals
-// tb + g, tb + g + groups, ... of s concurrently with the others.  For a
+// g, g + groups, ... of s's fixed-stride terminal list concurrently with the
+// others (every table the block needs is requested at its start).  For a
 // terminal z the opponent's reach r(h') = b_o(h') v_o[sigma_o(z)][h'] is
 // staged in LDS, each thread keeping its contiguous chunk of hands in
 // registers; then
@@ -74,7 +75,8 @@ struct GradArgs {
 
 template <class TV, class TO>
 __global__ __launch_bounds__(2 * kGroupThreads) void gradient_kernel(GradArgs<TV, TO> a) {
-  extern __shared__ double lds[];
+  constexpr int kCU = 2;  // card-image loads per thread in the first batch
+  extern __shared__ __align__(16) double lds[];
   __shared__ double wave_total[2][kGroupThreads / 64];
   const int n = a.H.n, ld = a.H.ld;
   const int groups = a.groups;
@@ -84,11 +86,12 @@ __global__ __launch_bounds__(2 * kGroupThreads) void gradient_kernel(GradArgs<TV
   const int lane = tid & 63, wig = gt >> 6;
   double* R = lds + (size_t)grp * per_group;  // r, then its exclusive prefix in place [n + 1]
   double* Pc = R + (n + 1);                   // per-card exclusive prefixes [n_card_slots]
-  int* cbeg = (int*)(lds + (size_t)groups * per_group);
-  int* chand = cbeg + a.H.n_cards + 1;
+  int* cbeg = (int*)(lds + (size_t)(groups * per_group + 1) / 2 * 2);  // 16-byte aligned card image
+  const int* chand = cbeg + a.H.chand_off;
 
   const int s = blockIdx.x;
-  const int tb = a.own.term_begin[s], te = a.own.term_begin[s + 1];
+  const int MT = a.own.term_stride;
+  const TermRec* recs = a.own.term_rec + (size_t)s * MT;
   const int chunk = (n + kGroupThreads - 1) / kGroupThreads;
   const int beg = min(gt * chunk, n), end = min(beg + chunk, n), cnt = end - beg;
 
@@ -96,41 +99,68 @@ __global__ __launch_bounds__(2 * kGroupThreads) void gradient_kernel(GradArgs<TV
 #pragma unroll
   for (int k = 0; k < kMaxHandsPerThread; ++k) acc[k] = 0.0;
 
-  // the hand tables of this thread's chunk, loaded once
+  // Everything the block reads from global memory is requested up front, so
+  // the loads overlap: this group's first terminal, the hand tables and own
+  // beliefs of this thread's chunk, the opponent's prior at the strided
+  // positions this thread stages, and the card image (into LDS).
+  TermRec tr = grp < MT ? recs[grp] : TermRec{-1, -1, 0.0};
   int4 HA[kMaxHandsPerThread], HB[kMaxHandsPerThread];
   int2 TG[kMaxHandsPerThread];
+  double bown[kMaxHandsPerThread], bopp[kMaxHandsPerThread];
 #pragma unroll
   for (int k = 0; k < kMaxHandsPerThread; ++k) {
     HA[k] = make_int4(0, 0, 0, 0);
     HB[k] = make_int4(0, 0, 0, 0);
     TG[k] = make_int2(0, 0);
-  }
-  if (te > tb) {
-#pragma unroll
-    for (int k = 0; k < kMaxHandsPerThread; ++k) {
-      if (k < cnt) {
-        HA[k] = a.H.ha[beg + k];
-        HB[k] = a.H.hb[beg + k];
-        TG[k] = a.H.tie[beg + k];
-      }
+    bown[k] = 0.0;
+    bopp[k] = 0.0;
+    if (k < cnt) {
+      HA[k] = a.H.ha[beg + k];
+      if (a.H.cph == 2) HB[k] = a.H.hb[beg + k];
+      TG[k] = a.H.tie[beg + k];
+      bown[k] = a.own.belief[beg + k];
     }
-    const int n_entries = a.H.card_begin[a.H.n_cards];
-    for (int i = tid; i <= a.H.n_cards; i += blockDim.x) cbeg[i] = a.H.card_begin[i];
-    for (int i = tid; i < n_entries; i += blockDim.x) chand[i] = a.H.card_hands[i];
+    const int i = gt + k * kGroupThreads;
+    if (i < n) bopp[k] = a.b_opp[i];
   }
-  const int rounds = (te - tb + groups - 1) / groups;
+  {
+    const uint4* img = (const uint4*)a.H.card_img;
+    uint4* dst = (uint4*)cbeg;
+    const int C16 = a.H.card_img16;
+    uint4 cv[kCU];
+#pragma unroll
+    for (int u = 0; u < kCU; ++u) {
+      const int i = u * (int)blockDim.x + tid;
+      cv[u] = i < C16 ? img[i] : make_uint4(0u, 0u, 0u, 0u);
+    }
+#pragma unroll
+    for (int u = 0; u < kCU; ++u) {
+      const int i = u * (int)blockDim.x + tid;
+      if (i < C16) dst[i] = cv[u];
+    }
+    for (int i = kCU * (int)blockDim.x + tid; i < C16; i += blockDim.x) dst[i] = img[i];
+  }
+  const int rounds = (MT + groups - 1) / groups;
   for (int rd = 0; rd < rounds; ++rd) {
-    const int t = tb + rd * groups + grp;
-    bool active = t < te;  // uniform within a group
-    if (active && a.fold_only && a.own.term_kind[t] != 0) active = false;
-    int kind = 0;
-    double coef = 0.0;
+    const int j = rd * groups + grp;
+    if (rd > 0) tr = j < MT ? recs[j] : TermRec{-1, -1, 0.0};
+    // uniform within a group
+    const bool active = tr.kind >= 0 && !(a.fold_only && tr.kind != 0);
+    const int kind = tr.kind;
+    const double coef = tr.coef;
     if (active) {
-      const int opp = a.own.term_opp[t];
-      kind = a.own.term_kind[t];
-      coef = a.own.term_coef[t];
-      const TV* v = opp >= 0 ? a.v_opp + (size_t)opp * ld : nullptr;
-      for (int i = gt; i < n; i += kGroupThreads) R[i] = a.b_opp[i] * (v ? (double)v[i] : 1.0);
+      const TV* v = tr.opp >= 0 ? a.v_opp + (size_t)tr.opp * ld : nullptr;
+      double vv[kMaxHandsPerThread];
+#pragma unroll
+      for (int k = 0; k < kMaxHandsPerThread; ++k) {
+        const int i = gt + k * kGroupThreads;
+        vv[k] = (v && i < n) ? (double)v[i] : 1.0;
+      }
+#pragma unroll
+      for (int k = 0; k < kMaxHandsPerThread; ++k) {
+        const int i = gt + k * kGroupThreads;
+        if (i < n) R[i] = bopp[k] * vv[k];
+      }
     }
     __syncthreads();
     double rloc[kMaxHandsPerThread];
@@ -139,11 +169,32 @@ __global__ __launch_bounds__(2 * kGroupThreads) void gradient_kernel(GradArgs<TV
     if (active) {
 #pragma unroll
       for (int k = 0; k < kMaxHandsPerThread; ++k) rloc[k] = k < cnt ? R[beg + k] : 0.0;
-      for (int c = gt; c < a.H.n_cards; c += kGroupThreads) {
-        const int cb = cbeg[c], len = cbeg[c + 1] - cb, base = cb + c;
-        double run = 0.0;
-        int k = 0;
-        for (; k + 8 <= len; k += 8) {
+      // Per-card exclusive prefixes over the card's strength-ordered hands:
+      // four lanes per card, each a contiguous quarter of the list; the
+      // quarter offsets are added in a fixed order.
+      const int sub = gt & 3;
+      for (int c = gt >> 2; c - (gt >> 2) < a.H.n_cards; c += kGroupThreads / 4) {
+        const bool valid = c < a.H.n_cards;
+        const int cb = valid ? cbeg[c] : 0;
+        const int len = valid ? cbeg[c + 1] - cb : 0;
+        const int base = cb + c;
+        const int qlen = (len + 3) >> 2;
+        const int lo = min(sub * qlen, len), hi = min(lo + qlen, len);
+        double part = 0.0;
+        int k = lo;
+        for (; k + 8 <= hi; k += 8) {
+          double v[8];
+#pragma unroll
+          for (int j = 0; j < 8; ++j) v[j] = R[chand[cb + k + j]];
+#pragma unroll
+          for (int j = 0; j < 8; ++j) part += v[j];
+        }
+        for (; k < hi; ++k) part += R[chand[cb + k]];
+        const int l0 = lane & ~3;
+        const double p0 = __shfl(part, l0, 64), p1 = __shfl(part, l0 + 1, 64), p2 = __shfl(part, l0 + 2, 64);
+        double run = sub == 0 ? 0.0 : sub == 1 ? p0 : sub == 2 ? p0 + p1 : (p0 + p1) + p2;
+        k = lo;
+        for (; k + 8 <= hi; k += 8) {
           double v[8];
 #pragma unroll
           for (int j = 0; j < 8; ++j) v[j] = R[chand[cb + k + j]];
@@ -153,11 +204,11 @@ __global__ __launch_bounds__(2 * kGroupThreads) void gradient_kernel(GradArgs<TV
             run += v[j];
           }
         }
-        for (; k < len; ++k) {
+        for (; k < hi; ++k) {
           Pc[base + k] = run;
           run += R[chand[cb + k]];
         }
-        Pc[base + len] = run;
+        if (valid && sub == 3) Pc[base + len] = run;
       }
     }
     __syncthreads();  // the card walks have finished reading r
@@ -227,7 +278,7 @@ __global__ __launch_bounds__(2 * kGroupThreads) void gradient_kernel(GradArgs<TV
     TO* row = a.out + (size_t)s * ld;
 #pragma unroll
     for (int k = 0; k < kMaxHandsPerThread; ++k)
-      if (k < cnt) row[beg + k] = (TO)(acc[k] * (a.own.belief[beg + k] * a.H.invZ));
+      if (k < cnt) row[beg + k] = (TO)(acc[k] * (bown[k] * a.H.invZ));
     for (int i = n + gt; i < ld; i += kGroupThreads) row[i] = (TO)0;
   }
 }
@@ -242,13 +293,12 @@ __global__ __launch_bounds__(2 * kGroupThreads) void gradient_kernel(GradArgs<TV
 // The action with the smallest g~ has the largest q_bar (weight exactly 1), so
 // V is the value g~_i + temp log q_bar_i + temp log n_v at that action, and
 // every exponent is <= 0.  Tables are read through the accessor `T`, the
-// child values through `getV`, results go through `putV` / `putQ`.
+// combined gradient cA gA + cB gB through `getG`, the child values through
+// `getV`; results go through `putV` / `putQ`.
 // ---------------------------------------------------------------------------
-template <class TG, class Tab, class GetV, class PutV, class PutQ>
-__device__ __forceinline__ void node_pass(const TreePass& t, const Tab& T, int v, int h, size_t ld, GetV getV,
-                                          PutV putV, PutQ putQ, bool want_q) {
-  const TG* gA = (const TG*)t.gA;
-  const TG* gB = (const TG*)t.gB;
+template <class TG, class Tab, class GetG, class GetV, class PutV, class PutQ>
+__device__ __forceinline__ void node_pass(double mu, const Tab& T, int v, GetG getG, GetV getV, PutV putV,
+                                          PutQ putQ, bool want_q) {
   const int s0 = T.first(v);
   const int na = T.nact(v);
   double gt[kMaxActions];
@@ -257,19 +307,18 @@ __device__ __forceinline__ void node_pass(const TreePass& t, const Tab& T, int v
   for (int k = 0; k < kMaxActions; ++k) {
     if (k < na) {
       const int s = s0 + k;
-      double x = t.cA * (double)gA[(size_t)s * ld + h];
-      if (gB) x += t.cB * (double)gB[(size_t)s * ld + h];
+      double x = getG(s);
       const int c1 = T.cbeg(s + 1);
       for (int c = T.cbeg(s); c < c1; ++c) x += getV(T.child(c));
       gt[k] = x;
       m = fmin(m, x);
     }
   }
-  if (!(t.mu > 0.0)) {
+  if (!(mu > 0.0)) {
     putV(v, m);
     return;
   }
-  const double temp = t.mu * T.beta(v);
+  const double temp = mu * T.beta(v);
   const double inv_temp = 1.0 / temp;
   double sum = 0.0;
   if constexpr (std::is_same<TG, float>::value) {
@@ -309,111 +358,250 @@ struct GlobalTab {
   __device__ int child(int c) const { return P.child[c]; }
 };
 
-struct LdsTab {
-  const int* f;
-  const int* na;
-  const double* b;
-  const double* ln;
-  const int* cb;
-  const int* ch;
-  __device__ int first(int v) const { return f[v]; }
-  __device__ int nact(int v) const { return na[v]; }
-  __device__ double beta(int v) const { return b[v]; }
-  __device__ double logn(int v) const { return ln[v]; }
-  __device__ int cbeg(int s) const { return cb[s]; }
-  __device__ int child(int c) const { return ch[c]; }
-};
 
 // ---------------------------------------------------------------------------
-// Fused pass for trees whose tables fit in LDS.  Block (HB hands, tree k),
-// 64 node slots x HB hands: stage the tree's tables, run every level
-// bottom-up (node values and q_bar of these hands stay in LDS; a block
-// barrier separates the levels), write the block's partial root sum (the tree
-// value is a sum over (root, hand)), then rebuild the sequence form top-down
-// from q_bar and apply the epilogue.  Slots h >= n_hands (the row padding)
-// write zeros.
+// Fused pass for trees whose tables fit in LDS.  Block = (tree k, HB hands),
+// 64 node slots x HB hands.
+//   1. Stage in LDS, all loads in flight together: the player's table image
+//      (FusedTabLayout), the combined gradient cA gA + cB gB of the block's
+//      hands and, for the epilogue, x_prev.
+//   2. Bottom-up, one level at a time (a block barrier after each phase):
+//      (a) sequence phase (levels above the lowest): g~_s = g_s + the values
+//          of the child nodes of s, read from their contiguous value slots;
+//      (b) node phase: the smoothed (or plain) best response at each
+//          (node, hand) from the g~ of its actions, writing the node value to
+//          its slot and q_bar.  Tasks are (sequence, hand) / (node, hand)
+//          pairs spread over all threads.
+//   3. The block's partial root sum (the tree value is a sum over (root, hand)).
+//   4. Top-down, level by level from the roots: q[s] = q[parent] * q_bar[s]
+//      in place, then the epilogue (1 - tau) x_prev + tau q.  Slots h >= n
+//      (the row padding) are written 0.
+//
+// The grid is one-dimensional over (tree, hand block) and spread so that each
+// XCD (workgroups go round-robin over the 8 XCDs) gets a contiguous range of
+// hand blocks: neighbouring blocks share cache lines of every row, and those
+// then meet in one L2.
 // ---------------------------------------------------------------------------
 struct FusedArgs {
   PassSet ps;
   Epilogue epi[kMaxTrees];
-  double* partial;  // [count][gridDim.x] or null
-  int cap_nodes, cap_seqs, cap_child;
+  double* partial;  // [count][n_hblocks] or null
+  int cap_tab, cap_nodes, cap_seqs;
+  int n_hblocks;  // hand blocks per tree (ld / HB)
 };
+
+// Bijection of [0, total): workgroup L (on XCD L % 8) -> position, with each
+// XCD's workgroups on consecutive positions.
+__device__ inline int xcd_spread(int L, int total) {
+  const int q = total / 8, r = total % 8;
+  const int x = L % 8, j = L / 8;
+  return x * q + min(x, r) + j;
+}
+
+// One (node, hand) task of the node phase: g~ of the node's actions in Gl,
+// value to the node's slot in Vs, q_bar to Ql (smoothed, want_q).  Every
+// action's g~ is read up front (indices clamped into the node), so the reads
+// overlap.  temp = mu beta_v; the exponent uses (1 / mu) (1 / beta_v).
+template <class TG, int HB>
+__device__ __forceinline__ void fused_node(const int4* rec, const double2* prm, const double* Gl, double* Ql,
+                                           double* Vs, int v, int hl, double mu, double inv_mu, bool want_q) {
+  const int4 r = rec[v];
+  const int s0 = r.x, na = r.y;
+  double g[kMaxActions];
+#pragma unroll
+  for (int k = 0; k < kMaxActions; ++k) g[k] = Gl[(s0 + min(k, na - 1)) * HB + hl];
+  double m = g[0];
+#pragma unroll
+  for (int k = 1; k < kMaxActions; ++k)
+    if (k < na) m = fmin(m, g[k]);
+  if (!(mu > 0.0)) {
+    Vs[r.z * HB + hl] = m;
+    return;
+  }
+  const double2 p0 = prm[2 * v], p1 = prm[2 * v + 1];  // {beta, 1 / beta}, {log n_v, 0}
+  const double temp = mu * p0.x;
+  const double inv_temp = inv_mu * p0.y;
+  double sum = 0.0;
+  if constexpr (std::is_same<TG, float>::value) {
+    // precision form: FP32 exponentials, FP64 normaliser and value
+#pragma unroll
+    for (int k = 0; k < kMaxActions; ++k) {
+      if (k < na) {
+        g[k] = (double)expf((float)((m - g[k]) * inv_temp));
+        sum += g[k];
+      }
+    }
+  } else {
+#pragma unroll
+    for (int k = 0; k < kMaxActions; ++k) {
+      if (k < na) {
+        g[k] = exp((m - g[k]) * inv_temp);
+        sum += g[k];
+      }
+    }
+  }
+  Vs[r.z * HB + hl] = (m - temp * log(sum)) + temp * p1.x;
+  if (want_q) {
+    const double inv_sum = 1.0 / sum;
+#pragma unroll
+    for (int k = 0; k < kMaxActions; ++k)
+      if (k < na) Ql[(s0 + k) * HB + hl] = (double)(TG)(g[k] * inv_sum);
+  }
+}
 
 template <int HB, class TG>
 __global__ __launch_bounds__(kFusedSlots * HB) void sbr_fused_kernel(FusedArgs a) {
   constexpr int kThreads = kFusedSlots * HB;
-  extern __shared__ double lds[];
-  const int k = blockIdx.y;
+  constexpr int kU = 4;   // gradient loads in flight per thread and batch
+  constexpr int kTU = 2;  // table loads per thread in the first batch
+  extern __shared__ __align__(16) unsigned char fused_lds[];
+  const int nb = a.n_hblocks;
+  const int P = xcd_spread((int)blockIdx.x, (int)gridDim.x);
+  const int k = P / nb, hblk = P % nb;
   const TreePass& t = a.ps.t[k];
   const Epilogue& e = a.epi[k];
-  const int N = t.P.n_nodes, S = t.P.n_seq, C = t.n_child;
-  double* Vl = lds;                            // [cap_nodes][HB]
-  double* Ql = Vl + (size_t)a.cap_nodes * HB;  // [cap_seqs][HB]
-  double* beta = Ql + (size_t)a.cap_seqs * HB;
-  double* logn = beta + a.cap_nodes;
-  int* first = (int*)(logn + a.cap_nodes);
-  int* nact = first + a.cap_nodes;
-  int* cbeg = nact + a.cap_nodes;
-  int* child = cbeg + a.cap_seqs + 1;
-  int* spar = child + a.cap_child;
+  const int N = t.P.n_nodes, S = t.P.n_seq;
+  const FusedTabLayout L = fused_tab_layout(N, S);
+  const int4* rec = (const int4*)(fused_lds + L.rec);
+  const double2* prm = (const double2*)(fused_lds + L.prm);
+  const int* cbeg = (const int*)(fused_lds + L.cbeg);
+  const int* spar = (const int*)(fused_lds + L.spar);
+  double* Gl = (double*)(fused_lds + a.cap_tab);  // [cap_seqs][HB] gradient, then g~
+  double* Ql = Gl + (size_t)a.cap_seqs * HB;      // [cap_seqs][HB] q_bar, then q
+  double* Xl = Ql + (size_t)a.cap_seqs * HB;      // [cap_seqs][HB] x_prev of the epilogue
+  double* Vs = Xl + (size_t)a.cap_seqs * HB;      // [cap_nodes][HB] node values by slot
   const int tid = threadIdx.x;
-  for (int i = tid; i < N; i += kThreads) {
-    first[i] = t.P.node_first_seq[i];
-    nact[i] = t.P.node_nact[i];
-    beta[i] = t.P.node_beta[i];
-    logn[i] = t.P.node_logn[i];
+  const int h0 = hblk * HB, n = a.ps.n;
+  const size_t ld = a.ps.ld;
+  const int SH = S * HB;
+
+  // 1. staging
+  const uint4* tab = (const uint4*)t.P.fused_tab;
+  uint4* tl = (uint4*)fused_lds;
+  const int T16 = t.P.fused_tab16;
+  const TG* gA = (const TG*)t.gA;
+  const TG* gB = (const TG*)t.gB;
+  const TG* x_prev = (const TG*)e.x_prev;
+  const bool want_x = e.comb_out != nullptr;
+  uint4 tb[kTU];
+#pragma unroll
+  for (int u = 0; u < kTU; ++u) {
+    const int i = u * kThreads + tid;
+    tb[u] = i < T16 ? tab[i] : make_uint4(0u, 0u, 0u, 0u);
   }
-  for (int i = tid; i <= S; i += kThreads) cbeg[i] = t.P.child_begin[i];
-  for (int i = tid; i < C; i += kThreads) child[i] = t.P.child[i];
-  for (int i = tid; i < S; i += kThreads) spar[i] = t.P.seq_parent[i];
+  for (int base = 0; base < SH; base += kThreads * kU) {
+    double va[kU], vb[kU], vx[kU];
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+      const int i = base + u * kThreads + tid;
+      const int hh = h0 + i % HB;
+      va[u] = vb[u] = vx[u] = 0.0;
+      if (i < SH && hh < n) {
+        const size_t idx = (size_t)(i / HB) * ld + hh;
+        va[u] = (double)gA[idx];
+        if (gB) vb[u] = (double)gB[idx];
+        if (want_x) vx[u] = (double)x_prev[idx];
+      }
+    }
+    if (base == 0) {
+#pragma unroll
+      for (int u = 0; u < kTU; ++u) {
+        const int i = u * kThreads + tid;
+        if (i < T16) tl[i] = tb[u];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+      const int i = base + u * kThreads + tid;
+      if (i < SH) {
+        double x = t.cA * va[u];
+        if (gB) x += t.cB * vb[u];
+        Gl[i] = x;
+        if (want_x) Xl[i] = vx[u];
+      }
+    }
+  }
+  if (SH == 0) {
+#pragma unroll
+    for (int u = 0; u < kTU; ++u) {
+      const int i = u * kThreads + tid;
+      if (i < T16) tl[i] = tb[u];
+    }
+  }
+  for (int i = kTU * kThreads + tid; i < T16; i += kThreads) tl[i] = tab[i];
   __syncthreads();
 
-  const LdsTab T{first, nact, beta, logn, cbeg, child};
-  const int hl = tid % HB, slot = tid / HB;
-  const int h = blockIdx.x * HB + hl;
-  const bool live = h < a.ps.n;
+  // 2. bottom-up
   const bool want_q = (e.q_out || e.comb_out) && t.mu > 0.0;
-  const size_t ld = a.ps.ld;
-  auto getV = [&](int c) { return Vl[c * HB + hl]; };
-  auto putV = [&](int v, double x) { Vl[v * HB + hl] = x; };
-  auto putQ = [&](int s, TG q) { Ql[s * HB + hl] = (double)q; };
+  const double mu = t.mu;
+  const double inv_mu = mu > 0.0 ? 1.0 / mu : 0.0;
   for (int l = 0; l < t.n_levels; ++l) {
-    if (live)
-      for (int v = t.level_begin[l] + slot; v < t.level_begin[l + 1]; v += kFusedSlots)
-        node_pass<TG>(t, T, v, h, ld, getV, putV, putQ, want_q);
+    if (l > 0) {
+      const int sb0 = t.seq_level_begin[l], cnt = (t.seq_level_begin[l + 1] - sb0) * HB;
+      for (int i = tid; i < cnt; i += kThreads) {
+        const int s = sb0 + i / HB, hl = i % HB;
+        const int c0 = cbeg[s], c1 = cbeg[s + 1];
+        if (h0 + hl >= n || c0 == c1) continue;
+        double x = Gl[s * HB + hl];
+        int c = c0;
+        for (; c + 4 <= c1; c += 4) {
+          const double v0 = Vs[c * HB + hl], v1 = Vs[(c + 1) * HB + hl];
+          const double v2 = Vs[(c + 2) * HB + hl], v3 = Vs[(c + 3) * HB + hl];
+          x += v0;
+          x += v1;
+          x += v2;
+          x += v3;
+        }
+        for (; c < c1; ++c) x += Vs[c * HB + hl];
+        Gl[s * HB + hl] = x;
+      }
+      __syncthreads();
+    }
+    const int nb0 = t.level_begin[l], cnt = (t.level_begin[l + 1] - nb0) * HB;
+    for (int i = tid; i < cnt; i += kThreads) {
+      const int v = nb0 + i / HB, hl = i % HB;
+      if (h0 + hl < n) fused_node<TG, HB>(rec, prm, Gl, Ql, Vs, v, hl, mu, inv_mu, want_q);
+    }
     __syncthreads();
   }
+
+  // 3. partial root sum
   if (a.partial && tid < HB) {
     double sv = 0.0;
-    if (live)
-      for (int r = 0; r < t.P.n_roots; ++r) sv += Vl[t.P.roots[r] * HB + hl];
+    if (h0 + tid < n) {
+      const int C = N - t.P.n_roots;
+      for (int r = 0; r < t.P.n_roots; ++r) sv += Vs[(C + r) * HB + tid];
+    }
 #pragma unroll
     for (int off = HB / 2; off > 0; off >>= 1) sv += __shfl_down(sv, off, HB);
-    if (tid == 0) a.partial[(size_t)k * gridDim.x + blockIdx.x] = sv;
+    if (tid == 0) a.partial[(size_t)k * nb + hblk] = sv;
   }
+
+  // 4. top-down and epilogue
   if (e.q_out || e.comb_out) {
+    for (int l = t.n_levels - 1; l >= 0; --l) {
+      const int sb0 = t.seq_level_begin[l], cnt = (t.seq_level_begin[l + 1] - sb0) * HB;
+      for (int i = tid; i < cnt; i += kThreads) {
+        const int s = sb0 + i / HB, hl = i % HB;
+        const int par = spar[s];
+        if (h0 + hl < n && par >= 0) Ql[s * HB + hl] = (double)((TG)Ql[par * HB + hl] * (TG)Ql[s * HB + hl]);
+      }
+      __syncthreads();
+    }
     TG* q_out = (TG*)e.q_out;
     TG* comb_out = (TG*)e.comb_out;
-    const TG* x_prev = (const TG*)e.x_prev;
     const TG tau = (TG)e.tau, one_m_tau = (TG)(1.0 - e.tau);
-    for (int s = slot; s < S; s += kFusedSlots) {
-      const size_t idx = (size_t)s * ld + h;
-      if (!live) {
+    for (int i = tid; i < SH; i += kThreads) {
+      const int hh = h0 + i % HB;
+      const size_t idx = (size_t)(i / HB) * ld + hh;
+      if (hh >= n) {
         if (q_out) q_out[idx] = (TG)0;
         if (comb_out) comb_out[idx] = (TG)0;
         continue;
       }
-      int depth = 0;
-      for (int q = s; q >= 0; q = spar[q]) ++depth;
-      TG val = (TG)1;
-      for (int j = depth - 1; j >= 0; --j) {
-        int q = s;
-        for (int i = 0; i < j; ++i) q = spar[q];
-        val *= (TG)Ql[q * HB + hl];
-      }
-      if (q_out) q_out[idx] = val;
-      if (comb_out) comb_out[idx] = one_m_tau * x_prev[idx] + tau * val;
+      const TG q = (TG)Ql[i];
+      if (q_out) q_out[idx] = q;
+      if (comb_out) comb_out[idx] = one_m_tau * (TG)Xl[i] + tau * q;
     }
   }
 }
@@ -432,10 +620,17 @@ __global__ __launch_bounds__(kPassThreads) void bottom_up_level_kernel(PassSet a
   if (h >= a.n) return;
   const size_t ld = a.ld;
   const GlobalTab T{t.P};
+  const TG* gA = (const TG*)t.gA;
+  const TG* gB = (const TG*)t.gB;
+  auto getG = [&](int s) {
+    double x = t.cA * (double)gA[(size_t)s * ld + h];
+    if (gB) x += t.cB * (double)gB[(size_t)s * ld + h];
+    return x;
+  };
   auto getV = [&](int c) { return t.V[(size_t)c * ld + h]; };
   auto putV = [&](int v, double x) { t.V[(size_t)v * ld + h] = x; };
   auto putQ = [&](int s, TG q) { ((TG*)t.QB)[(size_t)s * ld + h] = q; };
-  node_pass<TG>(t, T, t.level_begin[a.level] + y, h, ld, getV, putV, putQ, t.QB != nullptr);
+  node_pass<TG>(t.mu, T, t.level_begin[a.level] + y, getG, getV, putV, putQ, t.QB != nullptr);
 }
 
 // Root sums of the level path: block k sums tree k, roots in order, hands
@@ -570,13 +765,13 @@ static hipError_t gradient_launch(const egt_game* g, int player, const TV* v_opp
   a.out = grad_out;
   a.show_sign = player == 0 ? 1.0 : -1.0;
   a.fold_only = fold_only;
-  const int n_entries = g->dh.n_card_slots - g->dh.n_cards;  // hands x cards per hand
-  const size_t per_group = sizeof(double) * (size_t)(g->n + 1 + g->dh.n_card_slots);
-  const size_t shared_ints = sizeof(int) * (size_t)(g->dh.n_cards + 1 + n_entries);
+  const size_t per_group = (size_t)(g->n + 1 + g->dh.n_card_slots);  // doubles
+  const size_t card_bytes = 16 * (size_t)g->dh.card_img16;
+  auto lds_bytes = [&](int gr) { return sizeof(double) * ((gr * per_group + 1) / 2 * 2) + card_bytes; };
   int groups = g->hp[player].max_terms_per_seq >= 2 ? 2 : 1;
-  if (groups == 2 && 2 * per_group + shared_ints > kGradLdsLimit) groups = 1;
+  if (groups == 2 && lds_bytes(2) > kGradLdsLimit) groups = 1;
   a.groups = groups;
-  const size_t lds = groups * per_group + shared_ints;
+  const size_t lds = lds_bytes(groups);
   hipLaunchKernelGGL((gradient_kernel<TV, TO>), dim3(g->dp[player].n_seq), dim3(kGroupThreads * groups), lds, s, a);
   return hipGetLastError();
 }
@@ -614,15 +809,18 @@ static void fill_pass_set(const egt_game* g, const Pass* p, int count, PassSet& 
     t.QB = p[k].QB;
     t.n_levels = hp.n_levels;
     t.n_child = (int)hp.child.size();
-    for (int l = 0; l <= kMaxDepth; ++l) t.level_begin[l] = hp.level_begin[std::min(l, hp.n_levels)];
+    for (int l = 0; l <= kMaxDepth; ++l) {
+      const int lb = hp.level_begin[std::min(l, hp.n_levels)];
+      t.level_begin[l] = lb;
+      t.seq_level_begin[l] = lb < hp.n_nodes ? hp.node_first_seq[lb] : hp.n_seq;
+    }
   }
 }
 
 int n_partials(const egt_game* g) { return g->fused_passes ? g->ld / g->fused_hands : 1; }
 
-size_t fused_lds_bytes(int hands, int cap_nodes, int cap_seqs, int cap_child) {
-  return sizeof(double) * ((size_t)(cap_nodes + cap_seqs) * hands + 2 * (size_t)cap_nodes) +
-         sizeof(int) * (2 * (size_t)cap_nodes + (cap_seqs + 1) + cap_child + cap_seqs);
+size_t fused_lds_bytes(int hands, int cap_tab_bytes, int cap_nodes, int cap_seqs) {
+  return (size_t)cap_tab_bytes + sizeof(double) * (3 * (size_t)cap_seqs + (size_t)cap_nodes) * hands;
 }
 
 template <class TG>
@@ -634,12 +832,13 @@ static hipError_t passes_launch(const egt_game* g, const Pass* p, int count, con
     for (int k = 0; k < kMaxTrees; ++k)
       a.epi[k] = (epi && k < count) ? epi[k] : Epilogue{nullptr, nullptr, 0.0, nullptr};
     a.partial = partial;
+    a.cap_tab = (int)std::max(g->hp[0].fused_tab.size(), g->hp[1].fused_tab.size());
     a.cap_nodes = std::max(g->hp[0].n_nodes, g->hp[1].n_nodes);
     a.cap_seqs = std::max(g->hp[0].n_seq, g->hp[1].n_seq);
-    a.cap_child = std::max((int)g->hp[0].child.size(), (int)g->hp[1].child.size());
     const int hb = g->fused_hands;
-    const size_t lds = fused_lds_bytes(hb, a.cap_nodes, a.cap_seqs, a.cap_child);
-    const dim3 grid(g->ld / hb, count);
+    const size_t lds = fused_lds_bytes(hb, a.cap_tab, a.cap_nodes, a.cap_seqs);
+    a.n_hblocks = g->ld / hb;
+    const dim3 grid((unsigned)(a.n_hblocks * count));
     if (hb == 4)
       hipLaunchKernelGGL((sbr_fused_kernel<4, TG>), grid, dim3(kFusedSlots * 4), lds, s, a);
     else
