@@ -213,6 +213,7 @@ struct MixedTables {
   const int* col_own[2] = {nullptr, nullptr};
   const int* col_opp[2] = {nullptr, nullptr};
   const double* col_coef[2] = {nullptr, nullptr};
+  const float* belief32[2] = {nullptr, nullptr};  // [ld] each player's prior in FP32
 };
 
 }  // namespace egt

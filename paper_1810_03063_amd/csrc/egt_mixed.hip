@@ -30,10 +30,10 @@ namespace {
 typedef __attribute__((__vector_size__(8 * sizeof(short)))) short bf16x8;
 typedef __attribute__((__vector_size__(16 * sizeof(float)))) float f32x16;
 
-constexpr int kBM = 64;  // output hands per block
-constexpr int kBN = 64;  // showdown columns per block
-constexpr int kBK = 32;  // hands contracted per LDS stage
-constexpr int kLdsStride = kBK + 8;  // bf16 per LDS row, padded against bank conflicts
+constexpr int kTile = 32;     // output hands x showdown columns per block (one 32x32 MFMA tile)
+constexpr int kKWaves = 16;   // waves per block, each contracting every 16th k-step of 16 hands
+constexpr int kBatch = 3;     // k-steps whose operands a wave loads before multiplying
+constexpr int kRedStride = kTile + 1;
 
 __device__ inline unsigned short bf16_rn(float f) {
   unsigned u = __float_as_uint(f);
@@ -44,103 +44,103 @@ __device__ inline unsigned short bf16_rn(float f) {
 __device__ inline float bf16_to_f32(unsigned short b) { return __uint_as_float(((unsigned)b) << 16); }
 
 struct GemmArgs {
-  const unsigned short* W;  // [kpad][kpad] BF16 bits, row h, contiguous h'
-  int kpad;
+  const unsigned short* W;  // [ld][ld] BF16 bits, row h, contiguous h'
   int n, ld;
   int L;                    // showdown columns of the own player
   const int* col_own;       // [L] own sequence of the column
   const int* col_opp;       // [L] opponent sequence (-1 = empty sequence)
   const double* col_coef;   // [L] player-2 chips at the terminal
-  const double* b_opp;      // [ld]
+  const float* b_opp32;     // [ld] opponent prior in FP32
   const double* b_own;      // [ld]
   double scale;             // sign / Z
   const float* v_opp;       // opponent strategy [S_o][ld]
   float* out;               // own gradient [S_own][ld], fold part already written
 };
 
-__global__ __launch_bounds__(256) void show_gemm_kernel(GemmArgs a) {
-  __shared__ __attribute__((aligned(16))) unsigned short As[2][kBM * kLdsStride];
-  __shared__ __attribute__((aligned(16))) unsigned short Bh[2][kBN * kLdsStride];
-  __shared__ __attribute__((aligned(16))) unsigned short Bl[2][kBN * kLdsStride];
+// One 32 x 32 output tile (hands m0.., columns n0..) per block.  The k-steps
+// of 16 hands are dealt round-robin to the 16 waves; each wave loads the
+// operands of kBatch steps straight into registers (no reuse inside a block,
+// so no LDS staging), forms the FP32 reach, splits it into BF16 hi + lo and
+// issues two 32x32x16 MFMAs per step.  The 16 partial tiles are summed
+// through LDS in wave order, and one lane per output element applies the
+// epilogue.
+// Operand layouts of v_mfma_f32_32x32x16_bf16 (lane l, element e < 8):
+//   A[l % 32][8 (l / 32) + e], B[8 (l / 32) + e][l % 32];
+//   accumulator r: row (r / 4) 8 + (l / 32) 4 + r % 4, column l % 32.
+__global__ __launch_bounds__(64 * kKWaves) void show_gemm_kernel(GemmArgs a) {
+  __shared__ float red[kKWaves * kTile * kRedStride];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int m0 = blockIdx.y * kBM, n0 = blockIdx.x * kBN;
-  const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
-  // staging roles: 64 rows (or columns) x 32 k = 256 threads x 8 elements
-  const int srow = tid >> 2, skk = (tid & 3) * 8;
-  const int j = n0 + srow;
-  const bool jvalid = j < a.L;
+  const int m0 = blockIdx.y * kTile, n0 = blockIdx.x * kTile;
+  const int half = lane >> 5, l32 = lane & 31;
+  const int col = n0 + l32;
   const float* vrow = nullptr;
-  if (jvalid) {
-    const int o = a.col_opp[j];
+  const bool cvalid = col < a.L;
+  if (cvalid) {
+    const int o = a.col_opp[col];
     vrow = o >= 0 ? a.v_opp + (size_t)o * a.ld : nullptr;
   }
-  uint4 areg;
-  float breg[8];
-  auto load = [&](int ks) {
-    const int k0 = ks * kBK + skk;
-    areg = *(const uint4*)(a.W + (size_t)(m0 + srow) * a.kpad + k0);
-#pragma unroll
-    for (int e = 0; e < 8; ++e) {
-      const int k = k0 + e;
-      float r = 0.0f;
-      if (jvalid && k < a.n) r = (float)(a.b_opp[k] * (vrow ? (double)vrow[k] : 1.0));
-      breg[e] = r;
-    }
-  };
-  auto store = [&](int buf) {
-    *(uint4*)&As[buf][srow * kLdsStride + skk] = areg;
-    unsigned short hi[8], lo[8];
-#pragma unroll
-    for (int e = 0; e < 8; ++e) {
-      hi[e] = bf16_rn(breg[e]);
-      lo[e] = bf16_rn(breg[e] - bf16_to_f32(hi[e]));
-    }
-    uint4 ph, pl;
-    ph.x = hi[0] | ((unsigned)hi[1] << 16);
-    ph.y = hi[2] | ((unsigned)hi[3] << 16);
-    ph.z = hi[4] | ((unsigned)hi[5] << 16);
-    ph.w = hi[6] | ((unsigned)hi[7] << 16);
-    pl.x = lo[0] | ((unsigned)lo[1] << 16);
-    pl.y = lo[2] | ((unsigned)lo[3] << 16);
-    pl.z = lo[4] | ((unsigned)lo[5] << 16);
-    pl.w = lo[6] | ((unsigned)lo[7] << 16);
-    *(uint4*)&Bh[buf][srow * kLdsStride + skk] = ph;
-    *(uint4*)&Bl[buf][srow * kLdsStride + skk] = pl;
-  };
+  const unsigned short* wrow = a.W + (size_t)(m0 + l32) * a.ld + 8 * half;
+  const int nk = a.ld / 16;
 
   f32x16 acc;
 #pragma unroll
   for (int r = 0; r < 16; ++r) acc[r] = 0.0f;
-  const int ksteps = a.kpad / kBK;
-  load(0);
-  store(0);
-  __syncthreads();
-  for (int ks = 0; ks < ksteps; ++ks) {
-    const int buf = ks & 1;
-    if (ks + 1 < ksteps) load(ks + 1);  // next stage's global loads overlap the MFMAs
+  for (int base = wave; base < nk; base += kKWaves * kBatch) {
+    uint4 av[kBatch];
+    float4 v0[kBatch], v1[kBatch], b0[kBatch], b1[kBatch];
 #pragma unroll
-    for (int kk = 0; kk < kBK; kk += 16) {
-      const int koff = kk + 8 * (lane >> 5);
-      const bf16x8 av = *(const bf16x8*)&As[buf][(wm + (lane & 31)) * kLdsStride + koff];
-      const bf16x8 bh = *(const bf16x8*)&Bh[buf][(wn + (lane & 31)) * kLdsStride + koff];
-      const bf16x8 bl = *(const bf16x8*)&Bl[buf][(wn + (lane & 31)) * kLdsStride + koff];
-      acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, bh, acc, 0, 0, 0);
-      acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, bl, acc, 0, 0, 0);
+    for (int u = 0; u < kBatch; ++u) {
+      const int ks = base + u * kKWaves;
+      av[u] = make_uint4(0u, 0u, 0u, 0u);
+      v0[u] = v1[u] = make_float4(1.0f, 1.0f, 1.0f, 1.0f);
+      b0[u] = b1[u] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+      if (ks < nk) {
+        const int k0 = ks * 16 + 8 * half;
+        av[u] = *(const uint4*)(wrow + ks * 16);
+        if (cvalid) {
+          if (vrow) {
+            v0[u] = *(const float4*)(vrow + k0);
+            v1[u] = *(const float4*)(vrow + k0 + 4);
+          }
+          b0[u] = *(const float4*)(a.b_opp32 + k0);
+          b1[u] = *(const float4*)(a.b_opp32 + k0 + 4);
+        }
+      }
     }
-    if (ks + 1 < ksteps) store(buf ^ 1);
-    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < kBatch; ++u) {
+      if (base + u * kKWaves >= nk) break;  // uniform within the wave
+      // FP32 reach of the 8 hands, split into BF16 hi + lo
+      const float r[8] = {b0[u].x * v0[u].x, b0[u].y * v0[u].y, b0[u].z * v0[u].z, b0[u].w * v0[u].w,
+                          b1[u].x * v1[u].x, b1[u].y * v1[u].y, b1[u].z * v1[u].z, b1[u].w * v1[u].w};
+      bf16x8 hi, lo;
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const unsigned short h16 = bf16_rn(r[e]);
+        hi[e] = (short)h16;
+        lo[e] = (short)bf16_rn(r[e] - bf16_to_f32(h16));
+      }
+      const bf16x8 am = *(const bf16x8*)&av[u];
+      acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(am, hi, acc, 0, 0, 0);
+      acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(am, lo, acc, 0, 0, 0);
+    }
   }
-  // accumulator r of lane l holds C[row][col], col = l % 32,
-  // row = (r / 4) * 8 + (l / 32) * 4 + r % 4 within the wave's 32 x 32 tile
-  const int jc = n0 + wn + (lane & 31);
-  if (jc < a.L) {
-    const double c = a.col_coef[jc] * a.scale;
-    float* row = a.out + (size_t)a.col_own[jc] * a.ld;
+  // partial tiles to LDS as red[wave][column][row]
 #pragma unroll
-    for (int r = 0; r < 16; ++r) {
-      const int h = m0 + wm + (r >> 2) * 8 + (lane >> 5) * 4 + (r & 3);
-      if (h < a.n) row[h] += (float)(c * a.b_own[h] * (double)acc[r]);
-    }
+  for (int r = 0; r < 16; ++r) {
+    const int row = (r >> 2) * 8 + half * 4 + (r & 3);
+    red[(wave * kTile + l32) * kRedStride + row] = acc[r];
+  }
+  __syncthreads();
+  // one lane per output element: hands fastest, so each row is written coalesced
+  const int h = m0 + (tid & 31), cl = tid >> 5, j = n0 + cl;
+  if (j < a.L && h < a.n) {
+    float sum = 0.0f;
+#pragma unroll
+    for (int w = 0; w < kKWaves; ++w) sum += red[(w * kTile + cl) * kRedStride + (tid & 31)];
+    const double c = a.col_coef[j] * a.scale;
+    float* row = a.out + (size_t)a.col_own[j] * a.ld;
+    row[h] += (float)(c * a.b_own[h] * (double)sum);
   }
 }
 
@@ -152,7 +152,7 @@ int ensure_mixed_tables(const egt_game* cg) {
   egt_game* g = const_cast<egt_game*>(cg);  // cached tables owned by the game
   if (g->mx.block) return EGT_OK;
   const int n = g->n;
-  const int kpad = (n + kBM - 1) / kBM * kBM;
+  const int kpad = g->ld;  // rows and columns padded like every vector
   // slot order: strength ascending; compatibility from the cards of the slots
   std::vector<unsigned short> W((size_t)kpad * kpad, 0);
   for (int i = 0; i < n; ++i) {
@@ -181,10 +181,22 @@ int ensure_mixed_tables(const egt_game* cg) {
       }
     }
   }
+  // FP32 copies of the priors (the reach b v is formed in FP32)
+  std::vector<float> b32[2];
+  for (int p = 0; p < 2; ++p) {
+    std::vector<double> b64((size_t)g->ld);
+    const hipError_t e = hipMemcpy(b64.data(), g->dp[p].belief, sizeof(double) * b64.size(), hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_fail(e, "read-back of the priors");
+    b32[p].assign(b64.begin(), b64.end());
+  }
   size_t bytes = sizeof(unsigned short) * W.size();
   auto al = [](size_t x) { return (x + 255) / 256 * 256; };
-  size_t off_cols[2][3];
+  size_t off_cols[2][3], off_b32[2];
   size_t total = al(bytes);
+  for (int p = 0; p < 2; ++p) {
+    off_b32[p] = total;
+    total += al(sizeof(float) * b32[p].size());
+  }
   for (int p = 0; p < 2; ++p) {
     off_cols[p][0] = total;
     total += al(sizeof(int) * std::max<size_t>(own[p].size(), 1));
@@ -195,6 +207,7 @@ int ensure_mixed_tables(const egt_game* cg) {
   }
   std::vector<unsigned char> staging(total, 0);
   std::memcpy(staging.data(), W.data(), bytes);
+  for (int p = 0; p < 2; ++p) std::memcpy(staging.data() + off_b32[p], b32[p].data(), sizeof(float) * b32[p].size());
   for (int p = 0; p < 2; ++p) {
     if (!own[p].empty()) {
       std::memcpy(staging.data() + off_cols[p][0], own[p].data(), sizeof(int) * own[p].size());
@@ -217,6 +230,7 @@ int ensure_mixed_tables(const egt_game* cg) {
     g->mx.col_own[p] = (const int*)((unsigned char*)dev + off_cols[p][0]);
     g->mx.col_opp[p] = (const int*)((unsigned char*)dev + off_cols[p][1]);
     g->mx.col_coef[p] = (const double*)((unsigned char*)dev + off_cols[p][2]);
+    g->mx.belief32[p] = (const float*)((unsigned char*)dev + off_b32[p]);
   }
   g->mx.block = dev;
   return EGT_OK;
@@ -227,20 +241,19 @@ hipError_t launch_show_gemm(const egt_game* g, int player, const float* v_opp, f
   if (m.L[player] == 0) return hipSuccess;
   GemmArgs a;
   a.W = m.W;
-  a.kpad = m.kpad;
   a.n = g->n;
   a.ld = g->ld;
   a.L = m.L[player];
   a.col_own = m.col_own[player];
   a.col_opp = m.col_opp[player];
   a.col_coef = m.col_coef[player];
-  a.b_opp = g->dp[1 - player].belief;
+  a.b_opp32 = m.belief32[1 - player];
   a.b_own = g->dp[player].belief;
   a.scale = (player == 0 ? 1.0 : -1.0) / g->Z;
   a.v_opp = v_opp;
   a.out = grad_out;
-  const dim3 grid((unsigned)((a.L + kBN - 1) / kBN), (unsigned)(m.kpad / kBM));
-  hipLaunchKernelGGL(show_gemm_kernel, grid, dim3(256), 0, s, a);
+  const dim3 grid((unsigned)((a.L + kTile - 1) / kTile), (unsigned)(g->ld / kTile));
+  hipLaunchKernelGGL(show_gemm_kernel, grid, dim3(64 * kKWaves), 0, s, a);
   return hipGetLastError();
 }
 
