@@ -150,6 +150,8 @@ struct Epilogue {
   const void* x_prev;
   double tau;
   void* comb_out;
+  void* g_out;     // single-launch pass only: g_scale (cA gA + cB gB) of this tree, or null
+  double g_scale;
 };
 
 // Host description of one pass (player instead of device tables).
@@ -249,9 +251,11 @@ hipError_t launch_gradient(const egt_game* g, int player, const double* v_opp, d
 // count (1..kMaxTrees) independent passes in as few launches as possible:
 // bottom-up over every level; when `partial` is not null, the tree values as
 // n_partials(g) partial sums per tree (partial[k * n_partials + b], to be
-// added in order of b); when epi[k] asks for it, the top-down rebuild of
-// tree k's strategy with its epilogue.  On the level path a smoothed pass
-// with an epilogue needs its QB buffer.
+// added in order of b; partial may be the device address of pinned host
+// memory, read after the stream is synchronised); when epi[k] asks for it,
+// the top-down rebuild of tree k's strategy with its epilogue.  On the level
+// path a smoothed pass with an epilogue needs its QB buffer, and g_out is not
+// produced.
 hipError_t launch_passes(const egt_game* g, const Pass* p, int count, const Epilogue* epi, double* partial,
                          hipStream_t s, Prec prec = kF64);
 int n_partials(const egt_game* g);

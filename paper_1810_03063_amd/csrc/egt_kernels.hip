@@ -385,7 +385,7 @@ struct GlobalTab {
 struct FusedArgs {
   PassSet ps;
   Epilogue epi[kMaxTrees];
-  double* partial;  // [count][n_hblocks] or null
+  double* partial;  // [count][n_hblocks] or null (device or pinned host memory)
   int cap_tab, cap_nodes, cap_seqs;
   int n_hblocks;  // hand blocks per tree (ld / HB)
 };
@@ -483,6 +483,7 @@ __global__ __launch_bounds__(kFusedSlots * HB) void sbr_fused_kernel(FusedArgs a
   const TG* gB = (const TG*)t.gB;
   const TG* x_prev = (const TG*)e.x_prev;
   const bool want_x = e.comb_out != nullptr;
+  TG* g_out = (TG*)e.g_out;
   uint4 tb[kTU];
 #pragma unroll
   for (int u = 0; u < kTU; ++u) {
@@ -518,6 +519,7 @@ __global__ __launch_bounds__(kFusedSlots * HB) void sbr_fused_kernel(FusedArgs a
         if (gB) x += t.cB * vb[u];
         Gl[i] = x;
         if (want_x) Xl[i] = vx[u];
+        if (g_out) g_out[(size_t)(i / HB) * ld + h0 + i % HB] = (TG)(x * e.g_scale);  // 0 in the padding
       }
     }
   }
@@ -830,7 +832,7 @@ static hipError_t passes_launch(const egt_game* g, const Pass* p, int count, con
     FusedArgs a;
     fill_pass_set(g, p, count, a.ps);
     for (int k = 0; k < kMaxTrees; ++k)
-      a.epi[k] = (epi && k < count) ? epi[k] : Epilogue{nullptr, nullptr, 0.0, nullptr};
+      a.epi[k] = (epi && k < count) ? epi[k] : Epilogue{nullptr, nullptr, 0.0, nullptr, nullptr, 0.0};
     a.partial = partial;
     a.cap_tab = (int)std::max(g->hp[0].fused_tab.size(), g->hp[1].fused_tab.size());
     a.cap_nodes = std::max(g->hp[0].n_nodes, g->hp[1].n_nodes);

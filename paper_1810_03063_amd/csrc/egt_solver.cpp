@@ -62,8 +62,8 @@ struct egt_state {
   double* S64 = nullptr;    // FP64 q_bar scratch of the start-up (precision form)
   double* dscal = nullptr;  // device scalars
   double* hscal = nullptr;  // pinned host mirror (also the summed tree values)
-  double* dpart = nullptr;  // device root partial sums [trees][n_partials]
-  double* hpart = nullptr;  // pinned host mirror
+  double* hpart = nullptr;      // pinned root partial sums [trees][n_partials], written by the kernels
+  double* hpart_dev = nullptr;  // device address of hpart
   void* block = nullptr;
   bool owns_memory = true;  // false: block and hscal belong to a serving batch
   // saddle gap of the current iterate (valid when gap_valid)
@@ -119,16 +119,20 @@ int axpby(egt_state* st, int p, double a, const void* X, double b, const void* Y
   return EGT_OK;
 }
 
-// Enqueues the copy of the root partial sums of `trees` trees to the host.
-int enqueue_values(egt_state* st, int trees, hipStream_t s) {
-  const int nb = n_partials(st->g);
-  EGT_TRY(hipMemcpyAsync(st->hpart, st->dpart, sizeof(double) * trees * nb, hipMemcpyDeviceToHost, s));
+// The value launch of `trees` trees writes their partial sums into pinned
+// host memory; record how many to read.
+int enqueue_values(egt_state* st, int trees, hipStream_t) {
   st->pending_trees = trees;
   return EGT_OK;
 }
 
-// Waits for the enqueued copy and adds each tree's partials in order into hscal[k].
+// Waits for the stream (polling, which wakes up sooner than a blocking wait)
+// and adds each tree's partials in order into hscal[k].
 int finish_values(egt_state* st, hipStream_t s) {
+  hipError_t e;
+  while ((e = hipStreamQuery(s)) == hipErrorNotReady) {
+  }
+  if (e != hipSuccess) return hip_fail(e, "hipStreamQuery");
   EGT_TRY(hipStreamSynchronize(s));
   const int nb = n_partials(st->g);
   const int trees = st->pending_trees;
@@ -159,7 +163,7 @@ int fetch(egt_state* st, int count, hipStream_t s) {
 int egv_current(egt_state* st, hipStream_t s) {
   const Pass ps[2] = {{0, st->G[0], kSg[0], nullptr, 0.0, st->mu[0], st->V[0], nullptr},
                       {1, st->G[1], kSg[1], nullptr, 0.0, st->mu[1], st->V[1], nullptr}};
-  EGT_TRY(launch_passes(st->g, ps, 2, nullptr, st->dpart, s, st->prec));
+  EGT_TRY(launch_passes(st->g, ps, 2, nullptr, st->hpart_dev, s, st->prec));
   return EGT_OK;
 }
 
@@ -205,6 +209,7 @@ int narrow(egt_state* st, int p, const double* src, void* dst, hipStream_t s) {
 }  // namespace
 
 int64_t state_bytes(const egt_game* g, bool mixed);
+size_t state_host_doubles();
 
 int state_create_in(const egt_game* g, const egt_solve_opts* o, hipStream_t s, void* dev_mem, double* host_mem,
                     egt_state** out);
@@ -261,11 +266,10 @@ int state_create_in(const egt_game* g, const egt_solve_opts* o, hipStream_t s, v
   } else {
     hipError_t e = hipMalloc(&st->block, bytes);
     if (e != hipSuccess) return fail(EGT_ENOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
-    e = hipHostMalloc((void**)&st->hscal, (64 + (size_t)kMaxTrees * kMaxPartials) * sizeof(double),
+    e = hipHostMalloc((void**)&st->hscal, state_host_doubles() * sizeof(double),
                       hipHostMallocDefault);
     if (e != hipSuccess) return fail(EGT_ENOMEM, std::string("hipHostMalloc: ") + hipGetErrorString(e));
   }
-  st->hpart = st->hscal + 64;
   unsigned char* cur = (unsigned char*)st->block;
   auto take = [&](size_t nbytes) {
     void* r = cur;
@@ -300,7 +304,12 @@ int state_create_in(const egt_game* g, const egt_solve_opts* o, hipStream_t s, v
   // FP64 q_bar scratch of player p during the start-up
   auto qscratch = [&](int p) { return mixed ? st->S64 : (double*)st->T1[p]; };
   st->dscal = (double*)take(64 * sizeof(double));
-  st->dpart = (double*)take((size_t)kMaxTrees * kMaxPartials * sizeof(double));
+  st->hpart = st->hscal + 64;
+  {
+    void* dev = nullptr;  // device address of the pinned host scalars
+    EGT_TRY(hipHostGetDevicePointer(&dev, st->hscal, 0));
+    st->hpart_dev = (double*)dev + 64;
+  }
   EGT_HIP(hipMemsetAsync(st->block, 0, bytes, s));
 
   // x_omega and A^T x_omega with the FP64 operator: the start of Algorithms 1/3
@@ -375,7 +384,7 @@ int gap_launch(egt_state* st, hipStream_t s) {
     EGT_TRY(launch_gradient(st->g, 1, st->X64[0], st->G64[1], s));
     gap_passes(st, st->G64[0], 1.0, nullptr, 0.0, st->G64[1], 1.0, nullptr, 0.0, ps);
   }
-  EGT_TRY(launch_passes(st->g, ps, 2, nullptr, st->dpart, s, kF64));
+  EGT_TRY(launch_passes(st->g, ps, 2, nullptr, st->hpart_dev, s, kF64));
   return enqueue_values(st, 2, s);
 }
 
@@ -436,7 +445,14 @@ static int attempt(egt_state* st, int p, double tau, bool first, hipStream_t s) 
       gap_passes(st, st->T2[0], 1.0, nullptr, 0.0, st->G[1], 1.0 - tau, st->T1[1], tau, ps + 2);
     trees = 4;
   }
-  EGT_TRY(launch_passes(g, ps, trees, nullptr, st->dpart, s, st->prec));
+  // the single-launch pass also writes the accepted product (1-tau) G[p] + tau T1[p]
+  // of tree 0 into T2[p], so accepting the step is a swap
+  Epilogue epi[4] = {};
+  if (g->fused_passes) {
+    epi[0].g_out = st->T2[p];
+    epi[0].g_scale = kSg[p];
+  }
+  EGT_TRY(launch_passes(g, ps, trees, epi, st->hpart_dev, s, st->prec));
   return EGT_OK;
 }
 
@@ -490,7 +506,11 @@ int step_finish(egt_state* st, hipStream_t s, int* accepted, double* egv_out, in
     return EGT_OK;
   }
   // accept: G[p] <- (1-tau) G[p] + tau T1[p] (linearity), G[o] <- T2[o]
-  if ((rc = axpby(st, p, 1.0 - tau, st->G[p], tau, st->T1[p], st->G[p], s))) return rc;
+  if (st->g->fused_passes) {
+    std::swap(st->G[p], st->T2[p]);  // written by the value launch
+  } else if ((rc = axpby(st, p, 1.0 - tau, st->G[p], tau, st->T1[p], st->G[p], s))) {
+    return rc;
+  }
   std::swap(st->G[o], st->T2[o]);
   std::swap(st->X[p], st->Xn[p]);
   std::swap(st->X[o], st->Xn[o]);
@@ -664,10 +684,11 @@ int64_t state_bytes(const egt_game* g, bool mixed) {
     if (mixed) bytes += sizeof(double) * 3 * (size_t)vec_elems(g, p);
     bytes += 12 * 256;
   }
-  bytes += (64 + (size_t)kMaxTrees * kMaxPartials) * sizeof(double) + 2 * 256;
+  bytes += 64 * sizeof(double) + 256;
   return (int64_t)bytes;
 }
 
+// Pinned host doubles of a state: 64 scalars, then the root partial sums.
 size_t state_host_doubles() { return 64 + (size_t)kMaxTrees * kMaxPartials; }
 
 // Accessors for the batch engine.
