@@ -25,6 +25,14 @@ if ROOT not in sys.path:
 
 METRIC = "EGT iters/sec and endgame solves/sec to gap<=1e-3·pot; p50/p99 solve latency"
 HBM_PEAK_GBS = 8000.0
+# HBM bytes per roofline launch (sbr_fused_kernel, egt_smoothed_br without the
+# value) on the 1081-hand endgame c1, from two rocprofv3 --pmc passes of
+# `bench.py --roofline-only --kernel-reps 50 --copy-calibration-mb 256`:
+# FETCH_SIZE 1126.5 KiB and WRITE_SIZE 1895.5 KiB per dispatch, each scaled
+# by the same counter on the plain 256 MiB device copy of that run
+# (FETCH_SIZE reads 131085 KiB of the 262144 KiB copied: factor 2.0;
+# WRITE_SIZE 262144 KiB: factor 1.0).  Valid for this kernel version only.
+SBR_TRAFFIC_BYTES = {"c1": (1126.5 * 2.0 + 1895.5 * 1.0) * 1024}
 
 
 def parse():
@@ -35,15 +43,17 @@ def parse():
     ap.add_argument("--config", default="c1")
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--variant", default="AS")
-    ap.add_argument("--cpu-sample-iters", type=int, default=60)
+    ap.add_argument("--cpu-sample-iters", type=int, default=120)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--kernel-reps", type=int, default=200)
     ap.add_argument("--mixed-steps", type=int, default=5, help="precision-form solves of the same endgame")
-    ap.add_argument("--serve-requests", type=int, default=48, help="requests of the serving trace (0 = skip)")
+    ap.add_argument("--serve-requests", type=int, default=24, help="requests of the serving trace (0 = skip)")
     ap.add_argument("--serve-shapes", default="c0,c1,c2,c3")
     ap.add_argument("--serve-budget-gb", type=float, default=16.0)
     ap.add_argument("--copy-calibration-mb", type=float, default=0.0,
                     help="run 5 plain device copies of this many MB first (scales HBM counters)")
+    ap.add_argument("--roofline-only", action="store_true",
+                    help="only the kernel measurements (for counter runs under a profiler)")
     return ap.parse_args()
 
 
@@ -56,29 +66,53 @@ def percentile(xs, q):
     return xs[lo] + (xs[hi] - xs[lo]) * (k - lo)
 
 
-def kernel_roofline(egt, torch, G, reps):
-    """Average duration of the payoff-product launch (player 1's gradient
-    A y on a treeplex point), HIP events on the stream it runs on."""
-    y = egt.uniform(G, 1)
-    out = G.empty(0)
+def _timed(torch, fn, reps):
+    """Average duration of fn() over reps back-to-back calls, HIP events on
+    the current stream (the stream the library launches on)."""
     for _ in range(10):
-        egt.gradient(G, 0, y, out)
+        fn()
     s = torch.cuda.current_stream()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record(s)
     for _ in range(reps):
-        egt.gradient(G, 0, y, out)
+        fn()
     e1.record(s)
     e1.synchronize()
-    avg_s = e0.elapsed_time(e1) / 1e3 / reps
+    return e0.elapsed_time(e1) / 1e3 / reps
+
+
+def kernel_roofline(egt, torch, G, reps, config=None):
+    """The dominant kernel of an iteration, the single-launch smoothed best
+    response (sbr_fused_kernel), launched as egt_smoothed_br without the value
+    (one launch per call) on a product A y.  Algorithmic bytes per launch: the
+    gradient read and the strategy written, 8-byte doubles over every
+    (sequence, hand) of the player: 16 * n_seq * n."""
+    y = egt.uniform(G, 1)
+    g = egt.gradient(G, 0, y)
+    q = G.empty(0)
+    mu = 1e-3 * float(g.abs().max()) / 100.0
+    avg_s = _timed(torch, lambda: egt.smoothed_br(G, 0, g, mu, q, want_value=False), reps)
+    bytes_ = 16.0 * G.n_seq[0] * G.n
+    gbs = bytes_ / avg_s / 1e9
+    traffic = SBR_TRAFFIC_BYTES.get(config)
+    return dict(kernel="sbr_fused_kernel", bound="hbm", achieved=round(gbs, 3), peak=HBM_PEAK_GBS, unit="GB/s",
+                frac=round(gbs / HBM_PEAK_GBS, 6), traffic=round(traffic) if traffic else None,
+                avg_us=round(avg_s * 1e6, 3), algorithmic_bytes=int(bytes_),
+                launch="egt_smoothed_br, player 1, no value")
+
+
+def gradient_roofline(egt, torch, G, reps):
+    """The payoff product (gradient_kernel), A y at a treeplex point.
+    Algorithmic bytes: one opponent row per terminal read and one output row
+    per sequence written, 8-byte doubles over the n hands."""
+    y = egt.uniform(G, 1)
+    out = G.empty(0)
+    avg_s = _timed(torch, lambda: egt.gradient(G, 0, y, out), reps)
     n_fold, n_show = G.terminals()
-    # algorithmic bytes: one opponent row per terminal read, one output row per
-    # sequence written (8-byte doubles, n hands each)
     bytes_ = 8.0 * G.n * ((n_fold + n_show) + G.n_seq[0])
     gbs = bytes_ / avg_s / 1e9
     return dict(kernel="gradient_kernel", bound="hbm", achieved=round(gbs, 3), peak=HBM_PEAK_GBS, unit="GB/s",
-                frac=round(gbs / HBM_PEAK_GBS, 6), traffic=None, avg_us=round(avg_s * 1e6, 3),
-                algorithmic_bytes=int(bytes_))
+                frac=round(gbs / HBM_PEAK_GBS, 6), avg_us=round(avg_s * 1e6, 3), algorithmic_bytes=int(bytes_))
 
 
 def precision_form(egt, torch, G, steps, fp64_ms, fp64_value, reps):
@@ -110,8 +144,8 @@ def precision_form(egt, torch, G, steps, fp64_ms, fp64_value, reps):
     e1.synchronize()
     prod_us = e0.elapsed_time(e1) / reps * 1e3
     n_fold, n_show = G.terminals()
-    kpad = (G.n + 63) // 64 * 64
-    flops = 2.0 * kpad * kpad * n_show * 2  # hi and lo
+    # dense BF16 GEMM of the showdown columns: W (ld x ld) times Y hi and Y lo (ld x n_show)
+    flops = 2.0 * G.ld * G.ld * n_show * 2
     ms = elapsed / steps * 1e3
     return dict(
         solves_per_sec=steps / elapsed, iters_per_sec=iters / elapsed, ms_per_solve=ms,
@@ -207,6 +241,10 @@ def main():
     inst = make_instance(args.config, args.seed)
     G = egt.Game(inst)
     torch.cuda.synchronize()
+    if args.roofline_only:
+        print(json.dumps({"roofline": kernel_roofline(egt, torch, G, args.kernel_reps, args.config),
+                          "roofline_gradient": gradient_roofline(egt, torch, G, args.kernel_reps)}), flush=True)
+        return
     for _ in range(args.warmup):
         r, _ = egt.solve(G, variant=args.variant)
         print(f"warmup solve: {r['iters']} iters, gap {r['gap']:.4g}, {r['seconds']*1e3:.1f} ms", file=sys.stderr,
@@ -226,7 +264,8 @@ def main():
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     print(f"timed {args.steps} solves in {elapsed:.3f} s", file=sys.stderr, flush=True)
-    roof = kernel_roofline(egt, torch, G, args.kernel_reps)
+    roof = kernel_roofline(egt, torch, G, args.kernel_reps, args.config)
+    roof_grad = gradient_roofline(egt, torch, G, args.kernel_reps)
     iters_per_solve = iters / args.steps
     out = {
         "metric": METRIC,
@@ -255,6 +294,7 @@ def main():
         "p99_ms": percentile(lat, 99) * 1e3,
         "final_gap": res["gap"],
         "roofline": roof,
+        "roofline_gradient": roof_grad,
     }
     if args.mixed_steps > 0:
         out["precision_form"] = precision_form(egt, torch, G, args.mixed_steps, out["ms_per_step"], res["value_p1"],

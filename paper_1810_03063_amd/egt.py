@@ -225,14 +225,17 @@ def gradient(game: Game, player: int, strat_other, out=None, stream=None):
     return out
 
 
-def smoothed_br(game: Game, player: int, grad, mu: float, strat_out=None, value_out=None, stream=None):
-    """argmin_q <grad, q> + mu d(q): returns (strategy tensor, value tensor[1])."""
+def smoothed_br(game: Game, player: int, grad, mu: float, strat_out=None, value_out=None, stream=None,
+                want_value=True):
+    """argmin_q <grad, q> + mu d(q): returns (strategy tensor, value tensor[1] or None).
+    want_value=False skips the value (one launch instead of two)."""
     if strat_out is None:
         strat_out = game.empty(player)
-    if value_out is None:
+    if value_out is None and want_value:
         value_out = torch.zeros(1, dtype=torch.float64, device=grad.device)
     _check(_smoothed_br(game.handle, player, _dptr(grad, (game.n_seq[player], game.ld)), float(mu),
-                        _dptr(strat_out, (game.n_seq[player], game.ld)), _dptr(value_out), _stream(stream)))
+                        _dptr(strat_out, (game.n_seq[player], game.ld)),
+                        _dptr(value_out) if value_out is not None else None, _stream(stream)))
     return strat_out, value_out
 
 
