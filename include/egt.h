@@ -271,28 +271,32 @@ typedef struct egt_batch egt_batch;
  * admission test of egt_batch_admit charges exactly this. */
 int egt_state_bytes(const egt_game* game, const egt_solve_opts* opts, int64_t* bytes);
 
-/* A batch of at most max_slots concurrent solves whose states together stay
- * within budget_bytes of device memory. */
+/* A batch of at most max_slots (1..1024) concurrent solves whose states
+ * together stay within budget_bytes of device memory.  Reserves the budget
+ * as one device arena, a stream (default priority) and pinned host scalars
+ * per slot, and starts min(max_slots, 16) host worker threads; nothing is
+ * allocated after this call.  EGT_ENOMEM when the reservation fails. */
 int egt_batch_create(int64_t budget_bytes, int32_t max_slots, egt_batch** out);
 
-/* Retires every slot and frees the batch.  NULL is accepted. */
+/* Stops the workers (a running solve stops after its current iteration),
+ * joins them and frees everything the batch reserved.  NULL is accepted. */
 int egt_batch_destroy(egt_batch* batch);
 
-/* Starts a solve of `game` (caller-owned; it must outlive the slot) with
- * `opts` in a free slot, on a stream of its own: allocates its state and runs
- * the start-up of Algorithms 1/3 (synchronising that stream).  EGT_EBUDGET
- * when the state does not fit the remaining budget or no slot is free; the
- * caller retries after a retire. */
+/* Queues a solve of `game` (caller-owned; it must outlive the slot) with
+ * `opts` in a free slot and returns at once: the slot's state takes a
+ * first-fit range of egt_state_bytes() bytes of the arena, and a worker
+ * creates it and runs the solve (the same iteration as egt_solve) on the
+ * slot's stream, concurrently with the other slots.  EGT_EBUDGET when no
+ * slot is free or the state does not fit the free arena; the caller retries
+ * after a retire.  The precision-form tables of `game` are built here. */
 int egt_batch_admit(egt_batch* batch, const egt_game* game, const egt_solve_opts* opts,
                     int32_t* slot);
 
-/* Advances every live solve by one phase (a saddle-gap test when due, else one
- * attempt of an EGT step): all phases are enqueued on their streams first,
- * then each is waited for, so solves overlap on the device.  A solve whose
- * gap reaches its eps (or whose iteration cap is reached) becomes done.
- * n_active: live solves after the tick; n_finished: solves done in this tick.
- * A solve's result is bitwise the same as a lone egt_solve with the same
- * options. */
+/* Waits up to about 2 ms for a solve to finish (returns at once when one
+ * finished since the last tick or none is live).  n_active: queued and
+ * running solves; n_finished: solves finished since the last tick.  Solves
+ * advance on their own; ticking only reports.  Each result is bitwise the
+ * same as a lone egt_solve with the same options. */
 int egt_batch_tick(egt_batch* batch, int32_t* n_active, int32_t* n_finished);
 
 /* done = 1 once the slot's solve has finished; then status (EGT_OK,
@@ -301,7 +305,8 @@ int egt_batch_tick(egt_batch* batch, int32_t* n_active, int32_t* n_finished);
 int egt_batch_poll(egt_batch* batch, int32_t slot, int32_t* done, int32_t* status,
                    egt_result* result);
 
-/* Frees the slot's state and stream and returns its bytes to the budget. */
+/* Frees a finished slot and returns its bytes to the arena (EGT_EINVAL for a
+ * slot that is free, queued or running). */
 int egt_batch_retire(egt_batch* batch, int32_t slot);
 
 /* Bytes charged by live and done slots, and their counts. */
