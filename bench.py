@@ -47,7 +47,7 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--kernel-reps", type=int, default=200)
     ap.add_argument("--mixed-steps", type=int, default=5, help="precision-form solves of the same endgame")
-    ap.add_argument("--serve-requests", type=int, default=24, help="requests of the serving trace (0 = skip)")
+    ap.add_argument("--serve-requests", type=int, default=16, help="requests of the serving trace (0 = skip)")
     ap.add_argument("--serve-shapes", default="c0,c1,c2,c3")
     ap.add_argument("--serve-budget-gb", type=float, default=16.0)
     ap.add_argument("--copy-calibration-mb", type=float, default=0.0,
@@ -161,8 +161,8 @@ def precision_form(egt, torch, G, steps, fp64_ms, fp64_value, reps):
 
 def serving(egt, args):
     """Poisson trace of solve requests (shapes drawn uniformly), continuously
-    batched in the precision form under an HBM budget, against the same trace
-    served one at a time in FP64."""
+    batched in the precision form under an HBM budget (and, for comparison,
+    batched in FP64), against the same trace served one at a time in FP64."""
     from instances import make_instance
     from instances.endgames import serving_trace
     from paper_1810_03063_amd.serve import LibEngine, Request, serve, serve_sequential, summarize
@@ -175,8 +175,8 @@ def serving(egt, args):
         tr = serving_trace(n, rate=rate, seed=11, shapes=shapes)
         return [Request(i, a, make_instance(shape, seed)) for i, (a, shape, seed) in enumerate(tr)]
 
-    def run(rate):
-        eng = LibEngine(egt, budget, max_slots=64, precision="mixed", gap_every=10)
+    def run(rate, precision="mixed"):
+        eng = LibEngine(egt, budget, max_slots=64, precision=precision, gap_every=10 if precision == "mixed" else 1)
         out, wall = serve(eng, reqs_for(rate))
         eng.close()
         return summarize(out, wall)
@@ -184,6 +184,8 @@ def serving(egt, args):
     saturated = run(0.0)  # every request at t = 0: the batched throughput R
     rate = 0.7 * saturated["solves_per_sec"]
     loaded = run(rate)
+    loaded64 = run(rate, "fp64")
+    print("serving: batched runs done", file=sys.stderr, flush=True)
 
     def solve_one(r):
         G = egt.Game(r.payload)
@@ -194,8 +196,9 @@ def serving(egt, args):
     seq_out, seq_wall = serve_sequential(solve_one, reqs_for(rate))
     baseline = summarize(seq_out, seq_wall)
     return dict(shapes=list(shapes), requests=n, budget_gb=args.serve_budget_gb, saturated=saturated,
-                poisson_rate_per_s=rate, batched=loaded, sequential_fp64=baseline,
-                throughput_vs_sequential=loaded["solves_per_sec"] / baseline["solves_per_sec"])
+                poisson_rate_per_s=rate, batched=loaded, batched_fp64=loaded64, sequential_fp64=baseline,
+                throughput_vs_sequential=loaded["solves_per_sec"] / baseline["solves_per_sec"],
+                fp64_batched_vs_sequential=loaded64["solves_per_sec"] / baseline["solves_per_sec"])
 
 
 def cpu_baseline(inst, sample_iters, iters_per_solve, variant):

@@ -213,6 +213,13 @@ int finish_player(const Enumerator& en, int p, HostPlayer& hp, std::vector<int>&
   }
   if (mx > kMaxDepth) return fail(EGT_EINVAL, "a player's sequence chain is deeper than 16");
   hp.max_chain = mx;
+  // root-first path of every sequence, for the fully parallel top-down pass
+  hp.anc.assign((size_t)ns * kMaxDepth, -1);
+  for (int s = 0; s < ns; ++s) {
+    int path[kMaxDepth], d = 0;
+    for (int q = s; q >= 0; q = hp.seq_parent[q]) path[d++] = q;
+    for (int j = 0; j < d; ++j) hp.anc[(size_t)s * kMaxDepth + j] = path[d - 1 - j];
+  }
   hp.max_level_width = 0;
   for (int l = 0; l < hp.n_levels; ++l)
     hp.max_level_width = std::max(hp.max_level_width, hp.level_begin[l + 1] - hp.level_begin[l]);
@@ -421,7 +428,7 @@ int build_game(const egt_game_desc* d, hipStream_t stream, egt_game** out) {
     return off;
   };
   struct Offs {
-    size_t first, nact, beta, logn, spar, cbeg, child, tbeg, topp, tkind, tcoef, roots, belief, ftab, trec;
+    size_t first, nact, beta, logn, spar, cbeg, child, tbeg, topp, tkind, tcoef, roots, belief, ftab, trec, anc;
   } po[2];
   for (int p = 0; p < 2; ++p) {
     HostPlayer& hp = g->hp[p];
@@ -440,6 +447,7 @@ int build_game(const egt_game_desc* d, hipStream_t stream, egt_game** out) {
     po[p].belief = add(b[p].data(), b[p].size() * sizeof(double));
     po[p].ftab = add(hp.fused_tab.data(), hp.fused_tab.size());
     po[p].trec = add(hp.term_rec.data(), hp.term_rec.size() * sizeof(TermRec));
+    po[p].anc = add(hp.anc.data(), hp.anc.size() * sizeof(int));
   }
   const size_t o_cbeg = add(card_begin.data(), card_begin.size() * sizeof(int));
   const size_t o_chands = add(card_hands.data(), card_hands.size() * sizeof(int));
@@ -457,6 +465,8 @@ int build_game(const egt_game_desc* d, hipStream_t stream, egt_game** out) {
   for (const Piece& pc : pieces)
     if (pc.bytes) std::memcpy(staging.data() + pc.off, pc.src, pc.bytes);
   EGT_HIP(hipGetDevice(&g->device));
+  EGT_HIP(hipDeviceGetAttribute(&g->n_cu, hipDeviceAttributeMultiprocessorCount, g->device));
+  if (g->n_cu < 1) g->n_cu = 1;
   void* dev = nullptr;
   hipError_t e = hipMalloc(&dev, total);
   if (e != hipSuccess) return fail(EGT_ENOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
@@ -492,6 +502,7 @@ int build_game(const egt_game_desc* d, hipStream_t stream, egt_game** out) {
     dp.fused_tab = at(po[p].ftab);
     dp.fused_tab16 = (int)(hp.fused_tab.size() / 16);
     dp.term_rec = (const TermRec*)at(po[p].trec);
+    dp.anc = (const int*)at(po[p].anc);
     dp.term_stride = std::max(1, hp.max_terms_per_seq);
   }
   DHands& dh = g->dh;

@@ -88,6 +88,7 @@ struct DPlayer {
   const int* roots;            // [n_roots] root node ids
   const double* belief;        // [ld] this player's prior in slot order, 0 in the padding
   const void* fused_tab;       // the single-launch pass's table image (FusedTabLayout), 16-byte units
+  const int* anc;              // [n_seq][kMaxDepth] sequences on the path root -> s (s last), -1 after
   const TermRec* term_rec;     // [n_seq][term_stride] terminals of each sequence, padded with kind -1
   int term_stride;             // max terminals per sequence (>= 1)
   int fused_tab16;             // its size in 16-byte units
@@ -184,6 +185,7 @@ struct HostPlayer {
   std::vector<int> roots;
   std::vector<unsigned char> fused_tab;  // table image of the single-launch pass
   std::vector<TermRec> term_rec;         // [n_seq][max(1, max_terms_per_seq)]
+  std::vector<int> anc;                  // [n_seq][kMaxDepth]
   std::vector<std::string> seq_keys;
 };
 
@@ -222,6 +224,7 @@ struct MixedTables {
 
 struct egt_game {
   int n = 0, ld = 0, cph = 0, n_cards = 0;
+  int n_cu = 256;  // compute units of the game's device
   double pot = 0, stack = 0, Z = 0;
   int64_t n_fold = 0, n_show = 0;
   egt::HostPlayer hp[2];

@@ -89,21 +89,17 @@ __global__ __launch_bounds__(2 * kGroupThreads) void gradient_kernel(GradArgs<TV
   int* cbeg = (int*)(lds + (size_t)(groups * per_group + 1) / 2 * 2);  // 16-byte aligned card image
   const int* chand = cbeg + a.H.chand_off;
 
-  const int s = blockIdx.x;
-  const int MT = a.own.term_stride;
-  const TermRec* recs = a.own.term_rec + (size_t)s * MT;
+  const int MT = a.own.term_stride, n_seq = a.own.n_seq;
   const int chunk = (n + kGroupThreads - 1) / kGroupThreads;
   const int beg = min(gt * chunk, n), end = min(beg + chunk, n), cnt = end - beg;
-
-  double acc[kMaxHandsPerThread];
-#pragma unroll
-  for (int k = 0; k < kMaxHandsPerThread; ++k) acc[k] = 0.0;
+  const TermRec none{-1, -1, 0.0};
 
   // Everything the block reads from global memory is requested up front, so
   // the loads overlap: this group's first terminal, the hand tables and own
   // beliefs of this thread's chunk, the opponent's prior at the strided
-  // positions this thread stages, and the card image (into LDS).
-  TermRec tr = grp < MT ? recs[grp] : TermRec{-1, -1, 0.0};
+  // positions this thread stages, and the card image (into LDS).  The tables
+  // stay for every sequence the block then processes.
+  TermRec tr = grp < MT && (int)blockIdx.x < n_seq ? a.own.term_rec[(size_t)blockIdx.x * MT + grp] : none;
   int4 HA[kMaxHandsPerThread], HB[kMaxHandsPerThread];
   int2 TG[kMaxHandsPerThread];
   double bown[kMaxHandsPerThread], bopp[kMaxHandsPerThread];
@@ -141,9 +137,17 @@ __global__ __launch_bounds__(2 * kGroupThreads) void gradient_kernel(GradArgs<TV
     for (int i = kCU * (int)blockDim.x + tid; i < C16; i += blockDim.x) dst[i] = img[i];
   }
   const int rounds = (MT + groups - 1) / groups;
+  for (int s = blockIdx.x; s < n_seq; s += gridDim.x) {
+  const TermRec* recs = a.own.term_rec + (size_t)s * MT;
+  // the next sequence's first terminal, requested while this one runs
+  const int s_next = s + (int)gridDim.x;
+  const TermRec tr_next = grp < MT && s_next < n_seq ? a.own.term_rec[(size_t)s_next * MT + grp] : none;
+  double acc[kMaxHandsPerThread];
+#pragma unroll
+  for (int k = 0; k < kMaxHandsPerThread; ++k) acc[k] = 0.0;
   for (int rd = 0; rd < rounds; ++rd) {
     const int j = rd * groups + grp;
-    if (rd > 0) tr = j < MT ? recs[j] : TermRec{-1, -1, 0.0};
+    if (rd > 0) tr = j < MT ? recs[j] : none;
     // uniform within a group
     const bool active = tr.kind >= 0 && !(a.fold_only && tr.kind != 0);
     const int kind = tr.kind;
@@ -280,6 +284,9 @@ __global__ __launch_bounds__(2 * kGroupThreads) void gradient_kernel(GradArgs<TV
     for (int k = 0; k < kMaxHandsPerThread; ++k)
       if (k < cnt) row[beg + k] = (TO)(acc[k] * (bown[k] * a.H.invZ));
     for (int i = n + gt; i < ld; i += kGroupThreads) row[i] = (TO)0;
+  }
+  tr = tr_next;
+  __syncthreads();  // the next sequence rewrites R of both groups
   }
 }
 
@@ -663,12 +670,13 @@ __global__ __launch_bounds__(64) void sum_partials_kernel(const double* partial,
 
 // ---------------------------------------------------------------------------
 // Top-down pass of the level path, fully parallel: q[s] = q_bar[root] * ...
-// * q_bar[s] along the sequence's parent chain (multiplied from the root
-// down), then the epilogue comb = (1 - tau) x_prev + tau q.  Padding slots are
-// written 0.
+// * q_bar[s] along the sequence's path (multiplied from the root down, the
+// path read from the precomputed root-first table, so every q_bar load is
+// issued at once), then the epilogue comb = (1 - tau) x_prev + tau q.
+// Padding slots are written 0.
 // ---------------------------------------------------------------------------
 struct DownArgs {
-  const int* seq_parent;
+  const int* anc;
   const void* QB;
   int n, ld;
   void* q_out;
@@ -692,16 +700,20 @@ __global__ __launch_bounds__(kPassThreads) void top_down_kernel(DownArgs a) {
     if (comb_out) comb_out[idx] = (TS)0;
     return;
   }
-  int depth = 0;
-  for (int q = s; q >= 0; q = a.seq_parent[q]) ++depth;
-  TS val = (TS)1;
-  for (int j = depth - 1; j >= 0; --j) {
-    int q = s;
-    for (int k = 0; k < j; ++k) q = a.seq_parent[q];
-    val *= QB[(size_t)q * a.ld + h];
+  const int* path = a.anc + (size_t)s * kMaxDepth;
+  TS f[kMaxDepth];
+#pragma unroll
+  for (int j = 0; j < kMaxDepth; ++j) {
+    const int q = path[j];
+    f[j] = q >= 0 ? QB[(size_t)q * a.ld + h] : (TS)1;
   }
+  TS val = (TS)1;
+#pragma unroll
+  for (int j = 0; j < kMaxDepth; ++j)
+    if (path[j] >= 0) val *= f[j];
+  const TS xp = comb_out ? x_prev[idx] : (TS)0;
   if (q_out) q_out[idx] = val;
-  if (comb_out) comb_out[idx] = (TS)(1.0 - a.tau) * x_prev[idx] + (TS)a.tau * val;
+  if (comb_out) comb_out[idx] = (TS)(1.0 - a.tau) * xp + (TS)a.tau * val;
 }
 
 struct UniformArgs {
@@ -774,7 +786,10 @@ static hipError_t gradient_launch(const egt_game* g, int player, const TV* v_opp
   if (groups == 2 && lds_bytes(2) > kGradLdsLimit) groups = 1;
   a.groups = groups;
   const size_t lds = lds_bytes(groups);
-  hipLaunchKernelGGL((gradient_kernel<TV, TO>), dim3(g->dp[player].n_seq), dim3(kGroupThreads * groups), lds, s, a);
+  // one block per sequence up to two blocks per compute unit; beyond that each
+  // block loops over sequences (the tables are staged once per block)
+  const int blocks = std::min(g->dp[player].n_seq, 2 * g->n_cu);
+  hipLaunchKernelGGL((gradient_kernel<TV, TO>), dim3(blocks), dim3(kGroupThreads * groups), lds, s, a);
   return hipGetLastError();
 }
 
@@ -896,7 +911,7 @@ hipError_t launch_sum_partials(const egt_game* g, const double* partial, int cou
 hipError_t launch_top_down(const egt_game* g, int player, const void* QB, void* q_out, const void* x_prev,
                            double tau, void* comb_out, hipStream_t s, Prec prec) {
   DownArgs a;
-  a.seq_parent = g->dp[player].seq_parent;
+  a.anc = g->dp[player].anc;
   a.QB = QB;
   a.n = g->n;
   a.ld = g->ld;

@@ -126,13 +126,18 @@ int enqueue_values(egt_state* st, int trees, hipStream_t) {
   return EGT_OK;
 }
 
-// Waits for the stream (polling, which wakes up sooner than a blocking wait)
-// and adds each tree's partials in order into hscal[k].
+// Waits for the stream and adds each tree's partials in order into
+// hscal[k].  The wait polls for up to kSpinSeconds (a blocking wait wakes up
+// tens of microseconds late, which an iteration of ~100 us cannot afford),
+// then blocks, so that many concurrent solves do not keep every host core busy.
 int finish_values(egt_state* st, hipStream_t s) {
+  constexpr double kSpinSeconds = 200e-6;
+  const auto t0 = std::chrono::steady_clock::now();
   hipError_t e;
-  while ((e = hipStreamQuery(s)) == hipErrorNotReady) {
+  while ((e = hipStreamQuery(s)) == hipErrorNotReady &&
+         std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count() < kSpinSeconds) {
   }
-  if (e != hipSuccess) return hip_fail(e, "hipStreamQuery");
+  if (e != hipSuccess && e != hipErrorNotReady) return hip_fail(e, "hipStreamQuery");
   EGT_TRY(hipStreamSynchronize(s));
   const int nb = n_partials(st->g);
   const int trees = st->pending_trees;
