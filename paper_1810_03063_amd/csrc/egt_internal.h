@@ -127,8 +127,10 @@ struct TreePass {
   const void* gB;
   double cB;
   double mu;
-  double* V;       // node values: always FP64
+  double* V;       // node values by value slot (FusedTabLayout): always FP64
   void* QB;        // q_bar in the launch's precision
+  void* g_out;     // g_scale (cA gA + cB gB), or null (the epilogue's g_out)
+  double g_scale;
   int n_levels;
   int n_child;
   int level_begin[kMaxDepth + 1];

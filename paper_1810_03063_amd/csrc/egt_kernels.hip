@@ -299,72 +299,9 @@ __global__ __launch_bounds__(2 * kGroupThreads) void gradient_kernel(GradArgs<TV
 //   best response (mu = 0): V[v] = min_a g~_a.
 // The action with the smallest g~ has the largest q_bar (weight exactly 1), so
 // V is the value g~_i + temp log q_bar_i + temp log n_v at that action, and
-// every exponent is <= 0.  Tables are read through the accessor `T`, the
-// combined gradient cA gA + cB gB through `getG`, the child values through
-// `getV`; results go through `putV` / `putQ`.
+// every exponent is <= 0.  Both pass forms below evaluate exactly this, with
+// 1 / temp taken as (1 / mu) (1 / beta_v).
 // ---------------------------------------------------------------------------
-template <class TG, class Tab, class GetG, class GetV, class PutV, class PutQ>
-__device__ __forceinline__ void node_pass(double mu, const Tab& T, int v, GetG getG, GetV getV, PutV putV,
-                                          PutQ putQ, bool want_q) {
-  const int s0 = T.first(v);
-  const int na = T.nact(v);
-  double gt[kMaxActions];
-  double m = INFINITY;
-#pragma unroll
-  for (int k = 0; k < kMaxActions; ++k) {
-    if (k < na) {
-      const int s = s0 + k;
-      double x = getG(s);
-      const int c1 = T.cbeg(s + 1);
-      for (int c = T.cbeg(s); c < c1; ++c) x += getV(T.child(c));
-      gt[k] = x;
-      m = fmin(m, x);
-    }
-  }
-  if (!(mu > 0.0)) {
-    putV(v, m);
-    return;
-  }
-  const double temp = mu * T.beta(v);
-  const double inv_temp = 1.0 / temp;
-  double sum = 0.0;
-  if constexpr (std::is_same<TG, float>::value) {
-    // precision form: FP32 exponentials, FP64 normaliser and value
-#pragma unroll
-    for (int k = 0; k < kMaxActions; ++k) {
-      if (k < na) {
-        gt[k] = (double)expf((float)((m - gt[k]) * inv_temp));
-        sum += gt[k];
-      }
-    }
-  } else {
-#pragma unroll
-    for (int k = 0; k < kMaxActions; ++k) {
-      if (k < na) {
-        gt[k] = exp((m - gt[k]) * inv_temp);
-        sum += gt[k];
-      }
-    }
-  }
-  putV(v, (m - temp * log(sum)) + temp * T.logn(v));
-  if (want_q) {
-    const double inv_sum = 1.0 / sum;
-#pragma unroll
-    for (int k = 0; k < kMaxActions; ++k)
-      if (k < na) putQ(s0 + k, (TG)(gt[k] * inv_sum));
-  }
-}
-
-struct GlobalTab {
-  const DPlayer& P;
-  __device__ int first(int v) const { return P.node_first_seq[v]; }
-  __device__ int nact(int v) const { return P.node_nact[v]; }
-  __device__ double beta(int v) const { return P.node_beta[v]; }
-  __device__ double logn(int v) const { return P.node_logn[v]; }
-  __device__ int cbeg(int s) const { return P.child_begin[s]; }
-  __device__ int child(int c) const { return P.child[c]; }
-};
-
 
 // ---------------------------------------------------------------------------
 // Fused pass for trees whose tables fit in LDS.  Block = (tree k, HB hands),
@@ -616,7 +553,11 @@ __global__ __launch_bounds__(kFusedSlots * HB) void sbr_fused_kernel(FusedArgs a
 }
 
 // Large trees: one launch per level over all trees of the set; block = one
-// wavefront for (node, 64 hands); node values and q_bar in global memory.
+// wavefront for (node, 64 hands); node values (by value slot) and q_bar in
+// global memory.  The node's record and parameters come from the table image
+// (block-uniform loads), a sequence's children from contiguous value slots.
+// With g_out the launch also writes g_scale (cA gA + cB gB) of every sequence
+// it reads.
 template <class TG>
 __global__ __launch_bounds__(kPassThreads) void bottom_up_level_kernel(PassSet a) {
   int y = blockIdx.y, k = 0;
@@ -628,28 +569,73 @@ __global__ __launch_bounds__(kPassThreads) void bottom_up_level_kernel(PassSet a
   const int h = blockIdx.x * kPassThreads + threadIdx.x;
   if (h >= a.n) return;
   const size_t ld = a.ld;
-  const GlobalTab T{t.P};
+  const int v = t.level_begin[a.level] + y;
+  const FusedTabLayout L = fused_tab_layout(t.P.n_nodes, t.P.n_seq);
+  const unsigned char* tab = (const unsigned char*)t.P.fused_tab;
+  const int4 r = ((const int4*)(tab + L.rec))[v];
+  const double2 p0 = ((const double2*)(tab + L.prm))[2 * v], p1 = ((const double2*)(tab + L.prm))[2 * v + 1];
+  const int* cbeg = (const int*)(tab + L.cbeg);
+  const int s0 = r.x, na = r.y;
   const TG* gA = (const TG*)t.gA;
   const TG* gB = (const TG*)t.gB;
-  auto getG = [&](int s) {
-    double x = t.cA * (double)gA[(size_t)s * ld + h];
-    if (gB) x += t.cB * (double)gB[(size_t)s * ld + h];
-    return x;
-  };
-  auto getV = [&](int c) { return t.V[(size_t)c * ld + h]; };
-  auto putV = [&](int v, double x) { t.V[(size_t)v * ld + h] = x; };
-  auto putQ = [&](int s, TG q) { ((TG*)t.QB)[(size_t)s * ld + h] = q; };
-  node_pass<TG>(t.mu, T, t.level_begin[a.level] + y, getG, getV, putV, putQ, t.QB != nullptr);
+  TG* g_out = (TG*)t.g_out;
+  double g[kMaxActions];
+  double m = INFINITY;
+#pragma unroll
+  for (int j = 0; j < kMaxActions; ++j) {
+    if (j < na) {
+      const size_t idx = (size_t)(s0 + j) * ld + h;
+      double x = t.cA * (double)gA[idx];
+      if (gB) x += t.cB * (double)gB[idx];
+      if (g_out) g_out[idx] = (TG)(x * t.g_scale);
+      const int c1 = cbeg[s0 + j + 1];
+      for (int c = cbeg[s0 + j]; c < c1; ++c) x += t.V[(size_t)c * ld + h];
+      g[j] = x;
+      m = fmin(m, x);
+    }
+  }
+  if (!(t.mu > 0.0)) {
+    t.V[(size_t)r.z * ld + h] = m;
+    return;
+  }
+  const double temp = t.mu * p0.x;
+  const double inv_temp = (1.0 / t.mu) * p0.y;
+  double sum = 0.0;
+  if constexpr (std::is_same<TG, float>::value) {
+#pragma unroll
+    for (int j = 0; j < kMaxActions; ++j) {
+      if (j < na) {
+        g[j] = (double)expf((float)((m - g[j]) * inv_temp));
+        sum += g[j];
+      }
+    }
+  } else {
+#pragma unroll
+    for (int j = 0; j < kMaxActions; ++j) {
+      if (j < na) {
+        g[j] = exp((m - g[j]) * inv_temp);
+        sum += g[j];
+      }
+    }
+  }
+  t.V[(size_t)r.z * ld + h] = (m - temp * log(sum)) + temp * p1.x;
+  if (t.QB) {
+    const double inv_sum = 1.0 / sum;
+#pragma unroll
+    for (int j = 0; j < kMaxActions; ++j)
+      if (j < na) ((TG*)t.QB)[(size_t)(s0 + j) * ld + h] = (TG)(g[j] * inv_sum);
+  }
 }
 
-// Root sums of the level path: block k sums tree k, roots in order, hands
-// strided over the threads, then a fixed-order reduction.
+// Root sums of the level path: block k sums tree k, roots in order (value
+// slots C + r), hands strided over the threads, then a fixed-order reduction.
 __global__ __launch_bounds__(256) void root_sums_kernel(PassSet a, double* out) {
   __shared__ double part[4];
   const TreePass& t = a.t[blockIdx.x];
   double s = 0.0;
+  const int C = t.P.n_nodes - t.P.n_roots;  // the r-th root's value slot is C + r
   for (int r = 0; r < t.P.n_roots; ++r) {
-    const double* row = t.V + (size_t)t.P.roots[r] * a.ld;
+    const double* row = t.V + (size_t)(C + r) * a.ld;
     for (int h = threadIdx.x; h < a.n; h += 256) s += row[h];
   }
 #pragma unroll
@@ -824,6 +810,8 @@ static void fill_pass_set(const egt_game* g, const Pass* p, int count, PassSet& 
     t.mu = p[k].mu;
     t.V = p[k].V;
     t.QB = p[k].QB;
+    t.g_out = nullptr;
+    t.g_scale = 0.0;
     t.n_levels = hp.n_levels;
     t.n_child = (int)hp.child.size();
     for (int l = 0; l <= kMaxDepth; ++l) {
@@ -864,8 +852,11 @@ static hipError_t passes_launch(const egt_game* g, const Pass* p, int count, con
   }
   PassSet a;
   fill_pass_set(g, p, count, a);
-  for (int k = 0; k < count; ++k)
+  for (int k = 0; k < count; ++k) {
     if (epi && (epi[k].q_out || epi[k].comb_out) && !p[k].QB) return hipErrorInvalidValue;
+    a.t[k].g_out = epi ? epi[k].g_out : nullptr;
+    a.t[k].g_scale = epi ? epi[k].g_scale : 0.0;
+  }
   int max_levels = 0;
   for (int k = 0; k < count; ++k) max_levels = std::max(max_levels, a.t[k].n_levels);
   const unsigned bx = (unsigned)((g->n + kPassThreads - 1) / kPassThreads);

@@ -450,13 +450,11 @@ static int attempt(egt_state* st, int p, double tau, bool first, hipStream_t s) 
       gap_passes(st, st->T2[0], 1.0, nullptr, 0.0, st->G[1], 1.0 - tau, st->T1[1], tau, ps + 2);
     trees = 4;
   }
-  // the single-launch pass also writes the accepted product (1-tau) G[p] + tau T1[p]
+  // the value launch also writes the accepted product (1-tau) G[p] + tau T1[p]
   // of tree 0 into T2[p], so accepting the step is a swap
   Epilogue epi[4] = {};
-  if (g->fused_passes) {
-    epi[0].g_out = st->T2[p];
-    epi[0].g_scale = kSg[p];
-  }
+  epi[0].g_out = st->T2[p];
+  epi[0].g_scale = kSg[p];
   EGT_TRY(launch_passes(g, ps, trees, epi, st->hpart_dev, s, st->prec));
   return EGT_OK;
 }
@@ -511,11 +509,7 @@ int step_finish(egt_state* st, hipStream_t s, int* accepted, double* egv_out, in
     return EGT_OK;
   }
   // accept: G[p] <- (1-tau) G[p] + tau T1[p] (linearity), G[o] <- T2[o]
-  if (st->g->fused_passes) {
-    std::swap(st->G[p], st->T2[p]);  // written by the value launch
-  } else if ((rc = axpby(st, p, 1.0 - tau, st->G[p], tau, st->T1[p], st->G[p], s))) {
-    return rc;
-  }
+  std::swap(st->G[p], st->T2[p]);  // written by the value launch
   std::swap(st->G[o], st->T2[o]);
   std::swap(st->X[p], st->Xn[p]);
   std::swap(st->X[o], st->Xn[o]);
