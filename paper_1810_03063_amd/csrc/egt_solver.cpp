@@ -55,6 +55,13 @@ struct egt_state {
   void* T1[2] = {};
   void* T2[2] = {};
   void* QB[2] = {};
+  // spares that let the next iteration run before this one is decided: on
+  // acceptance X <- Xn <- Xs <- X and G <- T2 <- Gs <- G rotate, Xbar and the
+  // partial-sum buffers alternate, so a rejected step still finds its x, G and
+  // x_bar untouched
+  void* Xs[2] = {};
+  void* Gs[2] = {};
+  void* Xbar2[2] = {};
   double* V[2] = {};        // node values [n_nodes(p)][ld], FP64
   double* Vb[2] = {};       // node values of the best-response passes
   double* X64[2] = {};      // FP64 iterates for the gap (precision form; else scratch aliases)
@@ -64,6 +71,10 @@ struct egt_state {
   double* hscal = nullptr;  // pinned host mirror (also the summed tree values)
   double* hpart = nullptr;      // pinned root partial sums [trees][n_partials], written by the kernels
   double* hpart_dev = nullptr;  // device address of hpart
+  double* hpart2 = nullptr;     // the alternate buffer
+  double* hpart2_dev = nullptr;
+  const double* pending_part = nullptr;  // buffer of the values awaiting finish_values
+  hipEvent_t ev[2] = {nullptr, nullptr};  // end of an attempt's value launch
   void* block = nullptr;
   bool owns_memory = true;  // false: block and hscal belong to a serving batch
   // saddle gap of the current iterate (valid when gap_valid)
@@ -106,7 +117,6 @@ int sbr(egt_state* st, int p, const void* gA, double cA, const void* gB, double 
 
 // Product of player p's gradient at the opponent's strategy, in the state's precision.
 int grad(egt_state* st, int p, const void* v_opp, void* out, hipStream_t s) {
-  st->products++;
   if (st->prec == kF64)
     EGT_TRY(launch_gradient(st->g, p, (const double*)v_opp, (double*)out, s));
   else
@@ -120,35 +130,49 @@ int axpby(egt_state* st, int p, double a, const void* X, double b, const void* Y
 }
 
 // The value launch of `trees` trees writes their partial sums into pinned
-// host memory; record how many to read.
-int enqueue_values(egt_state* st, int trees, hipStream_t) {
+// host memory (`part`, st->hpart by default); record what to read.
+int enqueue_values(egt_state* st, int trees, hipStream_t, const double* part = nullptr) {
   st->pending_trees = trees;
+  st->pending_part = part ? part : st->hpart;
   return EGT_OK;
 }
 
-// Waits for the stream and adds each tree's partials in order into
-// hscal[k].  The wait polls for up to kSpinSeconds (a blocking wait wakes up
-// tens of microseconds late, which an iteration of ~100 us cannot afford),
-// then blocks, so that many concurrent solves do not keep every host core busy.
-int finish_values(egt_state* st, hipStream_t s) {
+// Waits until `done` reports completion: polls for up to kSpinSeconds (a
+// blocking wait wakes up tens of microseconds late, which an iteration of
+// ~100 us cannot afford), then blocks, so that many concurrent solves do not
+// keep every host core busy.
+template <class Query, class Block>
+int wait_for(Query done, Block block) {
   constexpr double kSpinSeconds = 200e-6;
   const auto t0 = std::chrono::steady_clock::now();
   hipError_t e;
-  while ((e = hipStreamQuery(s)) == hipErrorNotReady &&
+  while ((e = done()) == hipErrorNotReady &&
          std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count() < kSpinSeconds) {
   }
-  if (e != hipSuccess && e != hipErrorNotReady) return hip_fail(e, "hipStreamQuery");
-  EGT_TRY(hipStreamSynchronize(s));
+  if (e != hipSuccess && e != hipErrorNotReady) return hip_fail(e, "query");
+  EGT_TRY(block());
+  return EGT_OK;
+}
+
+// Adds each pending tree's partials in order into hscal[k] (the launch has
+// completed).
+int read_values(egt_state* st) {
   const int nb = n_partials(st->g);
   const int trees = st->pending_trees;
   st->pending_trees = 0;
   for (int k = 0; k < trees; ++k) {
     double v = 0.0;
-    for (int b = 0; b < nb; ++b) v += st->hpart[k * nb + b];
+    for (int b = 0; b < nb; ++b) v += st->pending_part[k * nb + b];
     if (!std::isfinite(v)) return fail(EGT_ENUMERIC, "non-finite value in the EGT driver");
     st->hscal[k] = v;
   }
   return EGT_OK;
+}
+
+// Waits for the stream, then read_values.
+int finish_values(egt_state* st, hipStream_t s) {
+  const int rc = wait_for([&] { return hipStreamQuery(s); }, [&] { return hipStreamSynchronize(s); });
+  return rc ? rc : read_values(st);
 }
 
 int fetch_values(egt_state* st, int trees, hipStream_t s) {
@@ -291,6 +315,9 @@ int state_create_in(const egt_game* g, const egt_solve_opts* o, hipStream_t s, v
     st->T1[p] = take(vb);
     st->T2[p] = take(vb);
     st->QB[p] = take(vb);
+    st->Xs[p] = take(vb);
+    st->Gs[p] = take(vb);
+    st->Xbar2[p] = take(vb);
     st->V[p] = (double*)take(sizeof(double) * (size_t)g->hp[p].n_nodes * g->ld);
     st->Vb[p] = (double*)take(sizeof(double) * (size_t)g->hp[p].n_nodes * g->ld);
     if (mixed) {
@@ -310,11 +337,14 @@ int state_create_in(const egt_game* g, const egt_solve_opts* o, hipStream_t s, v
   auto qscratch = [&](int p) { return mixed ? st->S64 : (double*)st->T1[p]; };
   st->dscal = (double*)take(64 * sizeof(double));
   st->hpart = st->hscal + 64;
+  st->hpart2 = st->hpart + (size_t)kMaxTrees * kMaxPartials;
   {
     void* dev = nullptr;  // device address of the pinned host scalars
     EGT_TRY(hipHostGetDevicePointer(&dev, st->hscal, 0));
     st->hpart_dev = (double*)dev + 64;
+    st->hpart2_dev = st->hpart_dev + (size_t)kMaxTrees * kMaxPartials;
   }
+  for (int i = 0; i < 2; ++i) EGT_TRY(hipEventCreateWithFlags(&st->ev[i], hipEventDisableTiming));
   EGT_HIP(hipMemsetAsync(st->block, 0, bytes, s));
 
   // x_omega and A^T x_omega with the FP64 operator: the start of Algorithms 1/3
@@ -362,6 +392,11 @@ int state_create_in(const egt_game* g, const egt_solve_opts* o, hipStream_t s, v
 int state_destroy(egt_state* st) {
   if (!st) return EGT_OK;
   int rc = EGT_OK;
+  for (hipEvent_t& e : st->ev)
+    if (e) {
+      (void)hipEventDestroy(e);
+      e = nullptr;
+    }
   if (st->owns_memory && (st->block || st->hscal)) {
     hipError_t e = hipDeviceSynchronize();
     if (st->block && e == hipSuccess) e = hipFree(st->block);
@@ -415,48 +450,107 @@ int state_gap(egt_state* st, double* gap, double* brmax, double* brmin, hipStrea
   return EGT_OK;
 }
 
-// One attempt of the step focused on p at step size tau.  first = compute
-// x_bar (otherwise reuse it).  Leaves the two EGV terms (and in FP64 the two
-// best-response values of the candidate's saddle gap) as root partials.
-static int attempt(egt_state* st, int p, double tau, bool first, hipStream_t s) {
+// The buffers one attempt reads and writes: the state's own, or those of the
+// iteration after an accepted step (see Xs / Gs / Xbar2).
+struct View {
+  void* X[2];
+  void* Xn[2];
+  void* Xbar[2];
+  void* G[2];
+  void* T2[2];
+  double* part_dev;  // where the value launch writes its partial sums
+  const double* part;
+};
+
+View current_view(const egt_state* st) {
+  return View{{st->X[0], st->X[1]},       {st->Xn[0], st->Xn[1]}, {st->Xbar[0], st->Xbar[1]},
+              {st->G[0], st->G[1]},       {st->T2[0], st->T2[1]}, st->hpart_dev,
+              st->hpart};
+}
+
+// The view the state takes once the current step is accepted.
+View next_view(const egt_state* st) {
+  return View{{st->Xn[0], st->Xn[1]},     {st->Xs[0], st->Xs[1]}, {st->Xbar2[0], st->Xbar2[1]},
+              {st->T2[0], st->T2[1]},     {st->Gs[0], st->Gs[1]}, st->hpart2_dev,
+              st->hpart2};
+}
+
+// Acceptance: x <- x_+, G <- the products at x_+ (rotating through the spares).
+void accept_rotate(egt_state* st) {
+  for (int q = 0; q < 2; ++q) {
+    void* x = st->X[q];
+    st->X[q] = st->Xn[q];
+    st->Xn[q] = st->Xs[q];
+    st->Xs[q] = x;
+    void* gq = st->G[q];
+    st->G[q] = st->T2[q];
+    st->T2[q] = st->Gs[q];
+    st->Gs[q] = gq;
+    std::swap(st->Xbar[q], st->Xbar2[q]);
+  }
+  std::swap(st->hpart, st->hpart2);
+  std::swap(st->hpart_dev, st->hpart2_dev);
+}
+
+// One attempt of the step focused on p at step size tau on the buffers of v,
+// with mu.  first = compute x_bar (otherwise reuse it).  Leaves the two EGV
+// terms (and in FP64 the two best-response values of the candidate's saddle
+// gap) as root partials in v.part; returns the number of value trees.
+static int attempt_v(egt_state* st, const View& v, int p, double tau, const double mu[2], bool first,
+                     hipStream_t s, int* trees_out) {
   const egt_game* g = st->g;
   const int o = 1 - p;
   int rc;
   if (first) {
-    if ((rc = sbr(st, p, st->G[p], kSg[p], nullptr, 0.0, st->mu[p], st->Xbar[p], st->X[p], tau, st->Xhat[p], s)))
-      return rc;
+    if ((rc = sbr(st, p, v.G[p], kSg[p], nullptr, 0.0, mu[p], v.Xbar[p], v.X[p], tau, st->Xhat[p], s))) return rc;
   } else {
-    if ((rc = axpby(st, p, 1.0 - tau, st->X[p], tau, st->Xbar[p], st->Xhat[p], s))) return rc;
+    if ((rc = axpby(st, p, 1.0 - tau, v.X[p], tau, v.Xbar[p], st->Xhat[p], s))) return rc;
   }
   if ((rc = grad(st, o, st->Xhat[p], st->T1[o], s))) return rc;
-  if ((rc = sbr(st, o, st->T1[o], kSg[o], nullptr, 0.0, st->mu[o], st->Xbar[o], st->X[o], tau, st->Xn[o], s)))
-    return rc;
-  if ((rc = grad(st, p, st->Xbar[o], st->T1[p], s))) return rc;
+  if ((rc = sbr(st, o, st->T1[o], kSg[o], nullptr, 0.0, mu[o], v.Xbar[o], v.X[o], tau, v.Xn[o], s))) return rc;
+  if ((rc = grad(st, p, v.Xbar[o], st->T1[p], s))) return rc;
   const double r = tau / (1.0 - tau);
-  if ((rc = sbr(st, p, st->G[p], kSg[p], st->T1[p], kSg[p] * r, st->mu[p], nullptr, st->X[p], tau, st->Xn[p], s)))
-    return rc;
-  if ((rc = grad(st, o, st->Xn[p], st->T2[o], s))) return rc;
-  const double mu_new = (1.0 - tau) * st->mu[p];
+  if ((rc = sbr(st, p, v.G[p], kSg[p], st->T1[p], kSg[p] * r, mu[p], nullptr, v.X[p], tau, v.Xn[p], s))) return rc;
+  if ((rc = grad(st, o, v.Xn[p], v.T2[o], s))) return rc;
+  const double mu_new = (1.0 - tau) * mu[p];
   // one launch for the value passes: EGV at (x_+, y_+) with mu_p+ and the
   // unchanged mu_o, and (FP64) the two best responses of the candidate's gap
   Pass ps[4];
-  ps[0] = Pass{p, st->G[p], kSg[p] * (1.0 - tau), st->T1[p], kSg[p] * tau, mu_new, st->V[p], nullptr};
-  ps[1] = Pass{o, st->T2[o], kSg[o], nullptr, 0.0, st->mu[o], st->V[o], nullptr};
+  ps[0] = Pass{p, v.G[p], kSg[p] * (1.0 - tau), st->T1[p], kSg[p] * tau, mu_new, st->V[p], nullptr};
+  ps[1] = Pass{o, v.T2[o], kSg[o], nullptr, 0.0, mu[o], st->V[o], nullptr};
   int trees = 2;
   if (st->prec == kF64) {
     if (p == 0)
-      gap_passes(st, st->G[0], 1.0 - tau, st->T1[0], tau, st->T2[1], 1.0, nullptr, 0.0, ps + 2);
+      gap_passes(st, v.G[0], 1.0 - tau, st->T1[0], tau, v.T2[1], 1.0, nullptr, 0.0, ps + 2);
     else
-      gap_passes(st, st->T2[0], 1.0, nullptr, 0.0, st->G[1], 1.0 - tau, st->T1[1], tau, ps + 2);
+      gap_passes(st, v.T2[0], 1.0, nullptr, 0.0, v.G[1], 1.0 - tau, st->T1[1], tau, ps + 2);
     trees = 4;
   }
   // the value launch also writes the accepted product (1-tau) G[p] + tau T1[p]
-  // of tree 0 into T2[p], so accepting the step is a swap
+  // of tree 0 into T2[p], so accepting the step is a rotation of buffers
   Epilogue epi[4] = {};
-  epi[0].g_out = st->T2[p];
+  epi[0].g_out = v.T2[p];
   epi[0].g_scale = kSg[p];
-  EGT_TRY(launch_passes(g, ps, trees, epi, st->hpart_dev, s, st->prec));
+  EGT_TRY(launch_passes(g, ps, trees, epi, v.part_dev, s, st->prec));
+  *trees_out = trees;
   return EGT_OK;
+}
+
+// Side and step size of an iteration after t accepted steps (the variant's
+// rule: alternate with 2 / (t + 3), the larger mu with 2 / (t + 3), or the
+// larger mu with the shared EGT/as tau).
+void side_and_tau(const egt_state* st, int64_t t, const double mu[2], double tau_as, int* p, double* tau) {
+  const int variant = st->opts.variant;
+  if (variant == EGT_VARIANT_ALT) {
+    *tau = 2.0 / ((double)t + 3.0);
+    *p = (t % 2 == 0) ? 0 : 1;
+  } else if (variant == EGT_VARIANT_BAL) {
+    *tau = 2.0 / ((double)t + 3.0);
+    *p = mu[0] > mu[1] ? 0 : 1;
+  } else {
+    *tau = tau_as;
+    *p = mu[0] > mu[1] ? 0 : 1;
+  }
 }
 
 // Enqueues the next attempt of the current iteration, opening one (side and
@@ -466,28 +560,19 @@ int step_launch(egt_state* st, int player, hipStream_t s) {
   if (player < -1 || player > 1) return fail(EGT_EINVAL, "player must be -1, 0 or 1");
   bool first = false;
   if (!st->step_open) {
-    const int variant = st->opts.variant;
     int p;
     double tau;
-    if (variant == EGT_VARIANT_ALT) {
-      tau = 2.0 / ((double)st->t + 3.0);
-      p = (st->t % 2 == 0) ? 0 : 1;
-    } else if (variant == EGT_VARIANT_BAL) {
-      tau = 2.0 / ((double)st->t + 3.0);
-      p = st->mu[0] > st->mu[1] ? 0 : 1;
-    } else {
-      tau = st->tau;
-      p = st->mu[0] > st->mu[1] ? 0 : 1;
-    }
+    side_and_tau(st, st->t, st->mu, st->tau, &p, &tau);
     if (player >= 0) p = player;
     st->step_open = true;
     st->step_p = p;
     st->step_tau = tau;
     first = true;
   }
-  int rc;
-  if ((rc = attempt(st, st->step_p, st->step_tau, first, s))) return rc;
-  return enqueue_values(st, st->prec == kF64 ? 4 : 2, s);
+  int rc, trees = 0;
+  if ((rc = attempt_v(st, current_view(st), st->step_p, st->step_tau, st->mu, first, s, &trees))) return rc;
+  st->products += 3;
+  return enqueue_values(st, trees, s, st->hpart);
 }
 
 // Waits for the enqueued attempt.  EGT/as with EGV < 0: tau halves and
@@ -498,7 +583,7 @@ int step_finish(egt_state* st, hipStream_t s, int* accepted, double* egv_out, in
   int rc;
   if ((rc = finish_values(st, s))) return rc;
   const double egv = st->hscal[0] + st->hscal[1];
-  const int p = st->step_p, o = 1 - p;
+  const int p = st->step_p;
   double tau = st->step_tau;
   if (st->opts.variant == EGT_VARIANT_AS && egv < 0.0) {
     tau *= 0.5;
@@ -508,11 +593,9 @@ int step_finish(egt_state* st, hipStream_t s, int* accepted, double* egv_out, in
     *accepted = 0;
     return EGT_OK;
   }
-  // accept: G[p] <- (1-tau) G[p] + tau T1[p] (linearity), G[o] <- T2[o]
-  std::swap(st->G[p], st->T2[p]);  // written by the value launch
-  std::swap(st->G[o], st->T2[o]);
-  std::swap(st->X[p], st->Xn[p]);
-  std::swap(st->X[o], st->Xn[o]);
+  // accept: G[p] <- (1-tau) G[p] + tau T1[p] (linearity; written by the value
+  // launch into T2[p]), G[o] <- T2[o], x <- x_+
+  accept_rotate(st);
   st->mu[p] *= (1.0 - tau);
   if (st->opts.variant == EGT_VARIANT_AS) st->tau = tau;
   st->t++;
@@ -632,10 +715,85 @@ int fill_result(egt_state* st, bool converged, double seconds, egt_result* res, 
   return EGT_OK;
 }
 
+// The FP64 iteration with the gap tested every iteration, pipelined: while
+// the host waits for the values of the current attempt, the device already
+// runs the next iteration as if the attempt were accepted (on the rotated
+// buffers of next_view, which leave x, G and x_bar of the current step
+// untouched).  On acceptance that work is the next iteration; on an EGT/as
+// rejection it is discarded and the retry is enqueued behind it.  Every
+// committed attempt is computed exactly as by state_step, so the results are
+// bitwise those of the unpipelined loop.
+int solve_loop_pipelined(egt_state* st, hipStream_t s, const volatile bool* stop, bool* converged) {
+  const egt_solve_opts& op = st->opts;
+  *converged = false;
+  int rc;
+  if (!st->gap_valid && (rc = state_gap(st, nullptr, nullptr, nullptr, s))) return rc;
+  if (st->gap <= op.eps) {
+    *converged = true;
+    return EGT_OK;
+  }
+  if (st->t >= op.max_iters || (stop && *stop)) return EGT_OK;
+  int p, trees = 0, cur = 0;
+  double tau;
+  side_and_tau(st, st->t, st->mu, st->tau, &p, &tau);
+  if ((rc = attempt_v(st, current_view(st), p, tau, st->mu, true, s, &trees))) return rc;
+  EGT_TRY(hipEventRecord(st->ev[cur], s));
+  for (;;) {
+    // the next iteration, assuming acceptance
+    bool spec = false;
+    int p2 = 0, t2 = 0;
+    double tau2 = 0.0;
+    if (st->t + 1 < op.max_iters && !(stop && *stop)) {
+      double mu2[2] = {st->mu[0], st->mu[1]};
+      mu2[p] *= (1.0 - tau);
+      side_and_tau(st, st->t + 1, mu2, op.variant == EGT_VARIANT_AS ? tau : st->tau, &p2, &tau2);
+      if ((rc = attempt_v(st, next_view(st), p2, tau2, mu2, true, s, &t2))) return rc;
+      EGT_TRY(hipEventRecord(st->ev[1 - cur], s));
+      spec = true;
+    }
+    // decide the current attempt
+    hipEvent_t ev = st->ev[cur];
+    if ((rc = wait_for([&] { return hipEventQuery(ev); }, [&] { return hipEventSynchronize(ev); }))) return rc;
+    st->pending_trees = trees;
+    st->pending_part = st->hpart;
+    if ((rc = read_values(st))) return rc;
+    st->products += 3;
+    const double egv = st->hscal[0] + st->hscal[1];
+    if (op.variant == EGT_VARIANT_AS && egv < 0.0) {
+      tau *= 0.5;
+      st->backtracks++;
+      if (tau < kTauFloor) return fail(EGT_ENOTCONV, "tau fell below 1e-30 in the EGT/as backtracking");
+      // retry from x_hat with the halved tau, behind the discarded iteration
+      if ((rc = attempt_v(st, current_view(st), p, tau, st->mu, false, s, &trees))) return rc;
+      EGT_TRY(hipEventRecord(st->ev[cur], s));
+      continue;
+    }
+    accept_rotate(st);
+    st->mu[p] *= (1.0 - tau);
+    if (op.variant == EGT_VARIANT_AS) st->tau = tau;
+    st->t++;
+    st->br_min_x = st->hscal[2];
+    st->br_max_y = -st->hscal[3];
+    st->gap = -st->hscal[3] - st->hscal[2];
+    st->gap_valid = true;
+    st->last_egv = egv;
+    if (st->gap <= op.eps) {
+      *converged = true;
+      return EGT_OK;
+    }
+    if (!spec) return EGT_OK;  // iteration cap or stop
+    p = p2;
+    tau = tau2;
+    trees = t2;
+    cur = 1 - cur;
+  }
+}
+
 // The iteration of egt_solve: gap test before every gap_every-th iteration,
 // stop at gap <= eps or max_iters (or when *stop becomes true).
 int solve_loop(egt_state* st, hipStream_t s, const volatile bool* stop, bool* converged) {
   const egt_solve_opts& op = st->opts;
+  if (st->prec == kF64 && op.gap_every == 1 && !st->step_open) return solve_loop_pipelined(st, s, stop, converged);
   *converged = false;
   int rc = EGT_OK;
   for (;;) {
@@ -679,16 +837,16 @@ int64_t state_bytes(const egt_game* g, bool mixed) {
   const size_t esz = mixed ? sizeof(float) : sizeof(double);
   size_t bytes = 0;
   for (int p = 0; p < 2; ++p) {
-    bytes += esz * 8 * (size_t)vec_elems(g, p) + sizeof(double) * 2 * (size_t)g->hp[p].n_nodes * g->ld;
+    bytes += esz * 11 * (size_t)vec_elems(g, p) + sizeof(double) * 2 * (size_t)g->hp[p].n_nodes * g->ld;
     if (mixed) bytes += sizeof(double) * 3 * (size_t)vec_elems(g, p);
-    bytes += 12 * 256;
+    bytes += 15 * 256;
   }
   bytes += 64 * sizeof(double) + 256;
   return (int64_t)bytes;
 }
 
-// Pinned host doubles of a state: 64 scalars, then the root partial sums.
-size_t state_host_doubles() { return 64 + (size_t)kMaxTrees * kMaxPartials; }
+// Pinned host doubles of a state: 64 scalars, then two buffers of root partial sums.
+size_t state_host_doubles() { return 64 + 2 * (size_t)kMaxTrees * kMaxPartials; }
 
 // Accessors for the batch engine.
 const egt_solve_opts& state_opts(const egt_state* st) { return st->opts; }
