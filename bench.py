@@ -28,11 +28,11 @@ HBM_PEAK_GBS = 8000.0
 # HBM bytes per roofline launch (sbr_fused_kernel, egt_smoothed_br without the
 # value) on the 1081-hand endgame c1, from two rocprofv3 --pmc passes of
 # `bench.py --roofline-only --kernel-reps 50 --copy-calibration-mb 256`:
-# FETCH_SIZE 1126.5 KiB and WRITE_SIZE 1895.5 KiB per dispatch, each scaled
+# FETCH_SIZE 1133.5 KiB and WRITE_SIZE 1895.5 KiB per dispatch, each scaled
 # by the same counter on the plain 256 MiB device copy of that run
 # (FETCH_SIZE reads 131085 KiB of the 262144 KiB copied: factor 2.0;
 # WRITE_SIZE 262144 KiB: factor 1.0).  Valid for this kernel version only.
-SBR_TRAFFIC_BYTES = {"c1": (1126.5 * 2.0 + 1895.5 * 1.0) * 1024}
+SBR_TRAFFIC_BYTES = {"c1": (1133.5 * 2.0 + 1895.5 * 1.0) * 1024}
 
 
 def parse():
