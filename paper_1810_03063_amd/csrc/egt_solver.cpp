@@ -497,7 +497,7 @@ void accept_rotate(egt_state* st) {
 // terms (and in FP64 the two best-response values of the candidate's saddle
 // gap) as root partials in v.part; returns the number of value trees.
 static int attempt_v(egt_state* st, const View& v, int p, double tau, const double mu[2], bool first,
-                     hipStream_t s, int* trees_out) {
+                     hipStream_t s, int* trees_out, bool with_gap = false) {
   const egt_game* g = st->g;
   const int o = 1 - p;
   int rc;
@@ -532,6 +532,18 @@ static int attempt_v(egt_state* st, const View& v, int p, double tau, const doub
   epi[0].g_out = v.T2[p];
   epi[0].g_scale = kSg[p];
   EGT_TRY(launch_passes(g, ps, trees, epi, v.part_dev, s, st->prec));
+  if (with_gap && st->prec == kF32) {
+    // precision form: the candidate's saddle gap in FP64 (widened iterates,
+    // FP64 products, FP64 best responses) as values 2 and 3
+    if ((rc = widen(st, 0, v.Xn[0], st->X64[0], s))) return rc;
+    if ((rc = widen(st, 1, v.Xn[1], st->X64[1], s))) return rc;
+    EGT_TRY(launch_gradient(g, 0, st->X64[1], st->G64[0], s));
+    EGT_TRY(launch_gradient(g, 1, st->X64[0], st->G64[1], s));
+    Pass gp[2];
+    gap_passes(st, st->G64[0], 1.0, nullptr, 0.0, st->G64[1], 1.0, nullptr, 0.0, gp);
+    EGT_TRY(launch_passes(g, gp, 2, nullptr, v.part_dev + 2 * (size_t)n_partials(g), s, kF64));
+    trees = 4;
+  }
   *trees_out = trees;
   return EGT_OK;
 }
@@ -715,35 +727,47 @@ int fill_result(egt_state* st, bool converged, double seconds, egt_result* res, 
   return EGT_OK;
 }
 
-// The FP64 iteration with the gap tested every iteration, pipelined: while
-// the host waits for the values of the current attempt, the device already
-// runs the next iteration as if the attempt were accepted (on the rotated
-// buffers of next_view, which leave x, G and x_bar of the current step
-// untouched).  On acceptance that work is the next iteration; on an EGT/as
-// rejection it is discarded and the retry is enqueued behind it.  Every
-// committed attempt is computed exactly as by state_step, so the results are
-// bitwise those of the unpipelined loop.
+// The iteration of egt_solve, pipelined: while the host waits for the values
+// of the current attempt, the device already runs the next iteration as if
+// the attempt were accepted (on the rotated buffers of next_view, which leave
+// x, G and x_bar of the current step untouched).  On acceptance that work is
+// the next iteration; on an EGT/as rejection it is discarded and the retry is
+// enqueued behind it.  The saddle gap of the iterates the loop tests (every
+// gap_every-th and the last) comes with the attempt that produces them: the
+// FP64 value launch always carries it, the precision form adds its FP64 gap
+// evaluation to that attempt, which is then not run ahead (its FP64 copies of
+// x and A y must survive a converged stop).  Every committed attempt is
+// computed exactly as by state_step, so the results are bitwise those of
+// stepping with a gap test before every gap_every-th iteration.
 int solve_loop_pipelined(egt_state* st, hipStream_t s, const volatile bool* stop, bool* converged) {
   const egt_solve_opts& op = st->opts;
+  const bool mixed = st->prec == kF32;
+  auto gap_due = [&](int64_t t) { return t % op.gap_every == 0 || t >= op.max_iters; };
   *converged = false;
-  int rc;
-  if (!st->gap_valid && (rc = state_gap(st, nullptr, nullptr, nullptr, s))) return rc;
-  if (st->gap <= op.eps) {
-    *converged = true;
-    return EGT_OK;
+  int rc = EGT_OK;
+  if (gap_due(st->t)) {
+    if (!st->gap_valid && (rc = state_gap(st, nullptr, nullptr, nullptr, s))) return rc;
+    if (st->gap <= op.eps) {
+      *converged = true;
+      return EGT_OK;
+    }
   }
-  if (st->t >= op.max_iters || (stop && *stop)) return EGT_OK;
+  if (st->t >= op.max_iters || (stop && *stop)) {
+    if (!st->gap_valid) rc = state_gap(st, nullptr, nullptr, nullptr, s);
+    return rc;
+  }
   int p, trees = 0, cur = 0;
   double tau;
   side_and_tau(st, st->t, st->mu, st->tau, &p, &tau);
-  if ((rc = attempt_v(st, current_view(st), p, tau, st->mu, true, s, &trees))) return rc;
+  bool wg = mixed && gap_due(st->t + 1);
+  if ((rc = attempt_v(st, current_view(st), p, tau, st->mu, true, s, &trees, wg))) return rc;
   EGT_TRY(hipEventRecord(st->ev[cur], s));
   for (;;) {
     // the next iteration, assuming acceptance
     bool spec = false;
     int p2 = 0, t2 = 0;
     double tau2 = 0.0;
-    if (st->t + 1 < op.max_iters && !(stop && *stop)) {
+    if (st->t + 1 < op.max_iters && !(stop && *stop) && !(mixed && gap_due(st->t + 2))) {
       double mu2[2] = {st->mu[0], st->mu[1]};
       mu2[p] *= (1.0 - tau);
       side_and_tau(st, st->t + 1, mu2, op.variant == EGT_VARIANT_AS ? tau : st->tau, &p2, &tau2);
@@ -764,7 +788,7 @@ int solve_loop_pipelined(egt_state* st, hipStream_t s, const volatile bool* stop
       st->backtracks++;
       if (tau < kTauFloor) return fail(EGT_ENOTCONV, "tau fell below 1e-30 in the EGT/as backtracking");
       // retry from x_hat with the halved tau, behind the discarded iteration
-      if ((rc = attempt_v(st, current_view(st), p, tau, st->mu, false, s, &trees))) return rc;
+      if ((rc = attempt_v(st, current_view(st), p, tau, st->mu, false, s, &trees, wg))) return rc;
       EGT_TRY(hipEventRecord(st->ev[cur], s));
       continue;
     }
@@ -772,44 +796,43 @@ int solve_loop_pipelined(egt_state* st, hipStream_t s, const volatile bool* stop
     st->mu[p] *= (1.0 - tau);
     if (op.variant == EGT_VARIANT_AS) st->tau = tau;
     st->t++;
-    st->br_min_x = st->hscal[2];
-    st->br_max_y = -st->hscal[3];
-    st->gap = -st->hscal[3] - st->hscal[2];
-    st->gap_valid = true;
+    if (trees == 4) {
+      st->br_min_x = st->hscal[2];
+      st->br_max_y = -st->hscal[3];
+      st->gap = -st->hscal[3] - st->hscal[2];
+      st->gap_valid = true;
+    } else {
+      st->gap_valid = false;
+    }
     st->last_egv = egv;
-    if (st->gap <= op.eps) {
+    if (gap_due(st->t) && st->gap_valid && st->gap <= op.eps) {
       *converged = true;
       return EGT_OK;
     }
-    if (!spec) return EGT_OK;  // iteration cap or stop
-    p = p2;
-    tau = tau2;
-    trees = t2;
+    if (st->t >= op.max_iters || (stop && *stop)) {
+      if (!st->gap_valid) rc = state_gap(st, nullptr, nullptr, nullptr, s);
+      return rc;
+    }
     cur = 1 - cur;
+    if (spec) {
+      p = p2;
+      tau = tau2;
+      trees = t2;
+      wg = false;
+    } else {
+      side_and_tau(st, st->t, st->mu, st->tau, &p, &tau);
+      wg = mixed && gap_due(st->t + 1);
+      if ((rc = attempt_v(st, current_view(st), p, tau, st->mu, true, s, &trees, wg))) return rc;
+      EGT_TRY(hipEventRecord(st->ev[cur], s));
+    }
   }
 }
 
 // The iteration of egt_solve: gap test before every gap_every-th iteration,
 // stop at gap <= eps or max_iters (or when *stop becomes true).
 int solve_loop(egt_state* st, hipStream_t s, const volatile bool* stop, bool* converged) {
-  const egt_solve_opts& op = st->opts;
-  if (st->prec == kF64 && op.gap_every == 1 && !st->step_open) return solve_loop_pipelined(st, s, stop, converged);
-  *converged = false;
-  int rc = EGT_OK;
-  for (;;) {
-    const bool check = (st->t % op.gap_every == 0) || st->t >= op.max_iters;
-    if (check) {
-      if ((rc = state_gap(st, nullptr, nullptr, nullptr, s))) return rc;
-      if (st->gap <= op.eps) {
-        *converged = true;
-        return EGT_OK;
-      }
-    }
-    if (st->t >= op.max_iters || (stop && *stop)) break;
-    if ((rc = state_step(st, -1, nullptr, nullptr, s))) return rc;
-  }
-  if (!st->gap_valid) rc = state_gap(st, nullptr, nullptr, nullptr, s);
-  return rc;
+  if (st->step_open) return fail(EGT_EINVAL, "a split step is in progress");
+  return solve_loop_pipelined(st, s, stop, converged);
 }
 
 int solve(const egt_game* g, const egt_solve_opts* o, egt_result* res, egt_state** state_out, hipStream_t s) {

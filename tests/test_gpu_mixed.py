@@ -177,3 +177,30 @@ def test_mixed_rejects_nothing_on_the_workload_trees(egt):
         G = egt.Game(make_instance(cfg, 0))
         y = G.empty(1, dtype=torch.float32)
         egt.gradient_mixed(G, 0, y)
+
+
+@pytest.mark.parametrize("cfg,seed,prec,ge", [("c0", 1, "mixed", 10), ("c0", 3, "mixed", 1), ("c0", 2, "fp64", 3)])
+def test_solve_equals_stepping_with_gap_tests(egt, cfg, seed, prec, ge):
+    """egt_solve runs the next iteration ahead while it decides the current
+    one; its result must be bitwise that of plain stepping with a gap test
+    before every ge-th iteration."""
+    inst = make_instance(cfg, seed)
+    print(f"[case] solve vs stepping {cfg} seed={seed} {prec} gap_every={ge}", flush=True)
+    G = egt.Game(inst)
+    eps = 1e-3 * inst.pot
+    r, st1 = egt.solve(G, keep_state=True, precision=prec, gap_every=ge)
+    st2 = egt.State(G, precision=prec, gap_every=ge)
+    t = 0
+    while True:
+        if t % ge == 0:
+            gap, _, _ = st2.gap()
+            if gap <= eps:
+                break
+        st2.step()
+        t += 1
+    a, b = st1.get(), st2.get()
+    assert a["iters"] == b["iters"] == r["iters"]
+    assert torch.equal(a["x"], b["x"]) and torch.equal(a["y"], b["y"])
+    assert r["gap"] == gap
+    st1.close()
+    st2.close()
