@@ -155,9 +155,27 @@ def _edge_instances():
     yield "all-distinct", replace(base, strength=np.random.default_rng(1).permutation(n).astype(np.int32))
     yield "no-raise", replace(base, max_raises=0)
     yield "no-bets", replace(base, bet_fracs=(), allin=False)
+    # 16 actions at the first decision (check, 14 bet sizes, all-in): the most a node may have
+    yield "max-actions", replace(base, bet_fracs=tuple(0.1 * (i + 1) for i in range(14)), max_raises=0)
+    # the largest hand count the library takes (2048): 65-card deck, 2048 of
+    # its two-card hands, no board, ragged strength ties
+    from instances.endgames import Instance
+
+    rng = np.random.default_rng(11)
+    pairs = np.array([(a, c) for a in range(65) for c in range(a + 1, 65)], dtype=np.int32)[:2048]
+    bl = rng.dirichlet(np.full(2048, 0.5), size=2)
+    yield "max-hands", Instance(name="max-hands", n_cards=65, cards_per_hand=2, board=np.zeros(0, dtype=np.int32),
+                                hand_cards=pairs, strength=rng.integers(0, 400, 2048).astype(np.int32), belief=bl,
+                                pot=100.0, stack=300.0, bet_fracs=(1.0,), allin=True, max_raises=1)
+    # two one-card hands (30 padding slots in every row)
+    yield "two-hands", Instance(name="two-hands", n_cards=2, cards_per_hand=1, board=np.zeros(0, dtype=np.int32),
+                                hand_cards=np.arange(2, dtype=np.int32).reshape(2, 1),
+                                strength=np.arange(2, dtype=np.int32), belief=np.full((2, 2), 0.5), pot=2.0,
+                                stack=4.0, bet_fracs=(0.5, 1.0), allin=True, max_raises=2)
 
 
-@pytest.mark.parametrize("name", ["zero-beliefs", "all-tied", "all-distinct", "no-raise", "no-bets"])
+@pytest.mark.parametrize("name", ["zero-beliefs", "all-tied", "all-distinct", "no-raise", "no-bets", "max-actions",
+                                  "max-hands", "two-hands"])
 def test_edge_cases(egt, name):
     inst = dict(_edge_instances())[name]
     _, P, G, L = setup(egt, name, 0, inst=inst)
