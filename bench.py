@@ -161,8 +161,9 @@ def precision_form(egt, torch, G, steps, fp64_ms, fp64_value, reps):
 
 def serving(egt, args):
     """Poisson trace of solve requests (shapes drawn uniformly), continuously
-    batched in the precision form under an HBM budget (and, for comparison,
-    batched in FP64), against the same trace served one at a time in FP64."""
+    batched in the precision form under an HBM budget: all at t = 0 (the
+    batched capacity R), then Poisson at 0.5 R and 0.9 R; at 0.9 R also
+    batched in FP64 and served one at a time in FP64 (the baseline)."""
     from instances import make_instance
     from instances.endgames import serving_trace
     from paper_1810_03063_amd.serve import LibEngine, Request, serve, serve_sequential, summarize
@@ -182,9 +183,11 @@ def serving(egt, args):
         return summarize(out, wall)
 
     saturated = run(0.0)  # every request at t = 0: the batched throughput R
-    rate = 0.7 * saturated["solves_per_sec"]
-    loaded = run(rate)
-    loaded64 = run(rate, "fp64")
+    rate_lo, rate_hi = 0.5 * saturated["solves_per_sec"], 0.9 * saturated["solves_per_sec"]
+    loaded_lo = run(rate_lo)
+    loaded = run(rate_hi)
+    loaded64 = run(rate_hi, "fp64")
+    rate = rate_hi
     print("serving: batched runs done", file=sys.stderr, flush=True)
 
     def solve_one(r):
@@ -196,6 +199,7 @@ def serving(egt, args):
     seq_out, seq_wall = serve_sequential(solve_one, reqs_for(rate))
     baseline = summarize(seq_out, seq_wall)
     return dict(shapes=list(shapes), requests=n, budget_gb=args.serve_budget_gb, saturated=saturated,
+                poisson_rate_half_per_s=rate_lo, batched_half=loaded_lo,
                 poisson_rate_per_s=rate, batched=loaded, batched_fp64=loaded64, sequential_fp64=baseline,
                 throughput_vs_sequential=loaded["solves_per_sec"] / baseline["solves_per_sec"],
                 fp64_batched_vs_sequential=loaded64["solves_per_sec"] / baseline["solves_per_sec"])
@@ -245,8 +249,12 @@ def main():
     G = egt.Game(inst)
     torch.cuda.synchronize()
     if args.roofline_only:
+        y32 = egt.uniform(G, 1).float().contiguous()
+        out32 = G.empty(0, dtype=torch.float32)
+        prod_s = _timed(torch, lambda: egt.gradient_mixed(G, 0, y32, out32), args.kernel_reps)
         print(json.dumps({"roofline": kernel_roofline(egt, torch, G, args.kernel_reps, args.config),
-                          "roofline_gradient": gradient_roofline(egt, torch, G, args.kernel_reps)}), flush=True)
+                          "roofline_gradient": gradient_roofline(egt, torch, G, args.kernel_reps),
+                          "mixed_product_us": round(prod_s * 1e6, 3)}), flush=True)
         return
     for _ in range(args.warmup):
         r, _ = egt.solve(G, variant=args.variant)
