@@ -254,10 +254,13 @@ int egt_state_gap(egt_state* state, double* gap, double* br_max_y, double* br_mi
                   hipStream_t stream);
 
 /* Runs EGT until gap <= eps (tested before each iteration, every gap_every
- * iterations) or max_iters.  The final iterates stay in the state if
- * state_out is not NULL (the caller then owns it), else they are freed.
- * Returns EGT_OK when converged, EGT_ENOTCONV at the iteration cap (result
- * still filled). */
+ * iterations) or max_iters.  While the host decides one iteration (the
+ * EGT/as accept-or-halve test) the device already runs the next one on spare
+ * buffers; results are bitwise those of egt_step in a loop with the same gap
+ * tests.  The final iterates stay in the state if state_out is not NULL (the
+ * caller then owns it), else they are freed.  Returns EGT_OK when converged,
+ * EGT_ENOTCONV at the iteration cap (result still filled); `stream` is idle
+ * on return. */
 int egt_solve(const egt_game* game, const egt_solve_opts* opts, egt_result* result,
               egt_state** state_out, hipStream_t stream);
 
