@@ -221,8 +221,12 @@ int finish_player(const Enumerator& en, int p, HostPlayer& hp, std::vector<int>&
     for (int j = 0; j < d; ++j) hp.anc[(size_t)s * kMaxDepth + j] = path[d - 1 - j];
   }
   hp.max_level_width = 0;
-  for (int l = 0; l < hp.n_levels; ++l)
+  hp.level_max_act.assign(hp.n_levels, 0);
+  for (int l = 0; l < hp.n_levels; ++l) {
     hp.max_level_width = std::max(hp.max_level_width, hp.level_begin[l + 1] - hp.level_begin[l]);
+    for (int i = hp.level_begin[l]; i < hp.level_begin[l + 1]; ++i)
+      hp.level_max_act[l] = std::max(hp.level_max_act[l], hp.node_nact[i]);
+  }
   // table image of the single-launch pass
   const FusedTabLayout L = fused_tab_layout(nn, ns);
   hp.fused_tab.assign((size_t)L.bytes, 0);

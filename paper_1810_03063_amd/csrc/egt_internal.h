@@ -181,6 +181,7 @@ struct HostPlayer {
   std::vector<int> node_first_seq, node_nact, node_level;
   std::vector<double> node_beta, node_logn;
   std::vector<int> level_begin;  // [n_levels + 1]
+  std::vector<int> level_max_act;  // [n_levels] most actions of a node at each level
   std::vector<int> seq_parent, child_begin, child;
   std::vector<int> term_begin, term_opp, term_kind;
   std::vector<double> term_coef;

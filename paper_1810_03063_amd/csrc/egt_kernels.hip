@@ -32,6 +32,11 @@ constexpr int kMaxHandsPerThread = 8;  // n <= 2048 = 256 threads x 8 contiguous
 constexpr int kPassThreads = 64;       // per-level pass: one wavefront per (node, 64 hands)
 constexpr int kFusedSlots = 64;        // fused pass: node slots per block (x HB hands per slot)
 
+// Explicit fused multiply-adds for the expressions that the level-path kernel
+// variants share, so that every variant rounds them identically.
+__device__ inline double fmadd(double a, double b, double c) { return __builtin_fma(a, b, c); }
+__device__ inline float fmadd(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+
 __device__ inline double wave_inclusive_scan(double x, int lane) {
 #pragma unroll
   for (int off = 1; off < 64; off <<= 1) {
@@ -73,9 +78,14 @@ struct GradArgs {
   int fold_only;  // skip showdown terminals (their part is added by the BF16 GEMM)
 };
 
-template <class TV, class TO>
-__global__ __launch_bounds__(2 * kGroupThreads) void gradient_kernel(GradArgs<TV, TO> a) {
+// HPT = hands per thread (n <= 256 HPT).  MINW = the waves per SIMD the
+// register allocation must leave room for: 4 lets two blocks share a compute
+// unit (a few per-hand values then live in scratch between uses), which pays
+// when each block loops over many sequences.
+template <class TV, class TO, int HPT, int MINW>
+__global__ __launch_bounds__(2 * kGroupThreads, MINW) void gradient_kernel(GradArgs<TV, TO> a) {
   constexpr int kCU = 2;  // card-image loads per thread in the first batch
+  constexpr int kWalk = MINW > 1 ? 4 : 8;  // LDS loads in flight per card walk step (fewer under the VGPR cap)
   extern __shared__ __align__(16) double lds[];
   __shared__ double wave_total[2][kGroupThreads / 64];
   const int n = a.H.n, ld = a.H.ld;
@@ -100,24 +110,21 @@ __global__ __launch_bounds__(2 * kGroupThreads) void gradient_kernel(GradArgs<TV
   // positions this thread stages, and the card image (into LDS).  The tables
   // stay for every sequence the block then processes.
   TermRec tr = grp < MT && (int)blockIdx.x < n_seq ? a.own.term_rec[(size_t)blockIdx.x * MT + grp] : none;
-  int4 HA[kMaxHandsPerThread], HB[kMaxHandsPerThread];
-  int2 TG[kMaxHandsPerThread];
-  double bown[kMaxHandsPerThread], bopp[kMaxHandsPerThread];
+  int4 HA[HPT], HB[HPT];
+  int2 TG[HPT];
+  double bown[HPT];
 #pragma unroll
-  for (int k = 0; k < kMaxHandsPerThread; ++k) {
+  for (int k = 0; k < HPT; ++k) {
     HA[k] = make_int4(0, 0, 0, 0);
     HB[k] = make_int4(0, 0, 0, 0);
     TG[k] = make_int2(0, 0);
     bown[k] = 0.0;
-    bopp[k] = 0.0;
     if (k < cnt) {
       HA[k] = a.H.ha[beg + k];
       if (a.H.cph == 2) HB[k] = a.H.hb[beg + k];
       TG[k] = a.H.tie[beg + k];
       bown[k] = a.own.belief[beg + k];
     }
-    const int i = gt + k * kGroupThreads;
-    if (i < n) bopp[k] = a.b_opp[i];
   }
   {
     const uint4* img = (const uint4*)a.H.card_img;
@@ -142,9 +149,9 @@ __global__ __launch_bounds__(2 * kGroupThreads) void gradient_kernel(GradArgs<TV
   // the next sequence's first terminal, requested while this one runs
   const int s_next = s + (int)gridDim.x;
   const TermRec tr_next = grp < MT && s_next < n_seq ? a.own.term_rec[(size_t)s_next * MT + grp] : none;
-  double acc[kMaxHandsPerThread];
+  double acc[HPT];
 #pragma unroll
-  for (int k = 0; k < kMaxHandsPerThread; ++k) acc[k] = 0.0;
+  for (int k = 0; k < HPT; ++k) acc[k] = 0.0;
   for (int rd = 0; rd < rounds; ++rd) {
     const int j = rd * groups + grp;
     if (rd > 0) tr = j < MT ? recs[j] : none;
@@ -154,25 +161,27 @@ __global__ __launch_bounds__(2 * kGroupThreads) void gradient_kernel(GradArgs<TV
     const double coef = tr.coef;
     if (active) {
       const TV* v = tr.opp >= 0 ? a.v_opp + (size_t)tr.opp * ld : nullptr;
-      double vv[kMaxHandsPerThread];
+      // the opponent's prior is read with the row (it stays in the caches)
+      double vv[HPT], bo[HPT];
 #pragma unroll
-      for (int k = 0; k < kMaxHandsPerThread; ++k) {
+      for (int k = 0; k < HPT; ++k) {
         const int i = gt + k * kGroupThreads;
         vv[k] = (v && i < n) ? (double)v[i] : 1.0;
+        bo[k] = i < n ? a.b_opp[i] : 0.0;
       }
 #pragma unroll
-      for (int k = 0; k < kMaxHandsPerThread; ++k) {
+      for (int k = 0; k < HPT; ++k) {
         const int i = gt + k * kGroupThreads;
-        if (i < n) R[i] = bopp[k] * vv[k];
+        if (i < n) R[i] = bo[k] * vv[k];
       }
     }
     __syncthreads();
-    double rloc[kMaxHandsPerThread];
+    double rloc[HPT];
 #pragma unroll
-    for (int k = 0; k < kMaxHandsPerThread; ++k) rloc[k] = 0.0;
+    for (int k = 0; k < HPT; ++k) rloc[k] = 0.0;
     if (active) {
 #pragma unroll
-      for (int k = 0; k < kMaxHandsPerThread; ++k) rloc[k] = k < cnt ? R[beg + k] : 0.0;
+      for (int k = 0; k < HPT; ++k) rloc[k] = k < cnt ? R[beg + k] : 0.0;
       // Per-card exclusive prefixes over the card's strength-ordered hands:
       // four lanes per card, each a contiguous quarter of the list; the
       // quarter offsets are added in a fixed order.
@@ -186,24 +195,24 @@ __global__ __launch_bounds__(2 * kGroupThreads) void gradient_kernel(GradArgs<TV
         const int lo = min(sub * qlen, len), hi = min(lo + qlen, len);
         double part = 0.0;
         int k = lo;
-        for (; k + 8 <= hi; k += 8) {
-          double v[8];
+        for (; k + kWalk <= hi; k += kWalk) {
+          double v[kWalk];
 #pragma unroll
-          for (int j = 0; j < 8; ++j) v[j] = R[chand[cb + k + j]];
+          for (int j = 0; j < kWalk; ++j) v[j] = R[chand[cb + k + j]];
 #pragma unroll
-          for (int j = 0; j < 8; ++j) part += v[j];
+          for (int j = 0; j < kWalk; ++j) part += v[j];
         }
         for (; k < hi; ++k) part += R[chand[cb + k]];
         const int l0 = lane & ~3;
         const double p0 = __shfl(part, l0, 64), p1 = __shfl(part, l0 + 1, 64), p2 = __shfl(part, l0 + 2, 64);
         double run = sub == 0 ? 0.0 : sub == 1 ? p0 : sub == 2 ? p0 + p1 : (p0 + p1) + p2;
         k = lo;
-        for (; k + 8 <= hi; k += 8) {
-          double v[8];
+        for (; k + kWalk <= hi; k += kWalk) {
+          double v[kWalk];
 #pragma unroll
-          for (int j = 0; j < 8; ++j) v[j] = R[chand[cb + k + j]];
+          for (int j = 0; j < kWalk; ++j) v[j] = R[chand[cb + k + j]];
 #pragma unroll
-          for (int j = 0; j < 8; ++j) {
+          for (int j = 0; j < kWalk; ++j) {
             Pc[base + k + j] = run;
             run += v[j];
           }
@@ -219,7 +228,7 @@ __global__ __launch_bounds__(2 * kGroupThreads) void gradient_kernel(GradArgs<TV
     double local = 0.0, incl = 0.0;
     if (active) {
 #pragma unroll
-      for (int k = 0; k < kMaxHandsPerThread; ++k) local += rloc[k];
+      for (int k = 0; k < HPT; ++k) local += rloc[k];
       incl = wave_inclusive_scan(local, lane);
       if (lane == 63) wave_total[grp][wig] = incl;
     }
@@ -228,7 +237,7 @@ __global__ __launch_bounds__(2 * kGroupThreads) void gradient_kernel(GradArgs<TV
       double run = incl - local;
       for (int w = 0; w < wig; ++w) run += wave_total[grp][w];
 #pragma unroll
-      for (int k = 0; k < kMaxHandsPerThread; ++k) {
+      for (int k = 0; k < HPT; ++k) {
         if (k < cnt) {
           R[beg + k] = run;
           run += rloc[k];
@@ -240,7 +249,7 @@ __global__ __launch_bounds__(2 * kGroupThreads) void gradient_kernel(GradArgs<TV
     if (active) {
       const double T = R[n];
 #pragma unroll
-      for (int k = 0; k < kMaxHandsPerThread; ++k) {
+      for (int k = 0; k < HPT; ++k) {
         if (k < cnt) {
           const int4 A = HA[k];
           double op;
@@ -267,21 +276,21 @@ __global__ __launch_bounds__(2 * kGroupThreads) void gradient_kernel(GradArgs<TV
   if (groups == 2) {
     if (grp == 1) {
 #pragma unroll
-      for (int k = 0; k < kMaxHandsPerThread; ++k)
+      for (int k = 0; k < HPT; ++k)
         if (k < cnt) R[beg + k] = acc[k];
     }
     __syncthreads();
     if (grp == 0) {
       const double* R1 = lds + per_group;
 #pragma unroll
-      for (int k = 0; k < kMaxHandsPerThread; ++k)
+      for (int k = 0; k < HPT; ++k)
         if (k < cnt) acc[k] += R1[beg + k];
     }
   }
   if (grp == 0) {
     TO* row = a.out + (size_t)s * ld;
 #pragma unroll
-    for (int k = 0; k < kMaxHandsPerThread; ++k)
+    for (int k = 0; k < HPT; ++k)
       if (k < cnt) row[beg + k] = (TO)(acc[k] * (bown[k] * a.H.invZ));
     for (int i = n + gt; i < ld; i += kGroupThreads) row[i] = (TO)0;
   }
@@ -586,7 +595,7 @@ __global__ __launch_bounds__(kPassThreads) void bottom_up_level_kernel(PassSet a
     if (j < na) {
       const size_t idx = (size_t)(s0 + j) * ld + h;
       double x = t.cA * (double)gA[idx];
-      if (gB) x += t.cB * (double)gB[idx];
+      if (gB) x = fmadd(t.cB, (double)gB[idx], x);
       if (g_out) g_out[idx] = (TG)(x * t.g_scale);
       const int c1 = cbeg[s0 + j + 1];
       for (int c = cbeg[s0 + j]; c < c1; ++c) x += t.V[(size_t)c * ld + h];
@@ -618,12 +627,235 @@ __global__ __launch_bounds__(kPassThreads) void bottom_up_level_kernel(PassSet a
       }
     }
   }
-  t.V[(size_t)r.z * ld + h] = (m - temp * log(sum)) + temp * p1.x;
+  t.V[(size_t)r.z * ld + h] = fmadd(temp, p1.x, fmadd(-temp, log(sum), m));
   if (t.QB) {
     const double inv_sum = 1.0 / sum;
 #pragma unroll
     for (int j = 0; j < kMaxActions; ++j)
       if (j < na) ((TG*)t.QB)[(size_t)(s0 + j) * ld + h] = (TG)(g[j] * inv_sum);
+  }
+}
+
+// The lowest level (no node has children) with two adjacent hands per lane:
+// one 16-byte access per gradient row (8 bytes in FP32), half the wavefronts.
+// Used when every row pointer is aligned to two elements; per hand the
+// arithmetic is the one above, and slots h >= n are not written.
+template <class TG>
+__device__ inline void store_pair(TG* p, double x0, double x1, bool both) {
+  using V2 = typename std::conditional<std::is_same<TG, float>::value, float2, double2>::type;
+  if (both) {
+    V2 o;
+    o.x = (TG)x0;
+    o.y = (TG)x1;
+    *(V2*)p = o;
+  } else {
+    p[0] = (TG)x0;
+  }
+}
+
+template <class TG>
+__global__ __launch_bounds__(kPassThreads) void bottom_up_leaf_pair_kernel(PassSet a) {
+  using V2 = typename std::conditional<std::is_same<TG, float>::value, float2, double2>::type;
+  int y = blockIdx.y, k = 0;
+  while (k < a.count - 1 && y >= a.level_cnt[k]) {
+    y -= a.level_cnt[k];
+    ++k;
+  }
+  const TreePass& t = a.t[k];
+  const int h = 2 * (blockIdx.x * kPassThreads + threadIdx.x);
+  if (h >= a.n) return;
+  const bool both = h + 1 < a.n;
+  const size_t ld = a.ld;
+  const int v = t.level_begin[a.level] + y;
+  const FusedTabLayout L = fused_tab_layout(t.P.n_nodes, t.P.n_seq);
+  const unsigned char* tab = (const unsigned char*)t.P.fused_tab;
+  const int4 r = ((const int4*)(tab + L.rec))[v];
+  const double2 p0 = ((const double2*)(tab + L.prm))[2 * v], p1 = ((const double2*)(tab + L.prm))[2 * v + 1];
+  const int s0 = r.x, na = r.y;
+  const TG* gA = (const TG*)t.gA;
+  const TG* gB = (const TG*)t.gB;
+  TG* g_out = (TG*)t.g_out;
+  double g0[kMaxActions], g1[kMaxActions];
+  double m0 = INFINITY, m1 = INFINITY;
+#pragma unroll
+  for (int j = 0; j < kMaxActions; ++j) {
+    if (j < na) {
+      const size_t idx = (size_t)(s0 + j) * ld + h;
+      const V2 A = *(const V2*)(gA + idx);
+      double x0 = t.cA * (double)A.x, x1 = t.cA * (double)A.y;
+      if (gB) {
+        const V2 B = *(const V2*)(gB + idx);
+        x0 = fmadd(t.cB, (double)B.x, x0);
+        x1 = fmadd(t.cB, (double)B.y, x1);
+      }
+      if (g_out) store_pair(g_out + idx, x0 * t.g_scale, x1 * t.g_scale, both);
+      g0[j] = x0;
+      g1[j] = x1;
+      m0 = fmin(m0, x0);
+      m1 = fmin(m1, x1);
+    }
+  }
+  double* Vrow = t.V + (size_t)r.z * ld + h;
+  if (!(t.mu > 0.0)) {
+    store_pair(Vrow, m0, m1, both);
+    return;
+  }
+  const double temp = t.mu * p0.x;
+  const double inv_temp = (1.0 / t.mu) * p0.y;
+  double sum0 = 0.0, sum1 = 0.0;
+#pragma unroll
+  for (int j = 0; j < kMaxActions; ++j) {
+    if (j < na) {
+      if constexpr (std::is_same<TG, float>::value) {
+        g0[j] = (double)expf((float)((m0 - g0[j]) * inv_temp));
+        g1[j] = (double)expf((float)((m1 - g1[j]) * inv_temp));
+      } else {
+        g0[j] = exp((m0 - g0[j]) * inv_temp);
+        g1[j] = exp((m1 - g1[j]) * inv_temp);
+      }
+      sum0 += g0[j];
+      sum1 += g1[j];
+    }
+  }
+  store_pair(Vrow, fmadd(temp, p1.x, fmadd(-temp, log(sum0), m0)), fmadd(temp, p1.x, fmadd(-temp, log(sum1), m1)),
+             both);
+  if (t.QB) {
+    const double inv0 = 1.0 / sum0, inv1 = 1.0 / sum1;
+#pragma unroll
+    for (int j = 0; j < kMaxActions; ++j)
+      if (j < na) store_pair((TG*)t.QB + (size_t)(s0 + j) * ld + h, g0[j] * inv0, g1[j] * inv1, both);
+  }
+}
+
+// Levels above the lowest (every node has child nodes): the same evaluation
+// with the actions in parallel.  Block = (node, 64 x HP hands) x `blockDim.y`
+// wavefronts (the level's most actions); wavefront j takes action j for HP
+// adjacent hands per lane (HP = 2 when every row is 2-element aligned): its
+// gradients and its children, whose value slots [cbeg[s], cbeg[s + 1]) are
+// read in batches of kChildBatch so that one round trip covers them all and
+// added in slot order.  The node's g~ and weights meet in LDS; the minimum,
+// the weight sum and the value are then formed in the same order as above, so
+// per hand the result is bitwise the one the one-wavefront form gives.
+template <class TG, int HP>
+__global__ __launch_bounds__(kPassThreads * kMaxActions) void bottom_up_internal_kernel(PassSet a) {
+  static_assert(HP == 1 || HP == 2, "one or two hands per lane");
+  using V2 = typename std::conditional<std::is_same<TG, float>::value, float2, double2>::type;
+  constexpr int kChildBatch = 8;
+  constexpr int W = HP * kPassThreads;
+  __shared__ double gl[kMaxActions][W];
+  __shared__ double wl[kMaxActions][W];
+  int y = blockIdx.y, k = 0;
+  while (k < a.count - 1 && y >= a.level_cnt[k]) {
+    y -= a.level_cnt[k];
+    ++k;
+  }
+  const TreePass& t = a.t[k];
+  const int lane = threadIdx.x, j = threadIdx.y;
+  const int h = HP * (blockIdx.x * kPassThreads + lane);  // the lane's first hand; h + 1 < ld when HP = 2
+  const bool both = HP == 2 && h + 1 < a.n;
+  const size_t ld = a.ld;
+  const int v = t.level_begin[a.level] + y;
+  const FusedTabLayout L = fused_tab_layout(t.P.n_nodes, t.P.n_seq);
+  const unsigned char* tab = (const unsigned char*)t.P.fused_tab;
+  const int4 r = ((const int4*)(tab + L.rec))[v];
+  const double2 p0 = ((const double2*)(tab + L.prm))[2 * v], p1 = ((const double2*)(tab + L.prm))[2 * v + 1];
+  const int* cbeg = (const int*)(tab + L.cbeg);
+  const int s0 = r.x, na = r.y;
+  const bool live = h < a.n;
+  const bool act = live && j < na;
+  auto load2 = [&](const TG* p, double& x0, double& x1) {
+    if constexpr (HP == 2) {
+      const V2 q = *(const V2*)p;
+      x0 = (double)q.x;
+      x1 = (double)q.y;
+    } else {
+      x0 = (double)p[0];
+      x1 = 0.0;
+    }
+  };
+  auto store2 = [&](auto* p, double x0, double x1) {
+    if constexpr (HP == 2)
+      store_pair(p, x0, x1, both);
+    else
+      p[0] = (std::remove_pointer_t<decltype(p)>)x0;
+  };
+  if (act) {
+    const size_t idx = (size_t)(s0 + j) * ld + h;
+    double x0, x1, b0, b1;
+    load2((const TG*)t.gA + idx, x0, x1);
+    x0 = t.cA * x0;
+    x1 = t.cA * x1;
+    if (t.gB) {
+      load2((const TG*)t.gB + idx, b0, b1);
+      x0 = fmadd(t.cB, b0, x0);
+      x1 = fmadd(t.cB, b1, x1);
+    }
+    if (t.g_out) store2((TG*)t.g_out + idx, x0 * t.g_scale, x1 * t.g_scale);
+    const int c0 = cbeg[s0 + j], c1 = cbeg[s0 + j + 1];
+    for (int c = c0; c < c1; c += kChildBatch) {
+      double cv0[kChildBatch], cv1[kChildBatch];
+#pragma unroll
+      for (int u = 0; u < kChildBatch; ++u) {
+        cv0[u] = 0.0;
+        cv1[u] = 0.0;
+        if (c + u < c1) {
+          const double* vp = t.V + (size_t)(c + u) * ld + h;
+          if constexpr (HP == 2) {
+            const double2 q = *(const double2*)vp;
+            cv0[u] = q.x;
+            cv1[u] = q.y;
+          } else {
+            cv0[u] = vp[0];
+          }
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < kChildBatch; ++u)
+        if (c + u < c1) {
+          x0 += cv0[u];
+          x1 += cv1[u];
+        }
+    }
+    gl[j][lane] = x0;
+    if constexpr (HP == 2) gl[j][kPassThreads + lane] = x1;
+  }
+  __syncthreads();
+  double m0 = INFINITY, m1 = INFINITY;
+  if (act)
+    for (int i = 0; i < na; ++i) {
+      m0 = fmin(m0, gl[i][lane]);
+      if constexpr (HP == 2) m1 = fmin(m1, gl[i][kPassThreads + lane]);
+    }
+  double* Vrow = t.V + (size_t)r.z * ld + h;
+  if (!(t.mu > 0.0)) {
+    if (act && j == 0) store2(Vrow, m0, m1);
+    return;
+  }
+  const double temp = t.mu * p0.x;
+  const double inv_temp = (1.0 / t.mu) * p0.y;
+  double w0 = 0.0, w1 = 0.0;
+  if (act) {
+    if constexpr (std::is_same<TG, float>::value) {
+      w0 = (double)expf((float)((m0 - gl[j][lane]) * inv_temp));
+      if constexpr (HP == 2) w1 = (double)expf((float)((m1 - gl[j][kPassThreads + lane]) * inv_temp));
+    } else {
+      w0 = exp((m0 - gl[j][lane]) * inv_temp);
+      if constexpr (HP == 2) w1 = exp((m1 - gl[j][kPassThreads + lane]) * inv_temp);
+    }
+    wl[j][lane] = w0;
+    if constexpr (HP == 2) wl[j][kPassThreads + lane] = w1;
+  }
+  __syncthreads();
+  if (act) {
+    double sum0 = 0.0, sum1 = 0.0;
+    for (int i = 0; i < na; ++i) {
+      sum0 += wl[i][lane];
+      if constexpr (HP == 2) sum1 += wl[i][kPassThreads + lane];
+    }
+    if (j == 0)
+      store2(Vrow, fmadd(temp, p1.x, fmadd(-temp, log(sum0), m0)),
+             HP == 2 ? fmadd(temp, p1.x, fmadd(-temp, log(sum1), m1)) : 0.0);
+    if (t.QB) store2((TG*)t.QB + (size_t)(s0 + j) * ld + h, w0 * (1.0 / sum0), HP == 2 ? w1 * (1.0 / sum1) : 0.0);
   }
 }
 
@@ -699,7 +931,57 @@ __global__ __launch_bounds__(kPassThreads) void top_down_kernel(DownArgs a) {
     if (path[j] >= 0) val *= f[j];
   const TS xp = comb_out ? x_prev[idx] : (TS)0;
   if (q_out) q_out[idx] = val;
-  if (comb_out) comb_out[idx] = (TS)(1.0 - a.tau) * xp + (TS)a.tau * val;
+  if (comb_out) comb_out[idx] = fmadd((TS)a.tau, val, (TS)(1.0 - a.tau) * xp);
+}
+
+// The same with two adjacent hands per lane (one 16-byte access per row for
+// FP64, 8 bytes for FP32), halving the wavefronts; used when every row
+// pointer is aligned to two elements.  Per hand the arithmetic is the one
+// above.
+template <class TS>
+__global__ __launch_bounds__(kPassThreads) void top_down_pair_kernel(DownArgs a) {
+  using V2 = typename std::conditional<std::is_same<TS, float>::value, float2, double2>::type;
+  const TS* QB = (const TS*)a.QB;
+  TS* q_out = (TS*)a.q_out;
+  TS* comb_out = (TS*)a.comb_out;
+  const TS* x_prev = (const TS*)a.x_prev;
+  const int h = 2 * (blockIdx.x * kPassThreads + threadIdx.x);  // ld is even: h + 1 < ld too
+  const int s = blockIdx.y;
+  if (h >= a.ld) return;
+  const size_t idx = (size_t)s * a.ld + h;
+  const int* path = a.anc + (size_t)s * kMaxDepth;
+  V2 f[kMaxDepth];
+#pragma unroll
+  for (int j = 0; j < kMaxDepth; ++j) {
+    const int q = path[j];
+    if (q >= 0) {
+      f[j] = *(const V2*)(QB + (size_t)q * a.ld + h);
+    } else {
+      f[j].x = (TS)1;
+      f[j].y = (TS)1;
+    }
+  }
+  TS v0 = (TS)1, v1 = (TS)1;
+#pragma unroll
+  for (int j = 0; j < kMaxDepth; ++j)
+    if (path[j] >= 0) {
+      v0 *= f[j].x;
+      v1 *= f[j].y;
+    }
+  const bool live0 = h < a.n, live1 = h + 1 < a.n;
+  if (q_out) {
+    V2 o;
+    o.x = live0 ? v0 : (TS)0;
+    o.y = live1 ? v1 : (TS)0;
+    *(V2*)(q_out + idx) = o;
+  }
+  if (comb_out) {
+    const V2 xp = *(const V2*)(x_prev + idx);
+    V2 o;
+    o.x = live0 ? fmadd((TS)a.tau, v0, (TS)(1.0 - a.tau) * xp.x) : (TS)0;
+    o.y = live1 ? fmadd((TS)a.tau, v1, (TS)(1.0 - a.tau) * xp.y) : (TS)0;
+    *(V2*)(comb_out + idx) = o;
+  }
 }
 
 struct UniformArgs {
@@ -775,7 +1057,16 @@ static hipError_t gradient_launch(const egt_game* g, int player, const TV* v_opp
   // one block per sequence up to two blocks per compute unit; beyond that each
   // block loops over sequences (the tables are staged once per block)
   const int blocks = std::min(g->dp[player].n_seq, 2 * g->n_cu);
-  hipLaunchKernelGGL((gradient_kernel<TV, TO>), dim3(blocks), dim3(kGroupThreads * groups), lds, s, a);
+  const dim3 grid(blocks), block(kGroupThreads * groups);
+  const bool looping = g->dp[player].n_seq > g->n_cu;  // blocks of the second round would wait for a CU
+  if (g->n <= 2 * kGroupThreads)
+    hipLaunchKernelGGL((gradient_kernel<TV, TO, 2, 1>), grid, block, lds, s, a);
+  else if (g->n <= 5 * kGroupThreads && looping)
+    hipLaunchKernelGGL((gradient_kernel<TV, TO, 5, 4>), grid, block, lds, s, a);
+  else if (g->n <= 5 * kGroupThreads)
+    hipLaunchKernelGGL((gradient_kernel<TV, TO, 5, 1>), grid, block, lds, s, a);
+  else
+    hipLaunchKernelGGL((gradient_kernel<TV, TO, kMaxHandsPerThread, 1>), grid, block, lds, s, a);
   return hipGetLastError();
 }
 
@@ -860,6 +1151,17 @@ static hipError_t passes_launch(const egt_game* g, const Pass* p, int count, con
   int max_levels = 0;
   for (int k = 0; k < count; ++k) max_levels = std::max(max_levels, a.t[k].n_levels);
   const unsigned bx = (unsigned)((g->n + kPassThreads - 1) / kPassThreads);
+  const unsigned bx_pair = (unsigned)(((g->n + 1) / 2 + kPassThreads - 1) / kPassThreads);
+  // two hands per lane when every row is 2-element aligned
+  bool pair = g->ld % 2 == 0;
+  {
+    const size_t pb = 2 * (std::is_same<TG, float>::value ? sizeof(float) : sizeof(double));
+    auto ok = [&](const void* ptr) { return ((uintptr_t)ptr % pb) == 0; };
+    for (int k = 0; k < count; ++k) {
+      const TreePass& t = a.t[k];
+      pair = pair && ok(t.gA) && ok(t.gB) && ok(t.g_out) && ok(t.QB) && ((uintptr_t)t.V % 16) == 0;
+    }
+  }
   for (int l = 0; l < max_levels; ++l) {
     unsigned total = 0;
     for (int k = 0; k < count; ++k) {
@@ -869,7 +1171,22 @@ static hipError_t passes_launch(const egt_game* g, const Pass* p, int count, con
     }
     if (total == 0) continue;
     a.level = l;
-    hipLaunchKernelGGL(bottom_up_level_kernel<TG>, dim3(bx, total), dim3(kPassThreads), 0, s, a);
+    if (l == 0 && pair) {
+      hipLaunchKernelGGL(bottom_up_leaf_pair_kernel<TG>, dim3(bx_pair, total), dim3(kPassThreads), 0, s, a);
+    } else if (l == 0) {
+      hipLaunchKernelGGL(bottom_up_level_kernel<TG>, dim3(bx, total), dim3(kPassThreads), 0, s, a);
+    } else {
+      // above the lowest level every node has children: one wavefront per action
+      int wa = 1;
+      for (int k = 0; k < count; ++k)
+        if (l < a.t[k].n_levels) wa = std::max(wa, g->hp[p[k].player].level_max_act[l]);
+      // two hands per lane only where the level fills the chip several times
+      // over; a narrow level is latency-bound and gains from more lanes
+      if (pair && (size_t)bx * total >= 4 * (size_t)g->n_cu)
+        hipLaunchKernelGGL((bottom_up_internal_kernel<TG, 2>), dim3(bx_pair, total), dim3(kPassThreads, wa), 0, s, a);
+      else
+        hipLaunchKernelGGL((bottom_up_internal_kernel<TG, 1>), dim3(bx, total), dim3(kPassThreads, wa), 0, s, a);
+    }
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
@@ -910,6 +1227,16 @@ hipError_t launch_top_down(const egt_game* g, int player, const void* QB, void* 
   a.x_prev = x_prev;
   a.tau = tau;
   a.comb_out = comb_out;
+  const size_t pair_bytes = prec == kF32 ? 8 : 16;
+  auto aligned = [&](const void* ptr) { return ((uintptr_t)ptr % pair_bytes) == 0; };
+  if (g->ld % 2 == 0 && aligned(QB) && aligned(q_out) && aligned(x_prev) && aligned(comb_out)) {
+    const dim3 grid((unsigned)((g->ld / 2 + kPassThreads - 1) / kPassThreads), g->dp[player].n_seq);
+    if (prec == kF32)
+      hipLaunchKernelGGL(top_down_pair_kernel<float>, grid, dim3(kPassThreads), 0, s, a);
+    else
+      hipLaunchKernelGGL(top_down_pair_kernel<double>, grid, dim3(kPassThreads), 0, s, a);
+    return hipGetLastError();
+  }
   const dim3 grid((unsigned)((g->ld + kPassThreads - 1) / kPassThreads), g->dp[player].n_seq);
   if (prec == kF32)
     hipLaunchKernelGGL(top_down_kernel<float>, grid, dim3(kPassThreads), 0, s, a);
