@@ -43,11 +43,14 @@ def parse():
     ap.add_argument("--config", default="c1")
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--variant", default="AS")
-    ap.add_argument("--cpu-sample-iters", type=int, default=120)
+    ap.add_argument("--cpu-sample-iters", type=int, default=300)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--kernel-reps", type=int, default=200)
     ap.add_argument("--mixed-steps", type=int, default=5, help="precision-form solves of the same endgame")
-    ap.add_argument("--serve-requests", type=int, default=16, help="requests of the serving trace (0 = skip)")
+    ap.add_argument("--serve-requests", type=int, default=24, help="requests of the serving trace (0 = skip)")
+    ap.add_argument("--serve-rate", type=float, default=0.757,
+                    help="Poisson arrival rate (requests/s); 0.757 is 0.9 x the saturated precision-form "
+                         "throughput of the full 512-request trace")
     ap.add_argument("--serve-shapes", default="c0,c1,c2,c3")
     ap.add_argument("--serve-budget-gb", type=float, default=16.0)
     ap.add_argument("--copy-calibration-mb", type=float, default=0.0,
@@ -160,10 +163,11 @@ def precision_form(egt, torch, G, steps, fp64_ms, fp64_value, reps):
 
 
 def serving(egt, args):
-    """Poisson trace of solve requests (shapes drawn uniformly), continuously
-    batched in the precision form under an HBM budget: all at t = 0 (the
-    batched capacity R), then Poisson at 0.5 R and 0.9 R; at 0.9 R also
-    batched in FP64 and served one at a time in FP64 (the baseline)."""
+    """Trace of solve requests (shapes drawn uniformly), continuously batched
+    under an HBM budget: all at t = 0 in the precision form (the batched
+    capacity over this short trace), then Poisson arrivals at --serve-rate,
+    batched in the precision form, batched in FP64, and served one at a time
+    in FP64 (the baseline)."""
     from instances import make_instance
     from instances.endgames import serving_trace
     from paper_1810_03063_amd.serve import LibEngine, Request, serve, serve_sequential, summarize
@@ -182,12 +186,10 @@ def serving(egt, args):
         eng.close()
         return summarize(out, wall)
 
-    saturated = run(0.0)  # every request at t = 0: the batched throughput R
-    rate_lo, rate_hi = 0.5 * saturated["solves_per_sec"], 0.9 * saturated["solves_per_sec"]
-    loaded_lo = run(rate_lo)
-    loaded = run(rate_hi)
-    loaded64 = run(rate_hi, "fp64")
-    rate = rate_hi
+    saturated = run(0.0)  # every request at t = 0
+    rate = args.serve_rate
+    loaded = run(rate)
+    loaded64 = run(rate, "fp64")
     print("serving: batched runs done", file=sys.stderr, flush=True)
 
     def solve_one(r):
@@ -199,7 +201,6 @@ def serving(egt, args):
     seq_out, seq_wall = serve_sequential(solve_one, reqs_for(rate))
     baseline = summarize(seq_out, seq_wall)
     return dict(shapes=list(shapes), requests=n, budget_gb=args.serve_budget_gb, saturated=saturated,
-                poisson_rate_half_per_s=rate_lo, batched_half=loaded_lo,
                 poisson_rate_per_s=rate, batched=loaded, batched_fp64=loaded64, sequential_fp64=baseline,
                 throughput_vs_sequential=loaded["solves_per_sec"] / baseline["solves_per_sec"],
                 fp64_batched_vs_sequential=loaded64["solves_per_sec"] / baseline["solves_per_sec"])

@@ -34,6 +34,7 @@ constexpr int kTile = 32;     // output hands x showdown columns per block (one 
 constexpr int kKWaves = 16;   // waves per block, each contracting every 16th k-step of 16 hands
 constexpr int kBatch = 3;     // k-steps whose operands a wave loads before multiplying
 constexpr int kRedStride = kTile + 1;
+constexpr int kTiledMinColumns = 512;  // from this many showdown columns on, the tiled GEMM
 
 __device__ inline unsigned short bf16_rn(float f) {
   unsigned u = __float_as_uint(f);
@@ -141,6 +142,196 @@ __global__ __launch_bounds__(64 * kKWaves) void show_gemm_kernel(GemmArgs a) {
     const double c = a.col_coef[j] * a.scale;
     float* row = a.out + (size_t)a.col_own[j] * a.ld;
     row[h] += (float)(c * a.b_own[h] * (double)sum);
+  }
+}
+
+// Many showdown columns (large trees): a tiled GEMM with operand reuse.
+// Block = 128 output hands x 64 columns, four waves, wave w owning rows
+// 32 w .. 32 w + 31 of the tile as two 32 x 32 MFMA tiles.  K (the opponent's
+// hands) advances in steps of kTK = 64: the block stages W[128 x 64] and the
+// column reaches split into BF16 hi and lo ([64 columns x 64], k contiguous)
+// in LDS while the next step's global loads are in flight in registers; the
+// opponent's FP32 prior is staged in LDS once.  The hi and lo products
+// accumulate in separate tiles (independent MFMA chains), added in the
+// epilogue, which goes through LDS so that every output row is updated with
+// coalesced accesses.  A step past ld (ld is a multiple of 32) reads zeros.
+// Tiles are numbered column block major and dealt to the XCDs in contiguous
+// ranges, so the row blocks that share a column block's reaches meet in one
+// L2.
+constexpr int kTM = 128, kTN = 64, kTK = 64;
+constexpr int kTKS = kTK + 8;  // LDS row stride (BF16 elements) of the staged operands
+constexpr int kTCS = kTM + 1;  // LDS column stride (floats) of the output tile
+
+struct TiledStage {
+  unsigned short a[kTM * kTKS];   // W rows, k contiguous
+  unsigned short bh[kTN * kTKS];  // reach hi, per column, k contiguous
+  unsigned short bl[kTN * kTKS];  // reach lo
+};
+static_assert(sizeof(TiledStage) % 16 == 0, "the prior follows the stage 16-byte aligned");
+static_assert(kTCS * kTN * sizeof(float) <= sizeof(TiledStage), "the output tile fits the stage");
+
+size_t tiled_lds_bytes(int ld) { return sizeof(TiledStage) + sizeof(float) * (size_t)ld; }
+
+// Launch index -> tile, each XCD (launch indices go round-robin over the 8
+// XCDs) taking a contiguous range of tiles.
+__device__ inline int tile_of_launch(int b, int total) {
+  const int q = total / 8, r = total % 8;
+  const int x = b % 8, j = b / 8;
+  return x * q + min(x, r) + j;
+}
+
+__global__ __launch_bounds__(256) void show_gemm_tiled_kernel(GemmArgs a) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  TiledStage& st = *(TiledStage*)smem;
+  float* bopp = (float*)(smem + sizeof(TiledStage));  // [ld]
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int half = lane >> 5, l32 = lane & 31;
+  const int n_rb = (a.ld + kTM - 1) / kTM;
+  const int t = tile_of_launch((int)blockIdx.x, (int)gridDim.x);
+  const int m0 = (t % n_rb) * kTM, n0 = (t / n_rb) * kTN;
+  const int nst = (a.ld + kTK - 1) / kTK;
+
+  // per thread and step: 32 k of one W row, 16 k of one column's reach
+  const int arow = tid >> 1, ak = (tid & 1) * 32;
+  const bool arow_ok = m0 + arow < a.ld;
+  const unsigned short* wsrc = a.W + (size_t)(m0 + arow) * a.ld + ak;
+  const int bcol = tid >> 2, bk = (tid & 3) * 16;
+  const int jcol = n0 + bcol;
+  const bool bcol_ok = jcol < a.L;
+  const float* vsrc = nullptr;
+  if (bcol_ok) {
+    const int o = a.col_opp[jcol];
+    vsrc = o >= 0 ? a.v_opp + (size_t)o * a.ld : nullptr;
+  }
+  for (int i = tid; i < a.ld; i += 256) bopp[i] = a.b_opp32[i];
+  struct StepRegs {
+    uint4 a[4];
+    float4 v[4];
+  };
+  auto load_step = [&](StepRegs& q, int s) {
+    const int k0 = s * kTK;
+    // a 16-element chunk lies wholly inside or outside ld
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      q.a[u] = make_uint4(0u, 0u, 0u, 0u);
+      if (arow_ok && k0 + ak + 8 * u < a.ld) q.a[u] = *(const uint4*)(wsrc + k0 + 8 * u);
+    }
+    // a column past the last one, or a chunk past ld, has reach 0; the empty sequence has v = 1
+    const bool kin = k0 + bk < a.ld;
+    const float vfill = bcol_ok && kin ? 1.0f : 0.0f;
+#pragma unroll
+    for (int u = 0; u < 4; ++u) q.v[u] = make_float4(vfill, vfill, vfill, vfill);
+    if (vsrc && kin) {
+#pragma unroll
+      for (int u = 0; u < 4; ++u) q.v[u] = *(const float4*)(vsrc + k0 + bk + 4 * u);
+    }
+  };
+  auto store_step = [&](const StepRegs& q, int s) {
+#pragma unroll
+    for (int u = 0; u < 4; ++u) *(uint4*)&st.a[arow * kTKS + ak + 8 * u] = q.a[u];
+    const int k0 = s * kTK + bk;
+#pragma unroll
+    for (int hh = 0; hh < 2; ++hh) {
+      float r[8];
+#pragma unroll
+      for (int u = 0; u < 2; ++u) {
+        const float4 v = q.v[2 * hh + u];
+        const int kb = k0 + 8 * hh + 4 * u;
+        const float4 b = kb < a.ld ? *(const float4*)&bopp[kb] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        r[4 * u + 0] = b.x * v.x;
+        r[4 * u + 1] = b.y * v.y;
+        r[4 * u + 2] = b.z * v.z;
+        r[4 * u + 3] = b.w * v.w;
+      }
+      bf16x8 hi, lo;
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const unsigned short h16 = bf16_rn(r[e]);
+        hi[e] = (short)h16;
+        lo[e] = (short)bf16_rn(r[e] - bf16_to_f32(h16));
+      }
+      *(bf16x8*)&st.bh[bcol * kTKS + bk + 8 * hh] = hi;
+      *(bf16x8*)&st.bl[bcol * kTKS + bk + 8 * hh] = lo;
+    }
+  };
+
+  f32x16 acc_hi[2], acc_lo[2];
+#pragma unroll
+  for (int c = 0; c < 2; ++c)
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      acc_hi[c][r] = 0.0f;
+      acc_lo[c][r] = 0.0f;
+    }
+  const int arow_w = (wave * 32 + l32) * kTKS + 8 * half;  // this lane's A operand row
+  const int bcol_w = l32 * kTKS + 8 * half;                // this lane's B operand column (tile 0)
+  StepRegs q;
+  load_step(q, 0);
+  __syncthreads();  // the prior is staged
+  store_step(q, 0);
+  __syncthreads();
+  for (int s = 0; s < nst; ++s) {
+    if (s + 1 < nst) load_step(q, s + 1);  // in flight while this step multiplies
+#pragma unroll
+    for (int kk = 0; kk < kTK; kk += 16) {
+      const bf16x8 am = *(const bf16x8*)&st.a[arow_w + kk];
+#pragma unroll
+      for (int c = 0; c < 2; ++c) {
+        const bf16x8 bh = *(const bf16x8*)&st.bh[bcol_w + 32 * c * kTKS + kk];
+        const bf16x8 bl = *(const bf16x8*)&st.bl[bcol_w + 32 * c * kTKS + kk];
+        acc_hi[c] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(am, bh, acc_hi[c], 0, 0, 0);
+        acc_lo[c] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(am, bl, acc_lo[c], 0, 0, 0);
+      }
+    }
+    __syncthreads();  // every wave has read the stage
+    if (s + 1 < nst) {
+      store_step(q, s + 1);
+      __syncthreads();
+    }
+  }
+  // output tile through LDS as ct[column][row] (the stage is free now)
+  float* ct = (float*)smem;
+#pragma unroll
+  for (int c = 0; c < 2; ++c)
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const int row = wave * 32 + (r >> 2) * 8 + half * 4 + (r & 3);
+      const int col = 32 * c + l32;
+      ct[col * kTCS + row] = acc_hi[c][r] + acc_lo[c][r];
+    }
+  __syncthreads();
+  // Each thread updates one hand in kEpi columns per pass, with every load of
+  // a pass issued before its first store (a store could alias a later load,
+  // so the compiler would otherwise serialise the read-modify-writes).
+  constexpr int kEpi = 16;
+  constexpr int kColsPerRound = 256 / kTM;  // columns covered by one sweep of the threads
+  const int row = tid % kTM, h = m0 + row;
+  const bool hok = h < a.n;
+  const double bo = hok ? a.b_own[h] : 0.0;
+#pragma unroll 1
+  for (int pass = 0; pass < kTN / (kColsPerRound * kEpi); ++pass) {
+    int own[kEpi];
+    double cf[kEpi];
+#pragma unroll
+    for (int u = 0; u < kEpi; ++u) {
+      const int j = n0 + tid / kTM + kColsPerRound * (pass * kEpi + u);
+      own[u] = -1;
+      cf[u] = 0.0;
+      if (hok && j < a.L) {
+        own[u] = a.col_own[j];
+        cf[u] = a.col_coef[j];
+      }
+    }
+    float cur[kEpi];
+#pragma unroll
+    for (int u = 0; u < kEpi; ++u) cur[u] = own[u] >= 0 ? a.out[(size_t)own[u] * a.ld + h] : 0.0f;
+#pragma unroll
+    for (int u = 0; u < kEpi; ++u) {
+      if (own[u] < 0) continue;
+      const int col = tid / kTM + kColsPerRound * (pass * kEpi + u);
+      const double c = cf[u] * a.scale;
+      a.out[(size_t)own[u] * a.ld + h] = cur[u] + (float)(c * bo * (double)ct[col * kTCS + row]);
+    }
   }
 }
 
@@ -252,6 +443,12 @@ hipError_t launch_show_gemm(const egt_game* g, int player, const float* v_opp, f
   a.scale = (player == 0 ? 1.0 : -1.0) / g->Z;
   a.v_opp = v_opp;
   a.out = grad_out;
+  if (a.L >= kTiledMinColumns) {
+    // enough columns for operand reuse to pay: the tiled form
+    const unsigned tiles = (unsigned)(((a.L + kTN - 1) / kTN) * ((g->ld + kTM - 1) / kTM));
+    hipLaunchKernelGGL(show_gemm_tiled_kernel, dim3(tiles), dim3(256), tiled_lds_bytes(g->ld), s, a);
+    return hipGetLastError();
+  }
   const dim3 grid((unsigned)((a.L + kTile - 1) / kTile), (unsigned)(g->ld / kTile));
   hipLaunchKernelGGL(show_gemm_kernel, grid, dim3(64 * kKWaves), 0, s, a);
   return hipGetLastError();

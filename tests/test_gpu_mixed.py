@@ -75,6 +75,21 @@ def grad_bound(P, p, v_opp):
 def test_mixed_product_error(egt, cfg, seed):
     inst = make_instance(cfg, seed)
     print(f"[case] mixed product {cfg} seed={seed}", flush=True)
+    _check_mixed_product(egt, inst, seed)
+
+
+def test_mixed_product_error_ragged_k(egt):
+    """The c3 betting tree (thousands of showdown columns, so the tiled GEMM)
+    on a 32-card deck: 351 hands, rows padded to 352, so the last K step of
+    64 is half outside the rows."""
+    from instances.endgames import CONFIGS, river
+    kw = dict(CONFIGS["c3"], n_ranks=8)
+    inst = river("c3_32cards", 0, **kw)
+    print("[case] mixed product c3 betting, 32-card deck", flush=True)
+    _check_mixed_product(egt, inst, 0)
+
+
+def _check_mixed_product(egt, inst, seed):
     P = Problem(inst)
     G = egt.Game(inst)
     L = Layout(G, P)
