@@ -75,7 +75,7 @@ class EGT:
         return 1e-3 * gmax / bmax
 
     def init_point(self, mu_x, mu_y):
-        """Algorithm 1, lines 1-2: y0 = y_{mu_y}(x_omega), x0 = x_{mu_x}(y0)."""
+        """Algorithm 1's start-up: y0 = y_{mu_y}(x_omega), x0 = x_{mu_x}(y0)."""
         xw = self.P.uniform(0)
         y0 = self.P.sbr(1, self.G(1, xw), mu_y)[0]
         x0 = self.P.sbr(0, self.G(0, y0), mu_x)[0]

@@ -304,17 +304,17 @@ __global__ __launch_bounds__(256) void show_gemm_tiled_kernel(GemmArgs a) {
   // a pass issued before its first store (a store could alias a later load,
   // so the compiler would otherwise serialise the read-modify-writes).
   constexpr int kEpi = 16;
-  constexpr int kColsPerRound = 256 / kTM;  // columns covered by one sweep of the threads
+  constexpr int kColsPerSweep = 256 / kTM;  // columns covered by one sweep of the threads
   const int row = tid % kTM, h = m0 + row;
   const bool hok = h < a.n;
   const double bo = hok ? a.b_own[h] : 0.0;
 #pragma unroll 1
-  for (int pass = 0; pass < kTN / (kColsPerRound * kEpi); ++pass) {
+  for (int pass = 0; pass < kTN / (kColsPerSweep * kEpi); ++pass) {
     int own[kEpi];
     double cf[kEpi];
 #pragma unroll
     for (int u = 0; u < kEpi; ++u) {
-      const int j = n0 + tid / kTM + kColsPerRound * (pass * kEpi + u);
+      const int j = n0 + tid / kTM + kColsPerSweep * (pass * kEpi + u);
       own[u] = -1;
       cf[u] = 0.0;
       if (hok && j < a.L) {
@@ -328,7 +328,7 @@ __global__ __launch_bounds__(256) void show_gemm_tiled_kernel(GemmArgs a) {
 #pragma unroll
     for (int u = 0; u < kEpi; ++u) {
       if (own[u] < 0) continue;
-      const int col = tid / kTM + kColsPerRound * (pass * kEpi + u);
+      const int col = tid / kTM + kColsPerSweep * (pass * kEpi + u);
       const double c = cf[u] * a.scale;
       a.out[(size_t)own[u] * a.ld + h] = cur[u] + (float)(c * bo * (double)ct[col * kTCS + row]);
     }
