@@ -45,6 +45,7 @@ def parse():
     ap.add_argument("--variant", default="AS")
     ap.add_argument("--cpu-sample-iters", type=int, default=300)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-large-tree", action="store_true", help="skip the c3 (level path, tiled GEMM) section")
     ap.add_argument("--kernel-reps", type=int, default=200)
     ap.add_argument("--mixed-steps", type=int, default=5, help="precision-form solves of the same endgame")
     ap.add_argument("--serve-requests", type=int, default=24, help="requests of the serving trace (0 = skip)")
@@ -208,6 +209,35 @@ def serving(egt, args):
                 fp64_batched_vs_sequential=loaded64["solves_per_sec"] / baseline["solves_per_sec"])
 
 
+def large_tree(egt, torch, args):
+    """The 8-bet-size endgame (c3), whose tables exceed one block's LDS so
+    every pass runs level by level and whose 3958 showdown columns take the
+    tiled GEMM: one FP64 EGT/as solve and one precision-form solve after a
+    warm-up of each, and the rooflines of its smoothed best response and
+    product."""
+    from instances import make_instance
+
+    inst = make_instance("c3", args.seed)
+    G = egt.Game(inst)
+    egt.solve(G, variant=args.variant)  # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    res, _ = egt.solve(G, variant=args.variant)
+    fp64_s = time.perf_counter() - t0
+    if res["converged"] != 1:
+        raise RuntimeError(f"c3 solve did not converge: {res}")
+    reps = max(1, args.kernel_reps // 10)
+    out = dict(
+        workload=f"c3: 52-card river endgame, {G.n} hands/player, bets {list(inst.bet_fracs)} pot + all-in, "
+                 f"max {inst.max_raises} raises, {G.n_seq[0] * G.n} sequences/player",
+        fp64_ms=fp64_s * 1e3, fp64_iters=res["iters"], fp64_iters_per_sec=res["iters"] / fp64_s,
+        roofline=kernel_roofline(egt, torch, G, reps, "c3"),
+        roofline_gradient=gradient_roofline(egt, torch, G, reps),
+        precision_form=precision_form(egt, torch, G, 1, fp64_s * 1e3, res["value_p1"], reps))
+    G.close()
+    return out
+
+
 def cpu_baseline(inst, sample_iters, iters_per_solve, variant):
     import numpy as np  # noqa: F401
     from threadpoolctl import threadpool_info
@@ -314,6 +344,11 @@ def main():
         out["precision_form"] = precision_form(egt, torch, G, args.mixed_steps, out["ms_per_step"], res["value_p1"],
                                                args.kernel_reps)
         print(f"precision form: {out['precision_form']['ms_per_solve']:.1f} ms per solve", file=sys.stderr,
+              flush=True)
+    if not args.no_large_tree and args.config != "c3":
+        out["large_tree"] = large_tree(egt, torch, args)
+        print(f"large tree: {out['large_tree']['fp64_ms']:.0f} ms FP64, "
+              f"{out['large_tree']['precision_form']['ms_per_solve']:.0f} ms precision form", file=sys.stderr,
               flush=True)
     if args.serve_requests > 0:
         out["serving"] = serving(egt, args)

@@ -342,6 +342,29 @@ int build_game(const egt_game_desc* d, hipStream_t stream, egt_game** out) {
     for (int s = 0; s < hp.n_seq; ++s)
       for (int t = hp.term_begin[s]; t < hp.term_begin[s + 1]; ++t)
         hp.term_rec[(size_t)s * stride + (t - hp.term_begin[s])] = TermRec{hp.term_opp[t], hp.term_kind[t], hp.term_coef[t]};
+    // work items for blocks that loop over sequences: two-terminal sequences
+    // whole, one-terminal sequences in pairs, empty sequences alone
+    hp.term_items.clear();
+    if (hp.max_terms_per_seq <= 2) {
+      const TermRec none{-1, -1, 0.0};
+      int pending = -1;
+      for (int s = 0; s < hp.n_seq; ++s) {
+        const int cnt = hp.term_begin[s + 1] - hp.term_begin[s];
+        const TermRec* r = &hp.term_rec[(size_t)s * stride];
+        if (cnt == 2) {
+          hp.term_items.push_back(TermItem{{r[0], r[1]}, {s, s}, {0, 0}});
+        } else if (cnt == 0) {
+          hp.term_items.push_back(TermItem{{none, none}, {s, -1}, {0, 0}});
+        } else if (pending < 0) {
+          pending = s;
+        } else {
+          hp.term_items.push_back(TermItem{{hp.term_rec[(size_t)pending * stride], r[0]}, {pending, s}, {0, 0}});
+          pending = -1;
+        }
+      }
+      if (pending >= 0)
+        hp.term_items.push_back(TermItem{{hp.term_rec[(size_t)pending * stride], none}, {pending, -1}, {0, 0}});
+    }
   }
   // enough 4-hand blocks to spread over the chip; 16-hand blocks for tiny hand counts
   g->fused_hands = g->ld >= 512 ? 4 : 16;
@@ -432,7 +455,7 @@ int build_game(const egt_game_desc* d, hipStream_t stream, egt_game** out) {
     return off;
   };
   struct Offs {
-    size_t first, nact, beta, logn, spar, cbeg, child, tbeg, topp, tkind, tcoef, roots, belief, ftab, trec, anc;
+    size_t first, nact, beta, logn, spar, cbeg, child, tbeg, topp, tkind, tcoef, roots, belief, ftab, trec, anc, titems;
   } po[2];
   for (int p = 0; p < 2; ++p) {
     HostPlayer& hp = g->hp[p];
@@ -452,6 +475,7 @@ int build_game(const egt_game_desc* d, hipStream_t stream, egt_game** out) {
     po[p].ftab = add(hp.fused_tab.data(), hp.fused_tab.size());
     po[p].trec = add(hp.term_rec.data(), hp.term_rec.size() * sizeof(TermRec));
     po[p].anc = add(hp.anc.data(), hp.anc.size() * sizeof(int));
+    po[p].titems = add(hp.term_items.data(), hp.term_items.size() * sizeof(TermItem));
   }
   const size_t o_cbeg = add(card_begin.data(), card_begin.size() * sizeof(int));
   const size_t o_chands = add(card_hands.data(), card_hands.size() * sizeof(int));
@@ -508,6 +532,8 @@ int build_game(const egt_game_desc* d, hipStream_t stream, egt_game** out) {
     dp.term_rec = (const TermRec*)at(po[p].trec);
     dp.anc = (const int*)at(po[p].anc);
     dp.term_stride = std::max(1, hp.max_terms_per_seq);
+    dp.n_items = (int)hp.term_items.size();
+    dp.term_items = dp.n_items > 0 ? (const TermItem*)at(po[p].titems) : nullptr;
   }
   DHands& dh = g->dh;
   dh.n = n;

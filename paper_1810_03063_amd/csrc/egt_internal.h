@@ -70,6 +70,18 @@ struct TermRec {
   double coef;
 };
 
+// One work item of the product kernel when its blocks loop over many
+// sequences: one (sequence, terminal) pair per wave group; seq -1 = none.  A
+// sequence with two terminals is one item whose two results are added (the
+// same as its sequence-by-sequence evaluation); sequences with one terminal
+// are paired, two output rows per item; a sequence without terminals is an
+// item that writes its zero row.
+struct TermItem {
+  TermRec t[2];
+  int seq[2];
+  int pad[2];
+};
+
 struct DPlayer {
   int n_seq;
   int n_nodes;
@@ -91,6 +103,8 @@ struct DPlayer {
   const int* anc;              // [n_seq][kMaxDepth] sequences on the path root -> s (s last), -1 after
   const TermRec* term_rec;     // [n_seq][term_stride] terminals of each sequence, padded with kind -1
   int term_stride;             // max terminals per sequence (>= 1)
+  const TermItem* term_items;  // [n_items] when every sequence has at most two terminals, else null
+  int n_items;
   int fused_tab16;             // its size in 16-byte units
 };
 
@@ -188,6 +202,7 @@ struct HostPlayer {
   std::vector<int> roots;
   std::vector<unsigned char> fused_tab;  // table image of the single-launch pass
   std::vector<TermRec> term_rec;         // [n_seq][max(1, max_terms_per_seq)]
+  std::vector<TermItem> term_items;      // work items of the looping product kernel (at most two terminals each)
   std::vector<int> anc;                  // [n_seq][kMaxDepth]
   std::vector<std::string> seq_keys;
 };

@@ -64,7 +64,10 @@ __device__ inline double wave_inclusive_scan(double x, int lane) {
 //             counts as neither.
 // out[s][h] = b_own(h) / Z * sum_z coef(z) * op_z(h), the showdown op negated
 // for player 2 (its gradient sums over player 1's hands).  Group partial sums
-// are combined in a fixed order, so the result is bitwise repeatable.
+// are combined in a fixed order, so the result is bitwise repeatable.  When
+// the blocks loop over many sequences, they walk work items instead
+// (TermItem): a two-terminal sequence still takes both groups, but two
+// one-terminal sequences share a block, one per group, so no group idles.
 // ---------------------------------------------------------------------------
 template <class TV, class TO>
 struct GradArgs {
@@ -76,6 +79,8 @@ struct GradArgs {
   double show_sign;
   int groups;
   int fold_only;  // skip showdown terminals (their part is added by the BF16 GEMM)
+  const TermItem* items;  // work items instead of whole sequences (two groups, blocks looping), or null
+  int n_items;
 };
 
 // HPT = hands per thread (n <= 256 HPT).  MINW = the waves per SIMD the
@@ -109,7 +114,26 @@ __global__ __launch_bounds__(2 * kGroupThreads, MINW) void gradient_kernel(GradA
   // beliefs of this thread's chunk, the opponent's prior at the strided
   // positions this thread stages, and the card image (into LDS).  The tables
   // stay for every sequence the block then processes.
-  TermRec tr = grp < MT && (int)blockIdx.x < n_seq ? a.own.term_rec[(size_t)blockIdx.x * MT + grp] : none;
+  // A work unit w is sequence w (both groups add into its row when there are
+  // two groups), or work item w (each group its own (sequence, terminal)).
+  const bool by_items = a.items != nullptr;
+  const int n_work = by_items ? a.n_items : n_seq;
+  auto work_of = [&](int w, TermRec& t, int& so, bool& comb) {
+    if (by_items) {
+      const TermItem& it = a.items[w];
+      t = it.t[grp];
+      so = it.seq[grp];
+      comb = it.seq[0] == it.seq[1];
+    } else {
+      t = grp < MT ? a.own.term_rec[(size_t)w * MT + grp] : none;
+      so = w;
+      comb = groups == 2;
+    }
+  };
+  TermRec tr = none;
+  int s_out = -1;       // the row this group's result goes to
+  bool combine = false;  // group 1's result is added to group 0's (block-uniform)
+  if ((int)blockIdx.x < n_work) work_of((int)blockIdx.x, tr, s_out, combine);
   int4 HA[HPT], HB[HPT];
   int2 TG[HPT];
   double bown[HPT];
@@ -143,18 +167,20 @@ __global__ __launch_bounds__(2 * kGroupThreads, MINW) void gradient_kernel(GradA
     }
     for (int i = kCU * (int)blockDim.x + tid; i < C16; i += blockDim.x) dst[i] = img[i];
   }
-  const int rounds = (MT + groups - 1) / groups;
-  for (int s = blockIdx.x; s < n_seq; s += gridDim.x) {
-  const TermRec* recs = a.own.term_rec + (size_t)s * MT;
-  // the next sequence's first terminal, requested while this one runs
-  const int s_next = s + (int)gridDim.x;
-  const TermRec tr_next = grp < MT && s_next < n_seq ? a.own.term_rec[(size_t)s_next * MT + grp] : none;
+  const int rounds = by_items ? 1 : (MT + groups - 1) / groups;
+  for (int w = blockIdx.x; w < n_work; w += gridDim.x) {
+  // the next work unit's first terminal, requested while this one runs
+  const int w_next = w + (int)gridDim.x;
+  TermRec tr_next = none;
+  int s_next = -1;
+  bool comb_next = false;
+  if (w_next < n_work) work_of(w_next, tr_next, s_next, comb_next);
   double acc[HPT];
 #pragma unroll
   for (int k = 0; k < HPT; ++k) acc[k] = 0.0;
   for (int rd = 0; rd < rounds; ++rd) {
     const int j = rd * groups + grp;
-    if (rd > 0) tr = j < MT ? recs[j] : none;
+    if (rd > 0) tr = j < MT ? a.own.term_rec[(size_t)w * MT + j] : none;  // sequence units only
     // uniform within a group
     const bool active = tr.kind >= 0 && !(a.fold_only && tr.kind != 0);
     const int kind = tr.kind;
@@ -273,7 +299,7 @@ __global__ __launch_bounds__(2 * kGroupThreads, MINW) void gradient_kernel(GradA
     }
     __syncthreads();  // the next round rewrites R and Pc
   }
-  if (groups == 2) {
+  if (combine) {
     if (grp == 1) {
 #pragma unroll
       for (int k = 0; k < HPT; ++k)
@@ -287,15 +313,17 @@ __global__ __launch_bounds__(2 * kGroupThreads, MINW) void gradient_kernel(GradA
         if (k < cnt) acc[k] += R1[beg + k];
     }
   }
-  if (grp == 0) {
-    TO* row = a.out + (size_t)s * ld;
+  if ((!combine || grp == 0) && s_out >= 0) {
+    TO* row = a.out + (size_t)s_out * ld;
 #pragma unroll
     for (int k = 0; k < HPT; ++k)
       if (k < cnt) row[beg + k] = (TO)(acc[k] * (bown[k] * a.H.invZ));
     for (int i = n + gt; i < ld; i += kGroupThreads) row[i] = (TO)0;
   }
   tr = tr_next;
-  __syncthreads();  // the next sequence rewrites R of both groups
+  s_out = s_next;
+  combine = comb_next;
+  __syncthreads();  // the next unit rewrites R of both groups
   }
 }
 
@@ -1047,6 +1075,8 @@ static hipError_t gradient_launch(const egt_game* g, int player, const TV* v_opp
   a.out = grad_out;
   a.show_sign = player == 0 ? 1.0 : -1.0;
   a.fold_only = fold_only;
+  a.items = nullptr;
+  a.n_items = 0;
   const size_t per_group = (size_t)(g->n + 1 + g->dh.n_card_slots);  // doubles
   const size_t card_bytes = 16 * (size_t)g->dh.card_img16;
   auto lds_bytes = [&](int gr) { return sizeof(double) * ((gr * per_group + 1) / 2 * 2) + card_bytes; };
@@ -1055,10 +1085,15 @@ static hipError_t gradient_launch(const egt_game* g, int player, const TV* v_opp
   a.groups = groups;
   const size_t lds = lds_bytes(groups);
   // one block per sequence up to two blocks per compute unit; beyond that each
-  // block loops over sequences (the tables are staged once per block)
-  const int blocks = std::min(g->dp[player].n_seq, 2 * g->n_cu);
-  const dim3 grid(blocks), block(kGroupThreads * groups);
+  // block loops over sequences (the tables are staged once per block), then
+  // over work items that keep both groups busy
   const bool looping = g->dp[player].n_seq > g->n_cu;  // blocks of the second round would wait for a CU
+  if (looping && groups == 2 && g->dp[player].term_items) {
+    a.items = g->dp[player].term_items;
+    a.n_items = g->dp[player].n_items;
+  }
+  const int blocks = std::min(a.items ? a.n_items : g->dp[player].n_seq, 2 * g->n_cu);
+  const dim3 grid(blocks), block(kGroupThreads * groups);
   if (g->n <= 2 * kGroupThreads)
     hipLaunchKernelGGL((gradient_kernel<TV, TO, 2, 1>), grid, block, lds, s, a);
   else if (g->n <= 5 * kGroupThreads && looping)

@@ -141,6 +141,41 @@ def test_best_response_uniform_and_gap_parity(egt, cfg, seed):
     assert gap >= -1e-12 * (abs(brmax_o) + abs(brmin_o))
 
 
+def _offset_rows(t):
+    """The same values in a buffer one double past a 16-byte boundary (the
+    ABI's 8-byte alignment, below the two-hands-per-lane kernels' 16)."""
+    buf = torch.zeros(t.numel() + 1, dtype=t.dtype, device=t.device)
+    view = buf[1:].view(t.shape)
+    view.copy_(t)
+    assert view.data_ptr() % 16 == 8
+    return view
+
+
+@pytest.mark.parametrize("p", [0, 1])
+def test_level_path_unaligned_rows_bitwise(egt, p):
+    """c3 runs level by level.  With 16-byte aligned rows the lowest level,
+    the wide levels and the top-down pass take two hands per lane; with rows
+    only 8-byte aligned they fall back to one hand per lane.  Both forms
+    evaluate the same arithmetic per hand, so strategy and value agree bit
+    for bit."""
+    inst, P, G, L = setup(egt, "c3", 0)
+    rng = np.random.default_rng(300 + p)
+    g = dev(L.to_lib(p, rng.standard_normal((P.n_seq[p], P.n)) * 10.0))
+    for mu in (3.0, 0.05):
+        print(f"[case] unaligned sbr c3 player={p} mu={mu}", flush=True)
+        q_a, v_a = egt.smoothed_br(G, p, g, mu)
+        q_u = _offset_rows(torch.zeros_like(q_a))
+        q_u, v_u = egt.smoothed_br(G, p, _offset_rows(g), mu, strat_out=q_u)
+        torch.cuda.synchronize()
+        assert torch.equal(q_a, q_u)
+        assert torch.equal(v_a, v_u)
+    print(f"[case] unaligned br c3 player={p}", flush=True)
+    b_a = egt.best_response(G, p, g)
+    b_u = egt.best_response(G, p, _offset_rows(g))
+    torch.cuda.synchronize()
+    assert torch.equal(b_a, b_u)
+
+
 def _edge_instances():
     base = make_instance("c0", 7)
     n = base.n_hands
