@@ -8,8 +8,11 @@
 //    partial sums, then the top-down rebuild q_i = q_{p_j} q_bar_i with the
 //    convex-combination epilogue of Algorithm 2 (x_hat, y_+, x_+);
 //    mu = 0 gives the best response;
-//  * bottom_up_level_kernel / top_down_kernel / root_sums_kernel : the same
-//    steps one level per launch for large trees;
+//  * the same steps one level per launch for large trees:
+//    bottom_up_leaf_pair_kernel (lowest level) or bottom_up_level_kernel
+//    (its one-hand-per-lane form), bottom_up_internal_kernel (levels with
+//    children, one wavefront per action), root_sums_kernel, and
+//    top_down_pair_kernel or top_down_kernel;
 //  * small helpers (uniform point, a*x + b*y, max |x|).
 //
 // Every vector is double[rows][ld], hands (slots) fastest, so consecutive
@@ -758,7 +761,8 @@ __global__ __launch_bounds__(kPassThreads) void bottom_up_leaf_pair_kernel(PassS
 // Levels above the lowest (every node has child nodes): the same evaluation
 // with the actions in parallel.  Block = (node, 64 x HP hands) x `blockDim.y`
 // wavefronts (the level's most actions); wavefront j takes action j for HP
-// adjacent hands per lane (HP = 2 when every row is 2-element aligned): its
+// adjacent hands per lane (HP = 2 on wide levels when every row is 2-element
+// aligned): its
 // gradients and its children, whose value slots [cbeg[s], cbeg[s + 1]) are
 // read in batches of kChildBatch so that one round trip covers them all and
 // added in slot order.  The node's g~ and weights meet in LDS; the minimum,
