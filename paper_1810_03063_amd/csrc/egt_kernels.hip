@@ -894,13 +894,30 @@ __global__ __launch_bounds__(kPassThreads * kMaxActions) void bottom_up_internal
 // Root sums of the level path: block k sums tree k, roots in order (value
 // slots C + r), hands strided over the threads, then a fixed-order reduction.
 __global__ __launch_bounds__(256) void root_sums_kernel(PassSet a, double* out) {
+  constexpr int kRootBatch = 4;                     // roots whose values are requested together
+  constexpr int kHandSteps = 8;                     // hands per thread and root (n <= 2048 = 256 x 8)
   __shared__ double part[4];
   const TreePass& t = a.t[blockIdx.x];
   double s = 0.0;
   const int C = t.P.n_nodes - t.P.n_roots;  // the r-th root's value slot is C + r
-  for (int r = 0; r < t.P.n_roots; ++r) {
-    const double* row = t.V + (size_t)(C + r) * a.ld;
-    for (int h = threadIdx.x; h < a.n; h += 256) s += row[h];
+  // each thread adds its hands h = tid + 256 m root by root, m ascending; the
+  // loads of kRootBatch roots are issued before the first add
+  for (int r0 = 0; r0 < t.P.n_roots; r0 += kRootBatch) {
+    double v[kRootBatch][kHandSteps];
+#pragma unroll
+    for (int u = 0; u < kRootBatch; ++u) {
+      const double* row = t.V + (size_t)(C + r0 + u) * a.ld;
+#pragma unroll
+      for (int m = 0; m < kHandSteps; ++m) {
+        const int h = (int)threadIdx.x + 256 * m;
+        v[u][m] = (r0 + u < t.P.n_roots && h < a.n) ? row[h] : 0.0;
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < kRootBatch; ++u)
+#pragma unroll
+      for (int m = 0; m < kHandSteps; ++m)
+        if (r0 + u < t.P.n_roots && (int)threadIdx.x + 256 * m < a.n) s += v[u][m];
   }
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
