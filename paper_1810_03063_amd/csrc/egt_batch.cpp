@@ -30,7 +30,7 @@ namespace egt {
 int state_create_in(const egt_game* g, const egt_solve_opts* o, hipStream_t s, void* dev_mem, double* host_mem,
                     egt_state** out);
 int state_destroy(egt_state* st);
-int solve_loop(egt_state* st, hipStream_t s, const volatile bool* stop, bool* converged);
+int solve_loop(egt_state* st, hipStream_t s, const std::atomic<bool>* stop, bool* converged);
 int fill_result(egt_state* st, bool converged, double seconds, egt_result* res, hipStream_t s);
 int64_t state_bytes(const egt_game* g, bool mixed);
 size_t state_host_doubles();
@@ -69,7 +69,7 @@ struct egt_batch {
   std::vector<std::thread> workers;
   std::mutex mu;
   std::condition_variable work_cv, done_cv;
-  volatile bool stop = false;
+  std::atomic<bool> stop{false};  // set by destroy, read by the workers' solve loops
   int64_t finished_total = 0, finished_seen = 0;
   int device = 0;
 };

@@ -27,6 +27,7 @@
 // run on the BF16 matrix cores, node values and normalisers stay FP64, and the
 // saddle gap is always measured with FP64 products of the (widened) iterates.
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <cmath>
 #include <cstring>
@@ -739,7 +740,7 @@ int fill_result(egt_state* st, bool converged, double seconds, egt_result* res, 
 // x and A y must survive a converged stop).  Every committed attempt is
 // computed exactly as by state_step, so the results are bitwise those of
 // stepping with a gap test before every gap_every-th iteration.
-int solve_loop_pipelined(egt_state* st, hipStream_t s, const volatile bool* stop, bool* converged) {
+int solve_loop_pipelined(egt_state* st, hipStream_t s, const std::atomic<bool>* stop, bool* converged) {
   const egt_solve_opts& op = st->opts;
   const bool mixed = st->prec == kF32;
   auto gap_due = [&](int64_t t) { return t % op.gap_every == 0 || t >= op.max_iters; };
@@ -752,7 +753,7 @@ int solve_loop_pipelined(egt_state* st, hipStream_t s, const volatile bool* stop
       return EGT_OK;
     }
   }
-  if (st->t >= op.max_iters || (stop && *stop)) {
+  if (st->t >= op.max_iters || (stop && stop->load(std::memory_order_relaxed))) {
     if (!st->gap_valid) rc = state_gap(st, nullptr, nullptr, nullptr, s);
     return rc;
   }
@@ -767,7 +768,7 @@ int solve_loop_pipelined(egt_state* st, hipStream_t s, const volatile bool* stop
     bool spec = false;
     int p2 = 0, t2 = 0;
     double tau2 = 0.0;
-    if (st->t + 1 < op.max_iters && !(stop && *stop) && !(mixed && gap_due(st->t + 2))) {
+    if (st->t + 1 < op.max_iters && !(stop && stop->load(std::memory_order_relaxed)) && !(mixed && gap_due(st->t + 2))) {
       double mu2[2] = {st->mu[0], st->mu[1]};
       mu2[p] *= (1.0 - tau);
       side_and_tau(st, st->t + 1, mu2, op.variant == EGT_VARIANT_AS ? tau : st->tau, &p2, &tau2);
@@ -809,7 +810,7 @@ int solve_loop_pipelined(egt_state* st, hipStream_t s, const volatile bool* stop
       *converged = true;
       return EGT_OK;
     }
-    if (st->t >= op.max_iters || (stop && *stop)) {
+    if (st->t >= op.max_iters || (stop && stop->load(std::memory_order_relaxed))) {
       if (!st->gap_valid) rc = state_gap(st, nullptr, nullptr, nullptr, s);
       return rc;
     }
@@ -830,7 +831,7 @@ int solve_loop_pipelined(egt_state* st, hipStream_t s, const volatile bool* stop
 
 // The iteration of egt_solve: gap test before every gap_every-th iteration,
 // stop at gap <= eps or max_iters (or when *stop becomes true).
-int solve_loop(egt_state* st, hipStream_t s, const volatile bool* stop, bool* converged) {
+int solve_loop(egt_state* st, hipStream_t s, const std::atomic<bool>* stop, bool* converged) {
   if (st->step_open) return fail(EGT_EINVAL, "a split step is in progress");
   return solve_loop_pipelined(st, s, stop, converged);
 }
