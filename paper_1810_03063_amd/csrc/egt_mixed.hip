@@ -148,17 +148,17 @@ __global__ __launch_bounds__(64 * kKWaves) void show_gemm_kernel(GemmArgs a) {
 // Many showdown columns (large trees): a tiled GEMM with operand reuse.
 // Block = 128 output hands x 64 columns, four waves, wave w owning rows
 // 32 w .. 32 w + 31 of the tile as two 32 x 32 MFMA tiles.  K (the opponent's
-// hands) advances in steps of kTK = 64: the block stages W[128 x 64] and the
-// column reaches split into BF16 hi and lo ([64 columns x 64], k contiguous)
-// in LDS while the next step's global loads are in flight in registers; the
-// opponent's FP32 prior is staged in LDS once.  The hi and lo products
-// accumulate in separate tiles (independent MFMA chains), added in the
-// epilogue, which goes through LDS so that every output row is updated with
-// coalesced accesses.  A step past ld (ld is a multiple of 32) reads zeros.
-// Tiles are numbered column block major and dealt to the XCDs in contiguous
-// ranges, so the row blocks that share a column block's reaches meet in one
-// L2.
-constexpr int kTM = 128, kTN = 64, kTK = 64;
+// hands) advances in steps of kTK = 32 (ld is a multiple of 32): the block
+// stages W[128 x 32] and the column reaches split into BF16 hi and lo
+// ([64 columns x 32], k contiguous) in two LDS buffers, and the global loads
+// run two steps ahead in registers, so each load has two steps of work to
+// land behind.  The opponent's FP32 prior is staged in LDS once.  The hi and
+// lo products accumulate in separate tiles (independent MFMA chains), added
+// in the epilogue, which goes through LDS so that every output row is updated
+// with coalesced accesses.  Tiles are numbered column block major and dealt to
+// the XCDs in contiguous ranges, so the row blocks that share a column block's
+// reaches meet in one L2.
+constexpr int kTM = 128, kTN = 64, kTK = 32;
 constexpr int kTKS = kTK + 8;  // LDS row stride (BF16 elements) of the staged operands
 constexpr int kTCS = kTM + 1;  // LDS column stride (floats) of the output tile
 
@@ -167,10 +167,10 @@ struct TiledStage {
   unsigned short bh[kTN * kTKS];  // reach hi, per column, k contiguous
   unsigned short bl[kTN * kTKS];  // reach lo
 };
-static_assert(sizeof(TiledStage) % 16 == 0, "the prior follows the stage 16-byte aligned");
-static_assert(kTCS * kTN * sizeof(float) <= sizeof(TiledStage), "the output tile fits the stage");
+static_assert(sizeof(TiledStage) % 16 == 0, "the stages and the prior stay 16-byte aligned");
+static_assert(kTCS * kTN * sizeof(float) <= 2 * sizeof(TiledStage), "the output tile fits the stages");
 
-size_t tiled_lds_bytes(int ld) { return sizeof(TiledStage) + sizeof(float) * (size_t)ld; }
+size_t tiled_lds_bytes(int ld) { return 2 * sizeof(TiledStage) + sizeof(float) * (size_t)ld; }
 
 // Launch index -> tile, each XCD (launch indices go round-robin over the 8
 // XCDs) taking a contiguous range of tiles.
@@ -182,20 +182,20 @@ __device__ inline int tile_of_launch(int b, int total) {
 
 __global__ __launch_bounds__(256) void show_gemm_tiled_kernel(GemmArgs a) {
   extern __shared__ __align__(16) unsigned char smem[];
-  TiledStage& st = *(TiledStage*)smem;
-  float* bopp = (float*)(smem + sizeof(TiledStage));  // [ld]
+  TiledStage* st = (TiledStage*)smem;                     // [2]
+  float* bopp = (float*)(smem + 2 * sizeof(TiledStage));  // [ld]
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int half = lane >> 5, l32 = lane & 31;
   const int n_rb = (a.ld + kTM - 1) / kTM;
   const int t = tile_of_launch((int)blockIdx.x, (int)gridDim.x);
   const int m0 = (t % n_rb) * kTM, n0 = (t / n_rb) * kTN;
-  const int nst = (a.ld + kTK - 1) / kTK;
+  const int nst = a.ld / kTK;
 
-  // per thread and step: 32 k of one W row, 16 k of one column's reach
-  const int arow = tid >> 1, ak = (tid & 1) * 32;
+  // per thread and step: 16 k of one W row, 8 k of one column's reach
+  const int arow = tid >> 1, ak = (tid & 1) * 16;
   const bool arow_ok = m0 + arow < a.ld;
   const unsigned short* wsrc = a.W + (size_t)(m0 + arow) * a.ld + ak;
-  const int bcol = tid >> 2, bk = (tid & 3) * 16;
+  const int bcol = tid >> 2, bk = (tid & 3) * 8;
   const int jcol = n0 + bcol;
   const bool bcol_ok = jcol < a.L;
   const float* vsrc = nullptr;
@@ -205,54 +205,40 @@ __global__ __launch_bounds__(256) void show_gemm_tiled_kernel(GemmArgs a) {
   }
   for (int i = tid; i < a.ld; i += 256) bopp[i] = a.b_opp32[i];
   struct StepRegs {
-    uint4 a[4];
-    float4 v[4];
+    uint4 a0, a1;
+    float4 v0, v1;
   };
   auto load_step = [&](StepRegs& q, int s) {
     const int k0 = s * kTK;
-    // a 16-element chunk lies wholly inside or outside ld
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      q.a[u] = make_uint4(0u, 0u, 0u, 0u);
-      if (arow_ok && k0 + ak + 8 * u < a.ld) q.a[u] = *(const uint4*)(wsrc + k0 + 8 * u);
+    q.a0 = q.a1 = make_uint4(0u, 0u, 0u, 0u);
+    if (arow_ok) {
+      q.a0 = *(const uint4*)(wsrc + k0);
+      q.a1 = *(const uint4*)(wsrc + k0 + 8);
     }
-    // a column past the last one, or a chunk past ld, has reach 0; the empty sequence has v = 1
-    const bool kin = k0 + bk < a.ld;
-    const float vfill = bcol_ok && kin ? 1.0f : 0.0f;
-#pragma unroll
-    for (int u = 0; u < 4; ++u) q.v[u] = make_float4(vfill, vfill, vfill, vfill);
-    if (vsrc && kin) {
-#pragma unroll
-      for (int u = 0; u < 4; ++u) q.v[u] = *(const float4*)(vsrc + k0 + bk + 4 * u);
+    // a column past the last one has reach 0; the empty sequence has v = 1
+    const float vfill = bcol_ok ? 1.0f : 0.0f;
+    q.v0 = q.v1 = make_float4(vfill, vfill, vfill, vfill);
+    if (vsrc) {
+      q.v0 = *(const float4*)(vsrc + k0 + bk);
+      q.v1 = *(const float4*)(vsrc + k0 + bk + 4);
     }
   };
-  auto store_step = [&](const StepRegs& q, int s) {
+  auto store_step = [&](const StepRegs& q, int s, TiledStage& d) {
+    *(uint4*)&d.a[arow * kTKS + ak] = q.a0;
+    *(uint4*)&d.a[arow * kTKS + ak + 8] = q.a1;
+    const int kb = s * kTK + bk;
+    const float4 b0 = *(const float4*)&bopp[kb], b1 = *(const float4*)&bopp[kb + 4];
+    const float r[8] = {b0.x * q.v0.x, b0.y * q.v0.y, b0.z * q.v0.z, b0.w * q.v0.w,
+                        b1.x * q.v1.x, b1.y * q.v1.y, b1.z * q.v1.z, b1.w * q.v1.w};
+    bf16x8 hi, lo;
 #pragma unroll
-    for (int u = 0; u < 4; ++u) *(uint4*)&st.a[arow * kTKS + ak + 8 * u] = q.a[u];
-    const int k0 = s * kTK + bk;
-#pragma unroll
-    for (int hh = 0; hh < 2; ++hh) {
-      float r[8];
-#pragma unroll
-      for (int u = 0; u < 2; ++u) {
-        const float4 v = q.v[2 * hh + u];
-        const int kb = k0 + 8 * hh + 4 * u;
-        const float4 b = kb < a.ld ? *(const float4*)&bopp[kb] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-        r[4 * u + 0] = b.x * v.x;
-        r[4 * u + 1] = b.y * v.y;
-        r[4 * u + 2] = b.z * v.z;
-        r[4 * u + 3] = b.w * v.w;
-      }
-      bf16x8 hi, lo;
-#pragma unroll
-      for (int e = 0; e < 8; ++e) {
-        const unsigned short h16 = bf16_rn(r[e]);
-        hi[e] = (short)h16;
-        lo[e] = (short)bf16_rn(r[e] - bf16_to_f32(h16));
-      }
-      *(bf16x8*)&st.bh[bcol * kTKS + bk + 8 * hh] = hi;
-      *(bf16x8*)&st.bl[bcol * kTKS + bk + 8 * hh] = lo;
+    for (int e = 0; e < 8; ++e) {
+      const unsigned short h16 = bf16_rn(r[e]);
+      hi[e] = (short)h16;
+      lo[e] = (short)bf16_rn(r[e] - bf16_to_f32(h16));
     }
+    *(bf16x8*)&d.bh[bcol * kTKS + bk] = hi;
+    *(bf16x8*)&d.bl[bcol * kTKS + bk] = lo;
   };
 
   f32x16 acc_hi[2], acc_lo[2];
@@ -265,29 +251,43 @@ __global__ __launch_bounds__(256) void show_gemm_tiled_kernel(GemmArgs a) {
     }
   const int arow_w = (wave * 32 + l32) * kTKS + 8 * half;  // this lane's A operand row
   const int bcol_w = l32 * kTKS + 8 * half;                // this lane's B operand column (tile 0)
-  StepRegs q;
-  load_step(q, 0);
-  __syncthreads();  // the prior is staged
-  store_step(q, 0);
-  __syncthreads();
-  for (int s = 0; s < nst; ++s) {
-    if (s + 1 < nst) load_step(q, s + 1);  // in flight while this step multiplies
+  auto multiply = [&](const TiledStage& c) {
 #pragma unroll
     for (int kk = 0; kk < kTK; kk += 16) {
-      const bf16x8 am = *(const bf16x8*)&st.a[arow_w + kk];
+      const bf16x8 am = *(const bf16x8*)&c.a[arow_w + kk];
 #pragma unroll
-      for (int c = 0; c < 2; ++c) {
-        const bf16x8 bh = *(const bf16x8*)&st.bh[bcol_w + 32 * c * kTKS + kk];
-        const bf16x8 bl = *(const bf16x8*)&st.bl[bcol_w + 32 * c * kTKS + kk];
-        acc_hi[c] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(am, bh, acc_hi[c], 0, 0, 0);
-        acc_lo[c] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(am, bl, acc_lo[c], 0, 0, 0);
+      for (int ct = 0; ct < 2; ++ct) {
+        const bf16x8 bh = *(const bf16x8*)&c.bh[bcol_w + 32 * ct * kTKS + kk];
+        const bf16x8 bl = *(const bf16x8*)&c.bl[bcol_w + 32 * ct * kTKS + kk];
+        acc_hi[ct] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(am, bh, acc_hi[ct], 0, 0, 0);
+        acc_lo[ct] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(am, bl, acc_lo[ct], 0, 0, 0);
       }
     }
-    __syncthreads();  // every wave has read the stage
-    if (s + 1 < nst) {
-      store_step(q, s + 1);
-      __syncthreads();
-    }
+  };
+  // Step s is multiplied from st[s & 1] while step s + 1 waits in registers
+  // for the other buffer and step s + 2 is being loaded.
+  StepRegs q0, q1;
+  load_step(q0, 0);
+  __syncthreads();  // the prior is staged
+  store_step(q0, 0, st[0]);
+  if (nst > 1) load_step(q0, 1);
+  __syncthreads();
+  int s = 0;
+  for (; s + 1 < nst; s += 2) {
+    // st[0] holds step s, q0 step s + 1
+    if (s + 2 < nst) load_step(q1, s + 2);
+    multiply(st[0]);
+    store_step(q0, s + 1, st[1]);
+    __syncthreads();
+    // st[1] holds step s + 1, q1 step s + 2
+    if (s + 3 < nst) load_step(q0, s + 3);
+    multiply(st[1]);
+    if (s + 2 < nst) store_step(q1, s + 2, st[0]);
+    __syncthreads();
+  }
+  if (s < nst) {  // an odd number of steps ends in st[0]
+    multiply(st[0]);
+    __syncthreads();  // the output tile below overwrites the stages
   }
   // output tile through LDS as ct[column][row] (the stage is free now)
   float* ct = (float*)smem;
