@@ -80,8 +80,9 @@ def test_mixed_product_error(egt, cfg, seed):
 
 def test_mixed_product_error_ragged_k(egt):
     """The c3 betting tree (thousands of showdown columns, so the tiled GEMM)
-    on a 32-card deck: 351 hands, rows padded to 352, so the last K step of
-    64 is half outside the rows."""
+    on a 32-card deck: 351 hands, rows padded to 352, so the last 128-row
+    tile is partly outside the rows and K takes an odd number (11) of steps
+    of 32."""
     from instances.endgames import CONFIGS, river
     kw = dict(CONFIGS["c3"], n_ranks=8)
     inst = river("c3_32cards", 0, **kw)
