@@ -33,6 +33,7 @@ namespace {
 constexpr int kGroupThreads = 256;     // one wave group evaluates one terminal
 constexpr int kMaxHandsPerThread = 8;  // n <= 2048 = 256 threads x 8 contiguous hands
 constexpr int kPassThreads = 64;       // per-level pass: one wavefront per (node, 64 hands)
+constexpr int kInternalWaves = 8;       // level path: wavefronts per node block (4 blocks fill a CU's 32 wave slots)
 constexpr int kFusedSlots = 64;        // fused pass: node slots per block (x HB hands per slot)
 
 // Explicit fused multiply-adds for the expressions that the level-path kernel
@@ -760,7 +761,8 @@ __global__ __launch_bounds__(kPassThreads) void bottom_up_leaf_pair_kernel(PassS
 
 // Levels above the lowest (every node has child nodes): the same evaluation
 // with the actions in parallel.  Block = (node, 64 x HP hands) x `blockDim.y`
-// wavefronts (the level's most actions); wavefront j takes action j for HP
+// wavefronts (the level's most actions, at most kInternalWaves); wavefront j
+// takes actions j, j + blockDim.y, ... for HP
 // adjacent hands per lane (HP = 2 on wide levels when every row is 2-element
 // aligned): its
 // gradients and its children, whose value slots [cbeg[s], cbeg[s + 1]) are
@@ -794,7 +796,8 @@ __global__ __launch_bounds__(kPassThreads * kMaxActions) void bottom_up_internal
   const int* cbeg = (const int*)(tab + L.cbeg);
   const int s0 = r.x, na = r.y;
   const bool live = h < a.n;
-  const bool act = live && j < na;
+  const bool act = live && j < na;  // this wavefront owns actions j, j + blockDim.y, ...
+  const int nw = (int)blockDim.y;
   auto load2 = [&](const TG* p, double& x0, double& x1) {
     if constexpr (HP == 2) {
       const V2 q = *(const V2*)p;
@@ -811,8 +814,8 @@ __global__ __launch_bounds__(kPassThreads * kMaxActions) void bottom_up_internal
     else
       p[0] = (std::remove_pointer_t<decltype(p)>)x0;
   };
-  if (act) {
-    const size_t idx = (size_t)(s0 + j) * ld + h;
+  for (int jj = j; live && jj < na; jj += nw) {
+    const size_t idx = (size_t)(s0 + jj) * ld + h;
     double x0, x1, b0, b1;
     load2((const TG*)t.gA + idx, x0, x1);
     x0 = t.cA * x0;
@@ -823,7 +826,7 @@ __global__ __launch_bounds__(kPassThreads * kMaxActions) void bottom_up_internal
       x1 = fmadd(t.cB, b1, x1);
     }
     if (t.g_out) store2((TG*)t.g_out + idx, x0 * t.g_scale, x1 * t.g_scale);
-    const int c0 = cbeg[s0 + j], c1 = cbeg[s0 + j + 1];
+    const int c0 = cbeg[s0 + jj], c1 = cbeg[s0 + jj + 1];
     for (int c = c0; c < c1; c += kChildBatch) {
       double cv0[kChildBatch], cv1[kChildBatch];
 #pragma unroll
@@ -848,8 +851,8 @@ __global__ __launch_bounds__(kPassThreads * kMaxActions) void bottom_up_internal
           x1 += cv1[u];
         }
     }
-    gl[j][lane] = x0;
-    if constexpr (HP == 2) gl[j][kPassThreads + lane] = x1;
+    gl[jj][lane] = x0;
+    if constexpr (HP == 2) gl[jj][kPassThreads + lane] = x1;
   }
   __syncthreads();
   double m0 = INFINITY, m1 = INFINITY;
@@ -865,17 +868,17 @@ __global__ __launch_bounds__(kPassThreads * kMaxActions) void bottom_up_internal
   }
   const double temp = t.mu * p0.x;
   const double inv_temp = (1.0 / t.mu) * p0.y;
-  double w0 = 0.0, w1 = 0.0;
-  if (act) {
+  for (int jj = j; live && jj < na; jj += nw) {
+    double w0, w1 = 0.0;
     if constexpr (std::is_same<TG, float>::value) {
-      w0 = (double)expf((float)((m0 - gl[j][lane]) * inv_temp));
-      if constexpr (HP == 2) w1 = (double)expf((float)((m1 - gl[j][kPassThreads + lane]) * inv_temp));
+      w0 = (double)expf((float)((m0 - gl[jj][lane]) * inv_temp));
+      if constexpr (HP == 2) w1 = (double)expf((float)((m1 - gl[jj][kPassThreads + lane]) * inv_temp));
     } else {
-      w0 = exp((m0 - gl[j][lane]) * inv_temp);
-      if constexpr (HP == 2) w1 = exp((m1 - gl[j][kPassThreads + lane]) * inv_temp);
+      w0 = exp((m0 - gl[jj][lane]) * inv_temp);
+      if constexpr (HP == 2) w1 = exp((m1 - gl[jj][kPassThreads + lane]) * inv_temp);
     }
-    wl[j][lane] = w0;
-    if constexpr (HP == 2) wl[j][kPassThreads + lane] = w1;
+    wl[jj][lane] = w0;
+    if constexpr (HP == 2) wl[jj][kPassThreads + lane] = w1;
   }
   __syncthreads();
   if (act) {
@@ -887,7 +890,10 @@ __global__ __launch_bounds__(kPassThreads * kMaxActions) void bottom_up_internal
     if (j == 0)
       store2(Vrow, fmadd(temp, p1.x, fmadd(-temp, log(sum0), m0)),
              HP == 2 ? fmadd(temp, p1.x, fmadd(-temp, log(sum1), m1)) : 0.0);
-    if (t.QB) store2((TG*)t.QB + (size_t)(s0 + j) * ld + h, w0 * (1.0 / sum0), HP == 2 ? w1 * (1.0 / sum1) : 0.0);
+    if (t.QB)
+      for (int jj = j; jj < na; jj += nw)
+        store2((TG*)t.QB + (size_t)(s0 + jj) * ld + h, wl[jj][lane] * (1.0 / sum0),
+               HP == 2 ? wl[jj][kPassThreads + lane] * (1.0 / sum1) : 0.0);
   }
 }
 
@@ -1236,6 +1242,7 @@ static hipError_t passes_launch(const egt_game* g, const Pass* p, int count, con
       int wa = 1;
       for (int k = 0; k < count; ++k)
         if (l < a.t[k].n_levels) wa = std::max(wa, g->hp[p[k].player].level_max_act[l]);
+      wa = std::min(wa, kInternalWaves);  // a wavefront takes actions j, j + wa, ... beyond that
       // two hands per lane only where the level fills the chip several times
       // over; a narrow level is latency-bound and gains from more lanes
       if (pair && (size_t)bx * total >= 4 * (size_t)g->n_cu)
