@@ -11,7 +11,7 @@
 //  * the same steps one level per launch for large trees:
 //    bottom_up_leaf_pair_kernel (lowest level) or bottom_up_level_kernel
 //    (its one-hand-per-lane form), bottom_up_internal_kernel (levels with
-//    children, one wavefront per action), root_sums_kernel, and
+//    children, a wavefront per action, at most 8), root_sums_kernel, and
 //    top_down_pair_kernel or top_down_kernel;
 //  * small helpers (uniform point, a*x + b*y, max |x|).
 //
@@ -1238,7 +1238,7 @@ static hipError_t passes_launch(const egt_game* g, const Pass* p, int count, con
     } else if (l == 0) {
       hipLaunchKernelGGL(bottom_up_level_kernel<TG>, dim3(bx, total), dim3(kPassThreads), 0, s, a);
     } else {
-      // above the lowest level every node has children: one wavefront per action
+      // above the lowest level every node has children: a wavefront per action (at most kInternalWaves)
       int wa = 1;
       for (int k = 0; k < count; ++k)
         if (l < a.t[k].n_levels) wa = std::max(wa, g->hp[p[k].player].level_max_act[l]);
