@@ -2,37 +2,51 @@
 
 TEST INFRASTRUCTURE ONLY (see the package docstring).
 
-Follows the paper's algorithms in their own order:
+The method (Section 2) keeps a strategy pair (x, y) and two smoothing weights
+(mu_x, mu_y) for which the excessive gap value
+    EGV = [min_x <x, A y> + mu_x d_X(x)] - [max_y <x, A y> - mu_y d_Y(y)]
+is non-negative; while that holds, the saddle-point residual is at most
+mu_x Omega_X + mu_y Omega_Y.  Every iteration shrinks one player's weight by
+the factor (1 - tau) and moves both strategies so that the condition survives.
 
-* ``EGT`` (Algorithm 1): start at x0 = x_{mu_x}(y0), y0 = y_{mu_y}(x_omega);
-  tau_t = 2 / (t + 3); steps alternate between x (even t) and y (odd t);
-  stop when the saddle-point residual eps_sad <= eps.
-* ``Step`` (Algorithm 2), for the x side:
-      x_hat = (1 - tau) x + tau x_{mu_x}(y)
-      y_+   = (1 - tau) y + tau y_{mu_y}(x_hat)
-      x_til = grad d*( grad d(x_{mu_x}(y)) - tau / ((1 - tau) mu_x) grad f_{mu_y}(x_hat) )
-      x_+   = (1 - tau) x + tau x_til
-      mu_x+ = (1 - tau) mu_x
-  The y side is the same step on the mirrored problem min_y max_x <y, -A^T x>.
-  ``grad d*`` is computed as the prox of Section 4: the smoothed best response
-  with mu = 1 of the shifted gradient  tau/((1-tau) mu_x) A y_bar - grad d(x_bar),
-  with grad d from the appendix.  The equivalent shift-free form
-  SBR(A y + tau/(1-tau) A y_bar, mu_x) is computed beside it and the largest
-  difference is recorded.
-* ``BAL`` (Section 5, mu balancing): as EGT, but step the player with the
-  larger mu.
-* ``AS`` (Algorithms 3 and 4, aggressive mu reduction): keep tau (initially
-  1/2) across iterations; after each step test the excessive gap condition
-  and, while EGV < 0, halve tau and redo the step from the same point.
+One iteration focused on player p (Algorithm 2; o is the opponent):
+  * the anchor: p's smoothed best response to the opponent's current
+    strategy, an interior point of p's treeplex;
+  * p's strategy mixed toward the anchor with weight tau; the opponent
+    answers that mixed point with its own smoothed best response and moves
+    toward the answer with the same weight;
+  * p's prox step from the anchor (Section 4): the minimiser of the linear
+    term tau / ((1 - tau) mu_p) <g, q> plus the Bregman divergence of d from
+    the anchor, where g is p's gradient at the opponent's answer.  It is the
+    smoothed best response with weight 1 to that scaled gradient minus
+    grad d(anchor), grad d taken from the appendix;
+  * p moves toward the prox point with weight tau, and mu_p shrinks.
+The focus on y is the same iteration on the mirrored problem
+min_y max_x <y, -A^T x>.  Beside the prox through grad d the oracle computes
+the equivalent shift-free form, the smoothed best response with weight mu_p
+to (gradient at the opponent's current strategy) + tau/(1 - tau) g, and
+records the largest difference between the two.
+
+Drivers:
+* ``ALT`` (Algorithm 1): tau_t = 2 / (t + 3), focus on x at even t and on y
+  at odd t, start x0 = x_{mu_x}(y0), y0 = y_{mu_y}(x_omega), stop when the
+  saddle-point residual reaches eps;
+* ``BAL`` (Section 5, mu balancing): as ALT but the focus goes to the player
+  with the larger mu;
+* ``AS`` (Algorithms 3 and 4): tau starts at 1/2, is kept between iterations,
+  and is halved (redoing the iteration from the same point) for as long as
+  the excessive gap value after the iteration is negative.
 
 Readings where the paper is silent or garbled:
-* Algorithm 1's first line is taken with a minus sign, x0 = grad d*(-f'/mu_x),
-  i.e. x0 is player 1's smoothed best response to A y0 (as in Algorithm 2);
-* the "practically tuned" initial mu is not given: mu0 = 1e-3 times the
-  largest gradient entry at the uniform point over the largest beta, doubled
-  for both players until the excessive gap condition holds at (x0, y0);
-* Algorithm 4 tests EGV at the new point (x+, y+) with mu+ and the other
-  player's unchanged mu, strictly "< 0", and returns (mu+, x+, y+, tau).
+* Algorithm 1's first line is taken with a minus sign: x0 is player 1's
+  smoothed best response to A y0, as in Algorithm 2's prox step;
+* the "practically tuned" initial mu is a convention of this implementation:
+  1e-3 times the largest gradient entry at the uniform point over the largest
+  beta, doubled for both players until the excessive gap condition holds at
+  (x0, y0);
+* Algorithm 4 tests EGV at the new point with the reduced mu and the other
+  player's unchanged mu, strictly "< 0", and hands back the new point, the
+  reduced mu and the tau that was accepted.
 """
 from __future__ import annotations
 
@@ -51,7 +65,6 @@ class Trace:
     mu0: tuple = (0.0, 0.0)
     iters: int = 0
     backtracks: int = 0
-    products_paper: int = 0
     gap: float = float("nan")
     value_p2: float = float("nan")
     max_prox_diff: float = 0.0
@@ -84,22 +97,36 @@ class EGT:
     def egv(self, x, y, mu_x, mu_y):
         return self.P.egv(x, y, mu_x, mu_y)[0]
 
+    def anchor(self, p, g_other, mu_p):
+        """p's smoothed best response to its gradient g_other at the opponent's
+        current strategy: (point, local log q_bar)."""
+        q, _, lqb, _ = self.P.sbr(p, g_other, mu_p)
+        return q, lqb
+
+    def prox(self, p, anchor_lqb, g, scale):
+        """Section 4's prox from an interior anchor: argmin_q scale <g, q> + D(q, anchor),
+        D the Bregman divergence of the dilated entropy; the linear part of D is
+        -grad d(anchor), so the minimiser is the smoothed best response with
+        weight 1 to scale g - grad d(anchor) (the appendix's gradient)."""
+        return self.P.sbr(p, scale * g - self.P.dgf_grad(p, anchor_lqb), 1.0)[0]
+
     def step(self, p, mu_p, mu_o, own, other, tau):
         """Algorithm 2 focused on player p.  Returns (mu_p+, own+, other+, prox_diff)."""
         o = 1 - p
-        g1 = self.G(p, other)
-        own_bar, _, lqb, _ = self.P.sbr(p, g1, mu_p)
-        own_hat = (1.0 - tau) * own + tau * own_bar
-        other_bar = self.P.sbr(o, self.G(o, own_hat), mu_o)[0]
-        other_plus = (1.0 - tau) * other + tau * other_bar
-        g3 = self.G(p, other_bar)
-        shifted = tau / ((1.0 - tau) * mu_p) * g3 - self.P.dgf_grad(p, lqb)
-        own_til_lit = self.P.sbr(p, shifted, 1.0)[0]
-        own_til_free = self.P.sbr(p, g1 + tau / (1.0 - tau) * g3, mu_p)[0]
-        diff = float(np.max(np.abs(own_til_lit - own_til_free)))
-        own_til = own_til_lit if self.literal else own_til_free
-        own_plus = (1.0 - tau) * own + tau * own_til
-        return (1.0 - tau) * mu_p, own_plus, other_plus, diff
+        g_other = self.G(p, other)
+        anc, anc_lqb = self.anchor(p, g_other, mu_p)
+        own_mixed = (1.0 - tau) * own + tau * anc
+        answer = self.P.sbr(o, self.G(o, own_mixed), mu_o)[0]
+        other_next = (1.0 - tau) * other + tau * answer
+        g_answer = self.G(p, answer)
+        target = self.prox(p, anc_lqb, g_answer, tau / ((1.0 - tau) * mu_p))
+        # shift-free form of the same prox (the anchor is the smoothed response to G(p, other))
+        target_free = self.P.sbr(p, g_other + tau / (1.0 - tau) * g_answer, mu_p)[0]
+        diff = float(np.max(np.abs(target - target_free)))
+        if not self.literal:
+            target = target_free
+        own_next = (1.0 - tau) * own + tau * target
+        return (1.0 - tau) * mu_p, own_next, other_next, diff
 
 
 def iterate(E: EGT, variant: str, t: int, x, y, mu_x: float, mu_y: float, tau: float, side=None,
@@ -185,7 +212,6 @@ def solve(prob: Problem, variant: str = "AS", eps: float | None = None, max_iter
         row.update(side=r["side"], tau=r["tau"], egv=r["egv"], backtracks=r["backtracks"])
         tr.rows.append(row)
         tr.backtracks += r["backtracks"]
-        tr.products_paper += (4 + 3 * r["backtracks"]) if variant == "AS" else 3
         x, y, mu_x, mu_y = r["x"], r["y"], r["mu_x"], r["mu_y"]
         if variant == "AS":
             tau = r["tau"]

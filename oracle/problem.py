@@ -121,7 +121,7 @@ class Problem:
         q = np.zeros((t.n_seq, self.n))
         for v in reversed(t.post_order):  # parents first
             node = t.nodes[v]
-            q[node.first_seq:node.first_seq + node.n_act] = self._parent_rows(p, q, v)[None, :] * (1.0 / node.n_act)
+            q[node.first_seq:node.first_seq + node.n_act] = self._parent_rows(p, q, v)[None, :] / node.n_act
         return q
 
     def flow_residual(self, p, q):
@@ -242,7 +242,10 @@ class Problem:
             cols = np.arange(self.n)
             V[v] = gt[i_star, cols] + temp * logqbar[sl][i_star, cols] + temp * np.log(node.n_act)
         q = np.zeros((t.n_seq, self.n))
-        for v in reversed(t.post_order):  # top-down
+        # top-down: the treeplex scales each simplex by its parent sequence
+        # (Section 3), so a sequence's mass is the parent's mass times the local
+        # probability of the action, q_i = q_{p_j} q_bar_i (Section 4)
+        for v in reversed(t.post_order):
             node = t.nodes[v]
             sl = slice(node.first_seq, node.first_seq + node.n_act)
             q[sl] = self._parent_rows(p, q, v)[None, :] * qbar_all[sl]

@@ -50,11 +50,13 @@ def test_kuhn_egt_converges_to_game_value(kuhn, variant):
     assert kuhn.flow_residual(0, tr.x) < 1e-13 and kuhn.flow_residual(1, tr.y) < 1e-13
 
 
-@pytest.mark.parametrize("seed", [0, 2])
-def test_iterates_bracket_lp_value(seed):
-    P = Problem(make_instance("micro", seed))
+@pytest.mark.parametrize("cfg,seed,eps", [("micro", 0, 1e-3), ("micro", 2, 1e-3), ("c0", 0, None)])
+def test_iterates_bracket_lp_value(cfg, seed, eps):
+    """c0 is the 105-hand endgame (2310 sequences per player), solved to
+    1e-3 pot; the micro endgames to 1e-3 chips."""
+    P = Problem(make_instance(cfg, seed))
     v_star, _ = lp_value(P)
-    tr = solve(P, "AS", eps=1e-3, max_iters=3000)
+    tr = solve(P, "AS", eps=eps, max_iters=3000)
     for r in tr.rows:
         assert r["br_min_x"] <= v_star + 1e-10
         assert r["br_max_y"] >= v_star - 1e-10
@@ -95,12 +97,66 @@ def test_theory_safe_start_keeps_condition_and_rate(cfg):
         assert r["gap"] <= 4 * nA / (r["t"] + 1) * np.sqrt(OX * OY * MX * MY)
 
 
-def test_paper_gradient_accounting(kuhn):
-    # 3 products per EGT step; EGT/as adds one for the EGV test and 3 per retry
-    tr = solve(kuhn, "AS", eps=1e-3, max_iters=500)
-    assert tr.products_paper == 4 * tr.iters + 3 * tr.backtracks
-    tr = solve(kuhn, "ALT", eps=1e-3, max_iters=500)
-    assert tr.products_paper == 3 * tr.iters
+def test_gradient_accounting_counts_real_products():
+    """Section 7 counts gradient computations: 3 per EGT step (A y for the
+    anchor, A^T x_hat for the opponent's answer, A y_bar for the prox), 4 per
+    EGT/as iteration (the excessive-gap test adds A^T x_+, while A y_+ follows
+    from linearity) and 3 more per retry (the anchor's A y is kept).  The
+    oracle's products are counted by wrapping grad_x / grad_y: a step makes
+    exactly 3 calls; an EGT/as attempt makes 5, and the two the paper does not
+    count are the reusable ones -- the gradient at y_+ equals the mixture of
+    the gradients at y and y_bar, and a retry's A y equals the first
+    attempt's."""
+    from oracle import EGT, iterate
+
+    P = Problem(make_instance("c0", 1))
+    E = EGT(P)
+    mu = E.auto_mu0()
+    while True:
+        x, y = E.init_point(mu, mu)
+        if E.egv(x, y, mu, mu) >= 0.0:
+            break
+        mu *= 2.0
+    log = []
+    gx0, gy0 = P.grad_x, P.grad_y
+
+    def gx(v):
+        out = gx0(v)
+        log.append(("x", v.copy(), out))
+        return out
+
+    def gy(v):
+        out = gy0(v)
+        log.append(("y", v.copy(), out))
+        return out
+
+    P.grad_x, P.grad_y = gx, gy
+    try:
+        E.step(0, mu, mu, x, y, 0.5)
+        assert [k for k, _, _ in log] == ["x", "y", "x"]
+        t, mx, my, tau = 0, mu, mu, 0.5
+        seen_retry = False
+        while t < 40 and not seen_retry:
+            log.clear()
+            r = iterate(E, "AS", t, x, y, mx, my, tau)
+            attempts = 1 + r["backtracks"]
+            assert len(log) == 5 * attempts
+            # the last attempt: step products, then the EGV test's grad_x(y+), grad_y(x+)
+            step = log[-5:-2]
+            kinds = "xy"[r["side"]] + "yx"[r["side"]] + "xy"[r["side"]]
+            assert "".join(k for k, _, _ in step) == kinds
+            g_plus = log[-2] if log[-2][0] == "xy"[r["side"]] else log[-1]
+            want = (1.0 - r["tau"]) * step[0][2] + r["tau"] * step[2][2]
+            assert np.abs(g_plus[2] - want).max() <= 1e-12 * np.abs(want).max()
+            if r["backtracks"]:
+                seen_retry = True
+                for a in range(1, attempts):
+                    assert np.array_equal(log[5 * a][2], log[0][2])  # A y (or A^T x) kept across retries
+            x, y, mx, my, tau = r["x"], r["y"], r["mu_x"], r["mu_y"], r["tau"]
+            t += 1
+        assert seen_retry
+    finally:
+        P.grad_x, P.grad_y = gx0, gy0
 
 
 def test_oracle_rounding_sensitivity():
