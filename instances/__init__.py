@@ -7,6 +7,8 @@ math), so both the CPU oracle and the GPU path may consume its output.
 """
 from .endgames import (  # noqa: F401
     CONFIGS,
+    LIBRATUS_RIVER,
+    BetAbstraction,
     Instance,
     kuhn,
     make_instance,

@@ -27,6 +27,29 @@ import numpy as np
 
 
 @dataclass(frozen=True)
+class BetAbstraction:
+    """Situation-dependent bet sizes (the shape of the Libratus river
+    abstraction in Section 7).  ``fracs[p][d]`` lists the pot fractions player
+    p may bet (d = 0, not facing a bet) or raise by (d >= 1) once d bets or
+    raises have been made on the river, d capped at 3 so that ``[p][3]``
+    covers every later raise; ``allin[p][d]`` adds all-in there;
+    ``open_fold[p]`` lets p fold when not facing a bet."""
+    fracs: tuple
+    allin: tuple
+    open_fold: tuple
+
+
+# Section 7's description of the Libratus river abstraction, player 1
+# (Libratus, first to act) then player 2.
+LIBRATUS_RIVER = BetAbstraction(
+    fracs=(((0.25, 0.5, 1.0, 2.0, 4.0, 8.0), (0.4, 0.7, 1.1, 2.0), (0.4, 0.7, 2.0), (0.7,)),
+           ((0.5, 0.75, 1.0), (0.7, 1.1), (0.7,), (0.7,))),
+    allin=((True, True, True, True), (True, True, True, True)),
+    open_fold=(True, True),
+)
+
+
+@dataclass(frozen=True)
 class Instance:
     name: str
     n_cards: int
@@ -41,6 +64,7 @@ class Instance:
     allin: bool
     max_raises: int
     seed: int = 0
+    abstraction: BetAbstraction | None = None  # None: bet_fracs / allin in every situation, no open fold
     meta: dict = field(default_factory=dict)
 
     @property
@@ -95,6 +119,7 @@ def river(
     max_raises: int,
     allin: bool = True,
     n_board: int = 5,
+    abstraction: BetAbstraction | None = None,
 ) -> Instance:
     rng = np.random.Generator(np.random.PCG64(seed))
     n_cards = 4 * n_ranks
@@ -124,6 +149,7 @@ def river(
         allin=bool(allin),
         max_raises=int(max_raises),
         seed=int(seed),
+        abstraction=abstraction,
     )
 
 
@@ -148,11 +174,33 @@ CONFIGS = {
                bet_fracs=(0.25, 0.5, 0.75, 1.0, 1.5, 2.0, 3.0), max_raises=4),
 }
 CONFIGS["c2"] = CONFIGS["c1"]
+# The Libratus-style river abstraction on a 52-card endgame with Endgame 2's
+# pot (2100) and the remaining stacks of 200-big-blind play (20000 - 1050):
+# 152 sequences per hand for player 1 and 153 for player 2 (its pass after
+# an opening fold), 164,312 and 165,393 over 1081 hands.
+CONFIGS["lib"] = dict(n_ranks=13, strength_kind="ranking_ties10", alpha=0.5, pot=2100.0, stack=18950.0,
+                      bet_fracs=(), max_raises=8, abstraction=LIBRATUS_RIVER)
+
+
+# The same rules on a 10-hand endgame (8-card deck, 3 board cards): small
+# enough for the exact LP and for game walks deal by deal.
+CONFIGS["lib_micro"] = dict(n_ranks=2, strength_kind="int30", alpha=1.0, pot=10.0, stack=20.0, bet_fracs=(),
+                            max_raises=8, n_board=3, abstraction=LIBRATUS_RIVER)
+
+# Kuhn poker where either player may also fold when not facing a bet (the
+# only size is all-in): folding first, or facing a check, is never better
+# than checking, so the game value is Kuhn's.
+KUHN_OPEN_FOLD = BetAbstraction(fracs=(((),) * 4, ((),) * 4), allin=((True,) * 4, (True,) * 4),
+                                open_fold=(True, True))
 
 
 def make_instance(config: str, seed: int = 0) -> Instance:
     if config == "kuhn":
         return kuhn()
+    if config == "kuhn_open_fold":
+        k = kuhn()
+        return Instance(**{**{f: getattr(k, f) for f in k.__dataclass_fields__}, "name": config,
+                           "bet_fracs": (), "abstraction": KUHN_OPEN_FOLD})
     if config.startswith("micro"):
         return micro(seed)
     return river(config, seed, **CONFIGS[config])

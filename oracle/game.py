@@ -18,8 +18,7 @@ What is built here, straight from the definitions:
   min_x max_y <x, A y> (Section 2, Eq. 2).  A holds player 2's payoff, which is
   player 1's loss, so player 1 (x, first to act) minimises.
 
-Betting rules used for the synthetic endgames (the paper's own abstraction is
-Libratus' and is not reproduced):
+Betting rules used for the synthetic endgames:
   * not facing a bet: check, or bet ``f * pot`` for each bet fraction f, plus
     all-in; a bet at or above the remaining stack becomes all-in; duplicates
     are removed;
@@ -28,7 +27,17 @@ Libratus' and is not reproduced):
     ``max_raises`` raises have happened after the opening bet and the opponent
     is not all-in;
   * the first player checking and the second checking back, or a call, ends in
-    a showdown; a fold ends the hand.
+    a showdown; a fold ends the hand (a fold before the opponent has acted
+    goes through a one-action "pass" decision of the opponent, see
+    ``_pass_node``).
+With the symmetric rules one list of fractions and the all-in flag apply in
+every situation.  With a situation-dependent abstraction (the shape Section 7
+gives for Libratus' river abstraction) the fractions and the all-in flag
+depend on the acting player and on how many bets or raises the river has
+seen so far (0 when not facing a bet, 1 facing the opening bet, 2 facing the
+first raise, 3 for every later raise), and a player not facing a bet may also
+fold (the paper lets Libratus fold first and the opponent fold facing a
+check).
 Payoffs are net chips for player 2: each player put pot/2 in before the
 river, so a fold by player 1 pays player 2 ``pot/2 + c1``, a fold by player 2
 costs player 2 ``pot/2 + c2`` and a showdown pays ``(pot/2 + c)`` times the
@@ -97,6 +106,7 @@ class Game:
         self.fracs = tuple(float(f) for f in inst.bet_fracs)
         self.allin = bool(inst.allin)
         self.max_raises = int(inst.max_raises)
+        self.abstraction = getattr(inst, "abstraction", None)
         self._nodes = [[], []]  # raw per player: (history, parent_seq_key)
         self._seq_keys = [[], []]
         self._seq_index = [{}, {}]
@@ -111,6 +121,15 @@ class Game:
         ]
 
     # -- betting tree ---------------------------------------------------
+    def _sizes(self, player, bets_so_far):
+        """(pot fractions, all-in flag) of the acting player when the river
+        has seen ``bets_so_far`` bets or raises."""
+        ab = self.abstraction
+        if ab is None:
+            return self.fracs, self.allin
+        d = min(bets_so_far, 3)
+        return tuple(float(f) for f in ab.fracs[player][d]), bool(ab.allin[player][d])
+
     def _actions(self, c, player, n_raises):
         """(token, kind, new contribution of the acting player)."""
         P, S = self.pot, self.stack
@@ -119,9 +138,12 @@ class Game:
         pot_now = P + c[0] + c[1]
         acts = []
         if to_call == 0.0:
+            if self.abstraction is not None and self.abstraction.open_fold[player]:
+                acts.append(("f", "fold", c[player]))
             acts.append(("k", "check", c[player]))
-            amounts = [min(c[player] + f * pot_now, S) for f in self.fracs]
-            if self.allin:
+            fracs, allin = self._sizes(player, 0)
+            amounts = [min(c[player] + f * pot_now, S) for f in fracs]
+            if allin:
                 amounts.append(S)
             for a in sorted(set(a for a in amounts if a > c[player])):
                 acts.append((_tok_amount(a), "bet", a))
@@ -129,8 +151,10 @@ class Game:
             acts.append(("f", "fold", c[player]))
             acts.append(("c", "call", c[opp]))
             if n_raises < self.max_raises and c[opp] < S:
-                amounts = [min(c[opp] + f * (pot_now + to_call), S) for f in self.fracs]
-                if self.allin:
+                # facing the opening bet after n_raises = 0 raises: 1 bet so far
+                fracs, allin = self._sizes(player, 1 + n_raises)
+                amounts = [min(c[opp] + f * (pot_now + to_call), S) for f in fracs]
+                if allin:
                     amounts.append(S)
                 for a in sorted(set(a for a in amounts if a > c[opp])):
                     acts.append((_tok_amount(a), "raise", a))
@@ -154,6 +178,9 @@ class Game:
             ls = tuple(ls)
             if kind == "fold":
                 u = (half + c[0]) if player == 0 else -(half + c[1])
+                if ls[1 - player] is None:
+                    ls = self._pass_node(h2, 1 - player, c, ls)
+                    h2 = h2 + ("p",)
                 self.terminals_raw.append(("fold", h2, ls[0], ls[1], u))
             elif kind == "call":
                 self.terminals_raw.append(("show", h2, ls[0], ls[1], half + c[1 - player]))
@@ -166,6 +193,23 @@ class Game:
                 nc = list(c)
                 nc[player] = newc
                 self._walk(h2, tuple(nc), 1 - player, n_raises + (1 if kind == "raise" else 0), ls)
+
+    def _pass_node(self, hist, player, c, last_seq):
+        """A fold before ``player`` has acted would end at player's empty
+        sequence, which has no coordinate in the treeplex (its value is the
+        constant 1), and would add a term linear in the folder's strategy to
+        the payoff.  Instead the opponent gets a decision with the single
+        action "p" (pass) before the fold takes effect: its sequence always
+        has mass 1, its simplex has no entropy, and the payoff stays bilinear
+        in the two treeplexes."""
+        self._nodes[player].append((hist, None))
+        self._node_actions[player].append([("p", "pass", c[player])])
+        skey = "/".join(hist + ("p",))
+        self._seq_index[player][skey] = len(self._seq_keys[player])
+        self._seq_keys[player].append(skey)
+        ls = list(last_seq)
+        ls[player] = skey
+        return tuple(ls)
 
     # -- treeplexes -----------------------------------------------------
     def _build_treeplex(self, p):

@@ -35,6 +35,7 @@ def explicit_A(prob):
     A = np.zeros((S0 * n, S1 * n))
     for z in prob.game.terminals:
         s0, s1 = z.seq
+        assert s0 >= 0 and s1 >= 0, "a terminal at an empty sequence has no entry in A"
         for h1 in range(n):
             for h2 in range(n):
                 if cards[h1] & cards[h2]:

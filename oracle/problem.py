@@ -53,6 +53,10 @@ class Problem:
         self.Z = float(self.b[0] @ self.C @ self.b[1])
         self.tp = self.game.treeplex
         self.n_seq = [t.n_seq for t in self.tp]
+        # the payoff is bilinear in the two treeplexes only if every terminal
+        # is reached after both players acted (the game gives a one-action
+        # decision to a player who would otherwise not have acted)
+        assert all(z.seq[0] >= 0 and z.seq[1] >= 0 for z in self.game.terminals)
         self._by_kind = {}
         for kind in ("fold", "show"):
             zs = [z for z in self.game.terminals if z.kind == kind]

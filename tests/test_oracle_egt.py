@@ -42,6 +42,16 @@ def test_kuhn_lp_value(kuhn):
     assert kuhn.flow_residual(0, x) < 1e-9
 
 
+def test_kuhn_with_open_folds_keeps_the_value():
+    """Folding when not facing a bet never beats checking, so adding those
+    folds (the paper's abstraction allows them) leaves Kuhn's value."""
+    P = Problem(make_instance("kuhn_open_fold"))
+    v, _ = lp_value(P)
+    assert v == pytest.approx(-_golden_kuhn(), abs=1e-12)
+    tr = solve(P, "AS", eps=2e-4, max_iters=20000)
+    assert tr.converged and abs(tr.value_p2 - (-_golden_kuhn())) <= tr.gap
+
+
 @pytest.mark.parametrize("variant", ["AS", "BAL", "ALT"])
 def test_kuhn_egt_converges_to_game_value(kuhn, variant):
     tr = solve(kuhn, variant, eps=2e-4, max_iters=20000)
@@ -50,7 +60,8 @@ def test_kuhn_egt_converges_to_game_value(kuhn, variant):
     assert kuhn.flow_residual(0, tr.x) < 1e-13 and kuhn.flow_residual(1, tr.y) < 1e-13
 
 
-@pytest.mark.parametrize("cfg,seed,eps", [("micro", 0, 1e-3), ("micro", 2, 1e-3), ("c0", 0, None)])
+@pytest.mark.parametrize("cfg,seed,eps", [("micro", 0, 1e-3), ("micro", 2, 1e-3), ("c0", 0, None),
+                                          ("lib_micro", 0, 1e-3)])
 def test_iterates_bracket_lp_value(cfg, seed, eps):
     """c0 is the 105-hand endgame (2310 sequences per player), solved to
     1e-3 pot; the micro endgames to 1e-3 chips."""
@@ -174,3 +185,32 @@ def test_oracle_rounding_sensitivity():
     assert d(5) < 1e-13
     assert d(100) > 1e-6
     assert a.max_prox_diff < 1e-12 and b.max_prox_diff < 1e-12
+
+
+def test_trajectory_sensitivity_to_product_rounding():
+    """EGT (Algorithm 1) amplifies rounding in the products as mu shrinks:
+    perturbing every product entry by at most one unit in the last place
+    (relative 2.2e-16, a seeded draw) moves the 105-hand endgame's
+    2000-iteration trajectory by about 1e-10 of max |x| by the end, although
+    the two runs agree to 1e-15 for the first hundred iterations.  Any two
+    correct FP64 evaluations of A y (e.g. the dense definition and the O(n)
+    prefix-sum form) differ by at least this much per product, so whole
+    2000-iteration trajectories can only be compared at a bar above it."""
+    P = Problem(make_instance("c0", 0))
+    Q = Problem(make_instance("c0", 0))
+    rng = np.random.default_rng(1)
+    gx0, gy0 = Q.grad_x, Q.grad_y
+    Q.grad_x = lambda v: gx0(v) * (1.0 + rng.uniform(-1.0, 1.0, (Q.n_seq[0], Q.n)) * 2.2e-16)
+    Q.grad_y = lambda v: gy0(v) * (1.0 + rng.uniform(-1.0, 1.0, (Q.n_seq[1], Q.n)) * 2.2e-16)
+    xa, xb = [], []
+    solve(P, "ALT", eps=0.0, max_iters=2000, on_iterate=lambda t, x, y, *r: xa.append((x.copy(), y.copy())))
+    solve(Q, "ALT", eps=0.0, max_iters=2000, on_iterate=lambda t, x, y, *r: xb.append((x.copy(), y.copy())))
+
+    def d(t):
+        (x0, y0), (x1, y1) = xa[t], xb[t]
+        return max(np.abs(x0 - x1).max() / np.abs(x0).max(), np.abs(y0 - y1).max() / np.abs(y0).max())
+
+    worst = max(d(t) for t in range(len(xa)))
+    print(f"  drift at t=100: {d(100):.2e}, t=2000: {d(2000):.2e}, worst {worst:.2e}")
+    assert d(100) < 1e-13
+    assert worst > 5e-11

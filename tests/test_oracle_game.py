@@ -85,6 +85,106 @@ def test_tree_sizes_match_independent_count(cfg):
     assert got["fold"] == leaves["fold"] and got["show"] == leaves["show"]
 
 
+def _count_abstraction(pot, stack, ab, R):
+    """The same counts under a situation-dependent abstraction: sizes by the
+    acting player and the bets or raises so far (capped at 3), open folds (a
+    fold before the opponent acted adds the opponent's one-action pass node)."""
+    nodes = [0, 0]
+    seqs = [0, 0]
+    leaves = {"fold": 0, "show": 0}
+
+    def rec(c, p, bets, opp_acted=True):
+        nodes[p] += 1
+        o = 1 - p
+        pot_now = pot + c[0] + c[1]
+        d = min(bets, 3)
+        if c[0] == c[1]:
+            amts = {min(c[p] + f * pot_now, stack) for f in ab.fracs[p][0]}
+            if ab.allin[p][0]:
+                amts.add(stack)
+            amts = sorted(a for a in amts if a > c[p])
+            folds = 1 if ab.open_fold[p] else 0
+            leaves["fold"] += folds
+            if folds and not opp_acted:
+                nodes[o] += 1
+                seqs[o] += 1
+            seqs[p] += folds + 1 + len(amts)
+            if p == 0:
+                rec(c, 1, bets)
+            else:
+                leaves["show"] += 1
+            for a in amts:
+                rec((a, c[1]) if p == 0 else (c[0], a), o, bets + 1)
+        else:
+            to_call = c[o] - c[p]
+            leaves["fold"] += 1
+            leaves["show"] += 1
+            amts = []
+            if bets - 1 < R and c[o] < stack:
+                s = {min(c[o] + f * (pot_now + to_call), stack) for f in ab.fracs[p][d]}
+                if ab.allin[p][d]:
+                    s.add(stack)
+                amts = sorted(a for a in s if a > c[o])
+            seqs[p] += 2 + len(amts)
+            for a in amts:
+                rec((a, c[1]) if p == 0 else (c[0], a), o, bets + 1)
+
+    rec((0.0, 0.0), 0, 0, opp_acted=False)
+    return nodes, seqs, leaves
+
+
+@pytest.mark.parametrize("cfg", ["kuhn_open_fold", "lib_micro", "lib"])
+def test_abstraction_tree_sizes_match_independent_count(cfg):
+    inst = make_instance(cfg, 0)
+    nodes, seqs, leaves = _count_abstraction(inst.pot, inst.stack, inst.abstraction, inst.max_raises)
+    got = Game(inst).counts()
+    assert got["nodes"] == nodes
+    assert got["seqs"] == seqs
+    assert got["fold"] == leaves["fold"] and got["show"] == leaves["show"]
+
+
+def test_kuhn_with_open_folds_written_out():
+    """Kuhn poker where a player not facing a bet may also fold: player 1 can
+    fold first, player 2 can fold facing a check.  A fold costs the folder
+    its ante (pot / 2 = 1) plus its river chips."""
+    g = Game(make_instance("kuhn_open_fold"))
+    assert g.treeplex[0].seq_keys == ["f", "k", "b1000", "k/b1000/f", "k/b1000/c"]
+    # player 2 passes (its only action) after player 1 folds first
+    assert g.treeplex[1].seq_keys == ["f/p", "k/f", "k/k", "k/b1000", "b1000/f", "b1000/c"]
+    got = sorted((z.history, z.kind, z.u) for z in g.terminals)
+    want = sorted([
+        (("f", "p"), "fold", 1.0),
+        (("k", "f"), "fold", -1.0),
+        (("k", "k"), "show", 1.0),
+        (("k", "b1000", "f"), "fold", 1.0),
+        (("k", "b1000", "c"), "show", 2.0),
+        (("b1000", "f"), "fold", -1.0),
+        (("b1000", "c"), "show", 2.0),
+    ])
+    assert got == want
+
+
+def test_libratus_abstraction_sizes_per_situation():
+    """Section 7's river abstraction on a pot of 2100 with 18950 behind: the
+    first player's opening sizes are 0.25x to 8x pot and all-in, after fold
+    and check."""
+    g = Game(make_instance("lib", 0))
+    root = [v for v in g.treeplex[0].nodes if v.parent_seq < 0]
+    assert len(root) == 1
+    keys = g.treeplex[0].seq_keys[root[0].first_seq:root[0].first_seq + root[0].n_act]
+    assert keys == ["f", "k", "b525000", "b1050000", "b2100000", "b4200000", "b8400000", "b16800000", "b18950000"]
+    # the second player facing a check: fold, check, 0.5x, 0.75x, 1x pot, all-in
+    v = next(v for v in g.treeplex[1].nodes if v.key == "k")
+    keys = g.treeplex[1].seq_keys[v.first_seq:v.first_seq + v.n_act]
+    assert keys == ["k/f", "k/k", "k/b1050000", "k/b1575000", "k/b2100000", "k/b18950000"]
+    # facing the opening bet of 1x pot (2100 into 2100): fold, call, raise to
+    # 2100 + f * (4200 + 2100) for f = 0.7, 1.1, all-in
+    v = next(v for v in g.treeplex[1].nodes if v.key == "b2100000")
+    keys = g.treeplex[1].seq_keys[v.first_seq:v.first_seq + v.n_act]
+    assert keys == ["b2100000/f", "b2100000/c", "b2100000/b6510000", "b2100000/b9030000", "b2100000/b18950000"]
+    assert g.counts()["seqs"] == [152, 153]
+
+
 def test_tree_sizes_of_the_workloads():
     # sequences per hand per player at the benchmark shapes
     assert Game(make_instance("c0", 0)).counts()["seqs"] == [22, 22]
@@ -92,7 +192,8 @@ def test_tree_sizes_of_the_workloads():
     assert Game(make_instance("c3", 0)).counts()["seqs"] == [5938, 5938]
 
 
-@pytest.mark.parametrize("cfg,seed", [("kuhn", 0), ("micro", 0), ("micro", 3)])
+@pytest.mark.parametrize("cfg,seed", [("kuhn", 0), ("micro", 0), ("micro", 3), ("kuhn_open_fold", 0),
+                                      ("lib_micro", 1)])
 def test_operator_equals_entrywise_A(cfg, seed):
     P = Problem(make_instance(cfg, seed))
     A = explicit_A(P)
@@ -167,7 +268,7 @@ def _walk_value(P, beh):
     return num / den
 
 
-@pytest.mark.parametrize("cfg,seed", [("kuhn", 0), ("micro", 1), ("c0", 2)])
+@pytest.mark.parametrize("cfg,seed", [("kuhn", 0), ("micro", 1), ("c0", 2), ("kuhn_open_fold", 0), ("lib_micro", 2)])
 def test_operator_matches_game_walk(cfg, seed):
     P = Problem(make_instance(cfg, seed))
     rng = np.random.default_rng(10 + seed)
