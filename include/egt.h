@@ -159,6 +159,24 @@ int egt_uniform(const egt_game* game, int player, double* strat_out, hipStream_t
 int egt_saddle_gap(const egt_game* game, const double* x, const double* y, double* gap,
                    double* br_max_y, double* br_min_x, hipStream_t stream);
 
+/* Allocation-free saddle gap, for callers that cannot allocate device memory:
+ * code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc.  Computes what egt_saddle_gap computes (the same kernels, the
+ * same summation order, so the same bits) but allocates nothing and does not
+ * synchronise: out3 is a caller-owned DEVICE array of three doubles that
+ * receives {gap, br_max_y, br_min_x} on `stream`.  Its scratch (both
+ * products, both best-response node-value buffers, the root partial sums) is
+ * a fixed library-owned device array of 160 MiB per device, reserved when the
+ * library's code is loaded on the device and held until the process ends;
+ * EGT_EINVAL when the game needs more (sum over both players of
+ * (n_seq + n_nodes) * ld doubles, each part rounded up to 256 bytes, plus 8 KiB:
+ * about 132 MiB for 1081 hands with eight bet sizes and four raises).  The game
+ * must live on the current device.  Every call on a device uses that device's
+ * one array: calls that overlap in time on one device (two streams, two
+ * threads) race and must be serialised by the caller. */
+int egt_saddle_gap_noalloc(const egt_game* game, const double* x, const double* y, double* out3,
+                           hipStream_t stream);
+
 /* ------------------------------------------------------------------------ */
 /* Precision form (FP32 vectors in the same canonical layout)                 */
 /* ------------------------------------------------------------------------ */

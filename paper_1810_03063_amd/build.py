@@ -18,7 +18,7 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libegt.so")
 
-SOURCES = ["egt_game.cpp", "egt_kernels.hip", "egt_mixed.hip", "egt_solver.cpp", "egt_batch.cpp", "egt_abi.cpp"]
+SOURCES = ["egt_game.cpp", "egt_kernels.hip", "egt_mixed.hip", "egt_solver.cpp", "egt_batch.cpp", "egt_abi.cpp", "egt_noalloc.hip"]
 
 FLAGS = [
     "--offload-arch=gfx950",

@@ -87,6 +87,7 @@ _best_response = _decl("egt_best_response", ctypes.c_int, _p, ctypes.c_int, _p, 
 _uniform = _decl("egt_uniform", ctypes.c_int, _p, ctypes.c_int, _p, _p)
 _saddle_gap = _decl("egt_saddle_gap", ctypes.c_int, _p, _p, _p, ctypes.POINTER(_f64), ctypes.POINTER(_f64),
                     ctypes.POINTER(_f64), _p)
+_saddle_gap_noalloc = _decl("egt_saddle_gap_noalloc", ctypes.c_int, _p, _p, _p, _p, _p)
 _state_create = _decl("egt_state_create", ctypes.c_int, _p, ctypes.POINTER(SolveOpts), _p, ctypes.POINTER(_p))
 _state_destroy = _decl("egt_state_destroy", ctypes.c_int, _p)
 _step = _decl("egt_step", ctypes.c_int, _p, ctypes.c_int, ctypes.POINTER(_f64), ctypes.POINTER(ctypes.c_int), _p)
@@ -117,7 +118,7 @@ EXPORTED = [
     "egt_uniform", "egt_saddle_gap", "egt_state_create", "egt_state_destroy", "egt_step",
     "egt_state_get", "egt_state_get_products", "egt_state_set", "egt_state_gap", "egt_solve",
     "egt_state_bytes", "egt_batch_create", "egt_batch_destroy", "egt_batch_admit", "egt_batch_tick",
-    "egt_batch_poll", "egt_batch_retire", "egt_batch_usage",
+    "egt_batch_poll", "egt_batch_retire", "egt_batch_usage", "egt_saddle_gap_noalloc",
 ]
 
 
@@ -283,6 +284,16 @@ def saddle_gap(game: Game, x, y, stream=None):
     _check(_saddle_gap(game.handle, _dptr(x, (game.n_seq[0], game.ld)), _dptr(y, (game.n_seq[1], game.ld)),
                        ctypes.byref(g), ctypes.byref(a), ctypes.byref(b), _stream(stream)))
     return g.value, a.value, b.value
+
+
+def saddle_gap_noalloc(game: Game, x, y, out3=None, stream=None):
+    """egt_saddle_gap_noalloc: {gap, max_y x^T A y, min_x x^T A y} into the
+    device tensor out3 (3 doubles, allocated here if None), no sync."""
+    if out3 is None:
+        out3 = torch.empty(3, dtype=torch.float64, device=x.device)
+    _check(_saddle_gap_noalloc(game.handle, _dptr(x, (game.n_seq[0], game.ld)), _dptr(y, (game.n_seq[1], game.ld)),
+                               _dptr(out3, (3,)), _stream(stream)))
+    return out3
 
 
 PRECISIONS = {"fp64": 0, "mixed": 1}
