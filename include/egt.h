@@ -64,6 +64,25 @@ const char* egt_last_error(void);
 /* that define A).                                                           */
 /* ------------------------------------------------------------------------ */
 
+/* Situation-dependent bet sizes: the shape Section 7 gives for the Libratus
+ * river abstraction.  For acting player p (0 = player 1) once d bets or raises
+ * have been made on the river (d = 0 when not facing a bet, 1 facing the
+ * opening bet, 2 facing the first raise, 3 for every later raise):
+ *   fracs[p][d][0 .. n_fracs[p][d])  pot fractions (bet f * pot when d = 0,
+ *                                    raise to c_opp + f * (pot + to_call) else),
+ *   allin[p][d]                      nonzero adds all-in there;
+ * open_fold[p] nonzero lets p fold when not facing a bet.  A fold before the
+ * opponent has acted gives the opponent a one-action decision "p" (pass)
+ * first, so that every terminal follows a sequence of each player and the
+ * payoff stays bilinear in the two treeplexes.  HOST memory, read during
+ * egt_build_game only. */
+typedef struct {
+  int32_t n_fracs[2][4];
+  const double* fracs[2][4];
+  int32_t allin[2][4];
+  int32_t open_fold[2];
+} egt_bet_abstraction;
+
 /* One river endgame.  All arrays are HOST memory, read during the call only.
  * hand_cards  [n_hands * cards_per_hand] card ids in [0, n_cards); two hands
  *             that share a card cannot be dealt together.
@@ -76,7 +95,9 @@ const char* egt_last_error(void);
  * c_opp + bet_fracs[i] * (pot + to_call) (plus all-in) while fewer than
  * max_raises raises followed the opening bet and the opponent is not all-in.
  * Amounts at or above the stack become all-in; duplicates are dropped.  Check
- * after check, or a call, is a showdown; a fold ends the hand. */
+ * after check, or a call, is a showdown; a fold ends the hand.  With
+ * abstraction != NULL the sizes (and the all-in flag) come from it per player
+ * and situation instead of bet_fracs / allin; max_raises still applies. */
 typedef struct {
   int32_t n_cards;
   int32_t cards_per_hand; /* 1 or 2 */
@@ -90,6 +111,7 @@ typedef struct {
   const double* bet_fracs;
   int32_t allin;
   int32_t max_raises;
+  const egt_bet_abstraction* abstraction; /* NULL: bet_fracs and allin in every situation */
 } egt_game_desc;
 
 /* Validates the description, enumerates the betting tree, builds both
@@ -113,7 +135,8 @@ int egt_game_dims(const egt_game* game, int player, int64_t* n_seq, int64_t* n_h
  * hand index at that slot.  keys (may be NULL) receives the betting-history
  * key of every sequence in library order, '\n'-terminated each; tokens are
  * joined by '/': "k" check, "f" fold, "c" call, "b<m>" bet or raise to a
- * total river contribution of m millichips.  *keys_len receives the bytes
+ * total river contribution of m millichips, "p" the pass that follows a fold
+ * made before the player acted.  *keys_len receives the bytes
  * needed (including a final NUL); EGT_EINVAL if keys_cap is too small. */
 int egt_game_layout(const egt_game* game, int player, int32_t* hand_perm, char* keys,
                     int64_t keys_cap, int64_t* keys_len);
@@ -212,7 +235,10 @@ typedef struct {
   double mu0_y;
   double tau0;        /* EGT/as initial tau; <= 0 means 0.5 */
   int32_t gap_every;  /* test the gap every k iterations (>= 1) */
-  int32_t reserved;
+  int32_t fresh_products; /* 0 (default): the stepped player's gradient at the opponent's new
+                             point is (1 - tau) A y + tau A y_bar by linearity, from products the
+                             step already made (3 products per attempt); 1: it is recomputed
+                             (4 per attempt, the accounting of Section 7) */
 } egt_solve_opts;
 
 typedef struct {
@@ -283,6 +309,84 @@ int egt_solve(const egt_game* game, const egt_solve_opts* opts, egt_result* resu
               egt_state** state_out, hipStream_t stream);
 
 /* ------------------------------------------------------------------------ */
+/* Counterfactual regret minimisation on the same kernels (the regret-based   */
+/* methods Section 7 compares EGT with; two products per iteration)           */
+/* ------------------------------------------------------------------------ */
+
+/* EGT_CFR_RM:     regret matching, both players updated against the
+ *                 strategies of the same iteration, uniform average;
+ * EGT_CFR_RMPLUS: the same with regret matching+ (cumulative regrets floored
+ *                 at zero after each update);
+ * EGT_CFR_PLUS:   regret matching+, player 2 updated against player 1's new
+ *                 strategy, average weighted by the iteration index. */
+enum { EGT_CFR_RM = 0, EGT_CFR_RMPLUS = 1, EGT_CFR_PLUS = 2 };
+
+typedef struct egt_cfr egt_cfr;
+
+/* Creates a CFR run on `game`: zero regrets, uniform local strategies, the
+ * uniform point as the first strategies and averages.  Synchronises
+ * `stream`. */
+int egt_cfr_create(const egt_game* game, int32_t variant, hipStream_t stream, egt_cfr** out);
+int egt_cfr_destroy(egt_cfr* cfr);
+
+/* Runs `iters` iterations on `stream` (no host synchronisation).  Iteration
+ * t folds the current strategies into the averages with weight w_t, then
+ * updates each player's cumulative counterfactual regrets from its product
+ * (A y for player 1, -A^T x for player 2) under its current local strategy
+ * and plays regret matching (or matching+) on them. */
+int egt_cfr_step(egt_cfr* cfr, int32_t iters, hipStream_t stream);
+
+/* Saddle gap of the average strategies (FP64 products and best responses;
+ * host outputs, any may be NULL).  Synchronises `stream`. */
+int egt_cfr_gap(egt_cfr* cfr, double* gap, double* br_max_y, double* br_min_x, hipStream_t stream);
+
+/* Copies the averages and the current strategies (device, canonical layout;
+ * any may be NULL) and the number of iterations run. */
+int egt_cfr_get(const egt_cfr* cfr, double* x_avg, double* y_avg, double* x_cur, double* y_cur,
+                int64_t* iters, hipStream_t stream);
+
+/* Runs CFR until the averages' saddle gap is <= eps (<= 0 means 1e-3 * pot),
+ * tested before the first iteration and every gap_every iterations, or
+ * max_iters.  result: iters, products (2 per iteration), gap and its terms,
+ * value_p1 of the averages, seconds; EGT_ENOTCONV at the cap. */
+int egt_cfr_solve(const egt_game* game, int32_t variant, double eps, int64_t max_iters, int32_t gap_every,
+                  egt_result* result, hipStream_t stream);
+
+/* ------------------------------------------------------------------------ */
+/* Mirror prox and Chambolle-Pock on the same kernels (Section 8's candidate  */
+/* first-order methods), with Bregman prox steps of the dilated entropy       */
+/* ------------------------------------------------------------------------ */
+
+/* EGT_FOM_MIRROR_PROX:     x^ = prox_x(eta_x A y), y^ = prox_y(-eta_y A^T x),
+ *                          x = prox_x(eta_x A y^), y = prox_y(-eta_y A^T x^),
+ *                          averages of x^, y^; 4 products per iteration;
+ * EGT_FOM_CHAMBOLLE_POCK:  x' = prox_x(tau A y), y' = prox_y(-sigma A^T (2 x' - x)),
+ *                          averages of x', y'; 2 products per iteration;
+ * prox_c(g) = argmin_q <g, q> + D(q, c), D the Bregman divergence of the
+ * dilated entropy; both start at its minimiser, the uniform point. */
+enum { EGT_FOM_MIRROR_PROX = 0, EGT_FOM_CHAMBOLLE_POCK = 1 };
+
+typedef struct egt_fom egt_fom;
+
+/* step_x, step_y: eta_x, eta_y (mirror prox) or tau, sigma (Chambolle-Pock),
+ * finite and > 0.  Synchronises `stream`. */
+int egt_fom_create(const egt_game* game, int32_t method, double step_x, double step_y, hipStream_t stream,
+                   egt_fom** out);
+int egt_fom_destroy(egt_fom* fom);
+
+/* Runs `iters` iterations on `stream` (no host synchronisation). */
+int egt_fom_step(egt_fom* fom, int32_t iters, hipStream_t stream);
+
+/* The averages (the current strategies before the first iteration) and the
+ * current strategies (device, canonical layout; any may be NULL), the
+ * iteration and product counts (host, may be NULL). */
+int egt_fom_get(const egt_fom* fom, double* x_avg, double* y_avg, double* x_cur, double* y_cur, int64_t* iters,
+                int64_t* products, hipStream_t stream);
+
+/* Saddle gap of the averages (FP64; host outputs).  Synchronises `stream`. */
+int egt_fom_gap(egt_fom* fom, double* gap, double* br_max_y, double* br_min_x, hipStream_t stream);
+
+/* ------------------------------------------------------------------------ */
 /* Serving form: continuous batching of solves on one device                  */
 /* ------------------------------------------------------------------------ */
 
@@ -329,6 +433,12 @@ int egt_batch_poll(egt_batch* batch, int32_t slot, int32_t* done, int32_t* statu
 /* Frees a finished slot and returns its bytes to the arena (EGT_EINVAL for a
  * slot that is free, queued or running). */
 int egt_batch_retire(egt_batch* batch, int32_t slot);
+
+/* Final iterates of a finished slot (canonical layout, FP64, device pointers
+ * x and y of the two players; either may be NULL), e.g. to re-measure the
+ * saddle gap.  The state stays in its arena range until the slot is retired.
+ * Synchronises `stream`.  EGT_EINVAL unless the slot's solve has finished. */
+int egt_batch_strategies(egt_batch* batch, int32_t slot, double* x, double* y, hipStream_t stream);
 
 /* Bytes charged by live and done slots, and their counts. */
 int egt_batch_usage(const egt_batch* batch, int64_t* used_bytes, int32_t* n_live, int32_t* n_done);

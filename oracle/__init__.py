@@ -8,3 +8,5 @@ instance generator in ``instances/``.
 from .game import Game  # noqa: F401,E402
 from .problem import Problem  # noqa: F401,E402
 from .egt import EGT, Trace, iterate, solve  # noqa: F401,E402
+from .cfr import Cfr, CfrTrace, solve_cfr  # noqa: F401,E402
+from .fom import ChambollePock, MirrorProx, bregman_prox, run_fom, theory_step  # noqa: F401,E402

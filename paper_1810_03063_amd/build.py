@@ -18,7 +18,7 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libegt.so")
 
-SOURCES = ["egt_game.cpp", "egt_kernels.hip", "egt_mixed.hip", "egt_solver.cpp", "egt_batch.cpp", "egt_abi.cpp", "egt_noalloc.hip"]
+SOURCES = ["egt_game.cpp", "egt_kernels.hip", "egt_product.hip", "egt_mixed.hip", "egt_solver.cpp", "egt_batch.cpp", "egt_abi.cpp", "egt_noalloc.hip", "egt_cfr.hip", "egt_fom.cpp"]
 
 FLAGS = [
     "--offload-arch=gfx950",
@@ -30,6 +30,10 @@ FLAGS = [
     "-Wno-unused-function",
     # no packed FP32 instructions anywhere in the device code
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # every product and sum rounded on its own: the kernels evaluate the
+    # paper's formulas in their written association (no fused multiply-adds
+    # unless a kernel asks for one)
+    "-ffp-contract=off",
 ]
 
 

@@ -217,10 +217,7 @@ int egt_best_response(const egt_game* g, int player, const double* grad, double*
 int egt_uniform(const egt_game* g, int player, double* strat_out, hipStream_t stream) {
   if (!g || bad_player(player) || !strat_out) return fail(EGT_EINVAL, "null argument or bad player");
   return guarded([&]() -> int {
-    int rc = ensure_workspace(g);
-    if (rc) return rc;
-    EGT_HIP(launch_uniform_qbar(g, player, g->ws.qb[player], stream));
-    EGT_HIP(launch_top_down(g, player, g->ws.qb[player], strat_out, nullptr, 0.0, nullptr, stream));
+    EGT_HIP(launch_uniform(g, player, strat_out, stream));
     return EGT_OK;
   });
 }

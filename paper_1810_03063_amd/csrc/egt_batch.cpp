@@ -32,6 +32,8 @@ int state_create_in(const egt_game* g, const egt_solve_opts* o, hipStream_t s, v
 int state_destroy(egt_state* st);
 int solve_loop(egt_state* st, hipStream_t s, const std::atomic<bool>* stop, bool* converged);
 int fill_result(egt_state* st, bool converged, double seconds, egt_result* res, hipStream_t s);
+int state_get(const egt_state* st, double* x, double* y, double* mu_x, double* mu_y, double* tau, int64_t* iters,
+              hipStream_t s);
 int64_t state_bytes(const egt_game* g, bool mixed);
 size_t state_host_doubles();
 }  // namespace egt
@@ -126,11 +128,9 @@ void run_slot(egt_batch* b, Slot& sl) {
   } else {
     res.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - sl.t0).count();
   }
-  if (st) {
-    (void)hipStreamSynchronize(sl.stream);
-    state_destroy(st);  // the memory stays with the batch
-  }
+  if (st) (void)hipStreamSynchronize(sl.stream);
   std::lock_guard<std::mutex> lk(b->mu);
+  sl.st = st;  // kept (in its arena range) until the slot is retired, for egt_batch_strategies
   sl.res = res;
   sl.status = rc;
   sl.phase = kDone;
@@ -204,6 +204,7 @@ int egt_batch_retire(egt_batch* b, int32_t slot) {
   std::lock_guard<std::mutex> lk(b->mu);
   Slot& sl = b->slots[(size_t)slot];
   if (sl.phase != kDone) return fail(EGT_EINVAL, "only a finished solve can be retired");
+  if (sl.st) state_destroy(sl.st);  // its memory stays with the batch
   arena_give(b, sl.off, sl.bytes);
   b->used -= sl.bytes;
   hipStream_t stream = sl.stream;
@@ -225,6 +226,10 @@ int egt_batch_destroy(egt_batch* b) {
   for (std::thread& t : b->workers) t.join();
   int rc = EGT_OK;
   for (Slot& sl : b->slots) {
+    if (sl.st) {
+      state_destroy(sl.st);
+      sl.st = nullptr;
+    }
     if (sl.stream) {
       const hipError_t e = hipStreamDestroy(sl.stream);
       if (e != hipSuccess && rc == EGT_OK) rc = hip_fail(e, "hipStreamDestroy");
@@ -296,6 +301,21 @@ int egt_batch_poll(egt_batch* b, int32_t slot, int32_t* done, int32_t* status, e
   if (done) *done = d ? 1 : 0;
   if (status) *status = d ? sl.status : EGT_OK;
   if (res && d) *res = sl.res;
+  return EGT_OK;
+}
+
+int egt_batch_strategies(egt_batch* b, int32_t slot, double* x, double* y, hipStream_t stream) {
+  if (!b || slot < 0 || slot >= (int32_t)b->slots.size()) return fail(EGT_EINVAL, "bad batch or slot");
+  egt_state* st = nullptr;
+  {
+    std::lock_guard<std::mutex> lk(b->mu);
+    const Slot& sl = b->slots[(size_t)slot];
+    if (sl.phase != kDone || !sl.st) return fail(EGT_EINVAL, "the slot holds no finished solve");
+    st = sl.st;
+  }
+  const int rc = state_get(st, x, y, nullptr, nullptr, nullptr, nullptr, stream);
+  if (rc) return rc;
+  EGT_HIP(hipStreamSynchronize(stream));
   return EGT_OK;
 }
 

@@ -27,7 +27,7 @@ namespace {
 thread_local std::string g_last_error;
 
 struct Act {
-  char kind;  // 'k' check, 'b' bet or raise, 'f' fold, 'c' call
+  char kind;  // 'k' check, 'b' bet or raise, 'f' fold, 'c' call, 'p' pass
   double amt; // acting player's river contribution after the action
   bool raise;
 };
@@ -50,6 +50,11 @@ struct Enumerator {
   std::vector<double> fracs;
   bool allin;
   int max_raises;
+  // situation-dependent sizes: per player and number of bets or raises so far (capped at 3)
+  bool situational = false;
+  std::vector<double> sfracs[2][4];
+  bool sallin[2][4] = {};
+  bool open_fold[2] = {false, false};
   std::vector<RawNode> nodes[2];
   std::vector<std::string> seq_key[2];
   std::vector<int> seq_node[2];
@@ -59,9 +64,22 @@ struct Enumerator {
     if (a.kind == 'k') return "k";
     if (a.kind == 'f') return "f";
     if (a.kind == 'c') return "c";
+    if (a.kind == 'p') return "p";
     char buf[64];
     std::snprintf(buf, sizeof buf, "b%lld", (long long)std::nearbyint(a.amt * 1000.0));
     return buf;
+  }
+
+  // pot fractions and all-in flag of player p after `bets` bets or raises on the river
+  void sizes(int p, int bets, const std::vector<double>** fr, bool* ai) const {
+    if (!situational) {
+      *fr = &fracs;
+      *ai = allin;
+      return;
+    }
+    const int d = std::min(bets, 3);
+    *fr = &sfracs[p][d];
+    *ai = sallin[p][d];
   }
 
   std::vector<Act> actions(const double c[2], int p, int raises) const {
@@ -70,10 +88,14 @@ struct Enumerator {
     const double pot_now = P + c[0] + c[1];
     std::vector<Act> acts;
     std::vector<double> amts;
+    const std::vector<double>* fr;
+    bool ai;
     if (to_call == 0.0) {
+      if (situational && open_fold[p]) acts.push_back({'f', c[p], false});
       acts.push_back({'k', c[p], false});
-      for (double f : fracs) amts.push_back(std::min(c[p] + f * pot_now, S));
-      if (allin) amts.push_back(S);
+      sizes(p, 0, &fr, &ai);
+      for (double f : *fr) amts.push_back(std::min(c[p] + f * pot_now, S));
+      if (ai) amts.push_back(S);
       std::sort(amts.begin(), amts.end());
       amts.erase(std::unique(amts.begin(), amts.end()), amts.end());
       for (double a : amts)
@@ -82,8 +104,9 @@ struct Enumerator {
       acts.push_back({'f', c[p], false});
       acts.push_back({'c', c[o], false});
       if (raises < max_raises && c[o] < S) {
-        for (double f : fracs) amts.push_back(std::min(c[o] + f * (pot_now + to_call), S));
-        if (allin) amts.push_back(S);
+        sizes(p, 1 + raises, &fr, &ai);  // facing the opening bet after `raises` raises
+        for (double f : *fr) amts.push_back(std::min(c[o] + f * (pot_now + to_call), S));
+        if (ai) amts.push_back(S);
         std::sort(amts.begin(), amts.end());
         amts.erase(std::unique(amts.begin(), amts.end()), amts.end());
         for (double a : amts)
@@ -91,6 +114,20 @@ struct Enumerator {
       }
     }
     return acts;
+  }
+
+  // A root decision of player p with the single action "p" at history hist;
+  // returns the raw index of its sequence.
+  int pass_node(const std::string& hist, int p, const double c[2]) {
+    RawNode nd;
+    nd.key = hist;
+    nd.parent_seq = -1;
+    nd.acts.push_back({'p', c[p], false});
+    nd.first_seq = (int)seq_key[p].size();
+    seq_key[p].push_back(hist + "/p");
+    seq_node[p].push_back((int)nodes[p].size());
+    nodes[p].push_back(nd);
+    return nd.first_seq;
   }
 
   // hist: public history key; last[p]: raw index of p's last sequence.
@@ -115,6 +152,8 @@ struct Enumerator {
       int nl[2] = {last[0], last[1]};
       nl[p] = first + (int)i;
       if (a.kind == 'f') {
+        // a fold before the opponent acted: the opponent's one-action pass first
+        if (nl[1 - p] < 0) nl[1 - p] = pass_node(h2, 1 - p, c);
         terms.push_back({0, {nl[0], nl[1]}, p == 0 ? (half + c[0]) : -(half + c[1])});
       } else if (a.kind == 'c') {
         terms.push_back({1, {nl[0], nl[1]}, half + c[1 - p]});
@@ -200,6 +239,13 @@ int finish_player(const Enumerator& en, int p, HostPlayer& hp, std::vector<int>&
     }
     if (par >= 0) kids_new[par].push_back(i);
   }
+  // a sequence's children (and the roots) in betting order, the order in which
+  // an action's child values are added to its gradient
+  for (auto& kids : kids_new) std::sort(kids.begin(), kids.end(), [&](int a, int b) { return order[a] < order[b]; });
+  std::sort(hp.roots.begin(), hp.roots.end(), [&](int a, int b) { return order[a] < order[b]; });
+  hp.seq_nact.assign(ns, 0);
+  for (int i = 0; i < nn; ++i)
+    for (int a = 0; a < hp.node_nact[i]; ++a) hp.seq_nact[hp.node_first_seq[i] + a] = hp.node_nact[i];
   hp.child_begin.assign(ns + 1, 0);
   for (int s = 0; s < ns; ++s) hp.child_begin[s + 1] = hp.child_begin[s] + (int)kids_new[s].size();
   hp.child.clear();
@@ -275,6 +321,16 @@ int build_game(const egt_game_desc* d, hipStream_t stream, egt_game** out) {
   for (int i = 0; i < d->n_bet_fracs; ++i)
     if (!(d->bet_fracs[i] > 0) || !std::isfinite(d->bet_fracs[i]))
       return fail(EGT_EINVAL, "bet fractions must be finite and > 0");
+  if (const egt_bet_abstraction* ab = d->abstraction) {
+    for (int p = 0; p < 2; ++p)
+      for (int k = 0; k < 4; ++k) {
+        if (ab->n_fracs[p][k] < 0 || ab->n_fracs[p][k] > kMaxActions || (ab->n_fracs[p][k] > 0 && !ab->fracs[p][k]))
+          return fail(EGT_EINVAL, "bad bet abstraction (0..16 fractions per situation)");
+        for (int i = 0; i < ab->n_fracs[p][k]; ++i)
+          if (!(ab->fracs[p][k][i] > 0) || !std::isfinite(ab->fracs[p][k][i]))
+            return fail(EGT_EINVAL, "bet fractions must be finite and > 0");
+      }
+  }
   std::set<std::vector<int>> seen;
   for (int h = 0; h < n; ++h) {
     std::vector<int> cs;
@@ -308,6 +364,16 @@ int build_game(const egt_game_desc* d, hipStream_t stream, egt_game** out) {
   en.fracs.assign(d->bet_fracs, d->bet_fracs + d->n_bet_fracs);
   en.allin = d->allin != 0;
   en.max_raises = d->max_raises;
+  if (const egt_bet_abstraction* ab = d->abstraction) {
+    en.situational = true;
+    for (int p = 0; p < 2; ++p) {
+      en.open_fold[p] = ab->open_fold[p] != 0;
+      for (int k = 0; k < 4; ++k) {
+        en.sfracs[p][k].assign(ab->fracs[p][k], ab->fracs[p][k] + ab->n_fracs[p][k]);
+        en.sallin[p][k] = ab->allin[p][k] != 0;
+      }
+    }
+  }
   const int none[2] = {-1, -1};
   const double c0[2] = {0.0, 0.0};
   en.walk("", c0, 0, 0, none);
@@ -398,26 +464,32 @@ int build_game(const egt_game_desc* d, hipStream_t stream, egt_game** out) {
   std::vector<std::vector<int>> lists(nc);
   for (int i = 0; i < n; ++i)
     for (int j = 0; j < cph; ++j) lists[d->hand_cards[perm[i] * cph + j]].push_back(i);
-  std::vector<int> card_begin(nc + 1, 0), card_hands;
-  for (int c = 0; c < nc; ++c) {
-    card_begin[c + 1] = card_begin[c] + (int)lists[c].size();
-    card_hands.insert(card_hands.end(), lists[c].begin(), lists[c].end());
-  }
-  std::vector<int4> ha(n), hb(n);
+  std::vector<int> card_begin(nc + 1, 0);
+  for (int c = 0; c < nc; ++c) card_begin[c + 1] = card_begin[c] + (int)lists[c].size();
+  // The product kernel's per-hand tables.  E lays the card lists end to end,
+  // card c's list at base_c = card_begin[c] + c followed by one slot for its
+  // total.  For the hand in slot i and each of its cards: the E index of the
+  // card's exclusive prefix at the start (lo) and end (hi) of i's tie group
+  // and of the card's total (len); and i's own position in the card's list
+  // (where the kernel scatters its reach).  Every index fits 16 bits.
+  std::vector<uint4> htab(n);
+  std::vector<unsigned> hpos(n);
   for (int i = 0; i < n; ++i) {
-    for (int j = 0; j < 2; ++j) {
-      int4 r = make_int4(0, 0, 0, 0);
-      if (j < cph) {
-        const int c = d->hand_cards[perm[i] * cph + j];
-        const auto& L = lists[c];
-        r.x = card_begin[c] + c;
-        r.y = (int)(std::lower_bound(L.begin(), L.end(), tie[i].x) - L.begin());
-        r.z = (int)(std::lower_bound(L.begin(), L.end(), tie[i].y) - L.begin());
-        r.w = (int)L.size();
-      }
-      (j == 0 ? ha : hb)[i] = r;
+    unsigned lo[2] = {0, 0}, hi[2] = {0, 0}, tot[2] = {0, 0}, pos[2] = {0, 0};
+    for (int j = 0; j < cph; ++j) {
+      const int c = d->hand_cards[perm[i] * cph + j];
+      const auto& L = lists[c];
+      const unsigned base = (unsigned)(card_begin[c] + c);
+      lo[j] = base + (unsigned)(std::lower_bound(L.begin(), L.end(), tie[i].x) - L.begin());
+      hi[j] = base + (unsigned)(std::lower_bound(L.begin(), L.end(), tie[i].y) - L.begin());
+      tot[j] = base + (unsigned)L.size();
+      pos[j] = base + (unsigned)(std::lower_bound(L.begin(), L.end(), i) - L.begin());
     }
+    htab[i] = make_uint4(lo[0] | (hi[0] << 16), tot[0] | (lo[1] << 16), hi[1] | (tot[1] << 16),
+                         (unsigned)tie[i].x | ((unsigned)tie[i].y << 16));
+    hpos[i] = pos[0] | (pos[1] << 16);
   }
+  if (card_begin[nc] + nc >= 65536) return fail(EGT_EINVAL, "too many card-list slots for 16-bit indices");
   // Z = sum over compatible deals of b1 b2
   std::vector<double> b[2];
   for (int p = 0; p < 2; ++p) {
@@ -455,7 +527,8 @@ int build_game(const egt_game_desc* d, hipStream_t stream, egt_game** out) {
     return off;
   };
   struct Offs {
-    size_t first, nact, beta, logn, spar, cbeg, child, tbeg, topp, tkind, tcoef, roots, belief, ftab, trec, anc, titems;
+    size_t first, nact, beta, logn, spar, cbeg, child, tbeg, topp, tkind, tcoef, roots, belief, ftab, trec, anc, titems,
+        snact;
   } po[2];
   for (int p = 0; p < 2; ++p) {
     HostPlayer& hp = g->hp[p];
@@ -476,18 +549,11 @@ int build_game(const egt_game_desc* d, hipStream_t stream, egt_game** out) {
     po[p].trec = add(hp.term_rec.data(), hp.term_rec.size() * sizeof(TermRec));
     po[p].anc = add(hp.anc.data(), hp.anc.size() * sizeof(int));
     po[p].titems = add(hp.term_items.data(), hp.term_items.size() * sizeof(TermItem));
+    po[p].snact = add(hp.seq_nact.data(), hp.seq_nact.size() * sizeof(int));
   }
   const size_t o_cbeg = add(card_begin.data(), card_begin.size() * sizeof(int));
-  const size_t o_chands = add(card_hands.data(), card_hands.size() * sizeof(int));
-  // card image for 16-byte staging: card_begin padded to 4 ints, then card_hands padded to 4 ints
-  const int chand_off = (nc + 1 + 3) / 4 * 4;
-  std::vector<int> card_img((size_t)chand_off + (card_hands.size() + 3) / 4 * 4, 0);
-  std::copy(card_begin.begin(), card_begin.end(), card_img.begin());
-  std::copy(card_hands.begin(), card_hands.end(), card_img.begin() + chand_off);
-  const size_t o_cimg = add(card_img.data(), card_img.size() * sizeof(int));
-  const size_t o_ha = add(ha.data(), ha.size() * sizeof(int4));
-  const size_t o_hb = add(hb.data(), hb.size() * sizeof(int4));
-  const size_t o_tie = add(tie.data(), tie.size() * sizeof(int2));
+  const size_t o_htab = add(htab.data(), htab.size() * sizeof(uint4));
+  const size_t o_hpos = add(hpos.data(), hpos.size() * sizeof(unsigned));
 
   std::vector<unsigned char> staging(total, 0);
   for (const Piece& pc : pieces)
@@ -495,6 +561,10 @@ int build_game(const egt_game_desc* d, hipStream_t stream, egt_game** out) {
   EGT_HIP(hipGetDevice(&g->device));
   EGT_HIP(hipDeviceGetAttribute(&g->n_cu, hipDeviceAttributeMultiprocessorCount, g->device));
   if (g->n_cu < 1) g->n_cu = 1;
+  EGT_HIP(hipDeviceGetAttribute(&g->lds_per_block, hipDeviceAttributeMaxSharedMemoryPerBlock, g->device));
+  EGT_HIP(hipDeviceGetAttribute(&g->lds_per_cu, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, g->device));
+  if (g->lds_per_block < 64 * 1024) g->lds_per_block = 64 * 1024;
+  if (g->lds_per_cu < g->lds_per_block) g->lds_per_cu = g->lds_per_block;
   void* dev = nullptr;
   hipError_t e = hipMalloc(&dev, total);
   if (e != hipSuccess) return fail(EGT_ENOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
@@ -534,6 +604,7 @@ int build_game(const egt_game_desc* d, hipStream_t stream, egt_game** out) {
     dp.term_stride = std::max(1, hp.max_terms_per_seq);
     dp.n_items = (int)hp.term_items.size();
     dp.term_items = dp.n_items > 0 ? (const TermItem*)at(po[p].titems) : nullptr;
+    dp.seq_nact = (const int*)at(po[p].snact);
   }
   DHands& dh = g->dh;
   dh.n = n;
@@ -541,14 +612,9 @@ int build_game(const egt_game_desc* d, hipStream_t stream, egt_game** out) {
   dh.cph = cph;
   dh.n_cards = nc;
   dh.n_card_slots = card_begin[nc] + nc;
-  dh.card_img = at(o_cimg);
-  dh.card_img16 = (int)(card_img.size() / 4);
-  dh.chand_off = chand_off;
   dh.card_begin = (const int*)at(o_cbeg);
-  dh.card_hands = (const int*)at(o_chands);
-  dh.ha = (const int4*)at(o_ha);
-  dh.hb = (const int4*)at(o_hb);
-  dh.tie = (const int2*)at(o_tie);
+  dh.htab = (const uint4*)at(o_htab);
+  dh.hpos = (const unsigned*)at(o_hpos);
   dh.invZ = 1.0 / Z;
   *out = guard.release();
   return EGT_OK;

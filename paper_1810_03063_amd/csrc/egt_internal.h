@@ -15,7 +15,6 @@ namespace egt {
 constexpr int kMaxActions = 16;  // actions per decision node
 constexpr int kMaxDepth = 16;    // sequences on a root-to-leaf chain of one player (and levels)
 constexpr int kMaxTrees = 4;     // trees evaluated by one bottom-up launch
-constexpr size_t kGradLdsLimit = 64 * 1024;   // LDS budget of one product block
 constexpr size_t kFusedLdsLimit = 64 * 1024;  // LDS budget of one single-launch pass block
 
 // Table image of one player's treeplex for the single-launch pass, staged
@@ -106,14 +105,23 @@ struct DPlayer {
   const TermItem* term_items;  // [n_items] when every sequence has at most two terminals, else null
   int n_items;
   int fused_tab16;             // its size in 16-byte units
+  const int* seq_nact;         // [n_seq] number of actions of the sequence's decision node
 };
 
 // Hands in strength-ascending slot order, with the card tables the O(n) leaf
-// evaluation needs.  For a hand in slot i:
-//   tie group [glo, ghi): slots with the same strength;
-//   for each of its cards c: base = card_begin[c] + c (start of the card's
-//   prefix array), len = hands holding c, lo / hi = how many of those hands sit
-//   before glo / ghi in slot order.
+// evaluation needs.  The card lists (the strength-ordered slots holding each
+// card) are laid end to end, card c's at base_c = card_begin[c] + c followed
+// by one slot for its total: n_card_slots slots in all.  For a hand in slot i
+// with tie group [glo, ghi) (the slots of equal strength), htab[i] holds
+// 16-bit fields
+//   x = lo_a | hi_a << 16,  y = tot_a | lo_b << 16,  z = hi_b | tot_b << 16,
+//   w = glo | ghi << 16,
+// where lo_c / hi_c are the E indices of the first hand of card c's list at or
+// after glo / ghi in slot order (so the exclusive per-card prefix there is the
+// mass of card c's hands below the tie group / up to its end), tot_c is the E
+// index of card c's total, and hpos[i] = pos_a | pos_b << 16 are the E indices
+// of i's own entries in the two lists.  Card b's fields are 0 for one-card
+// hands.
 struct DHands {
   int n;
   int ld;
@@ -121,13 +129,8 @@ struct DHands {
   int n_cards;
   int n_card_slots;            // card_begin[n_cards] + n_cards
   const int* card_begin;       // [n_cards + 1]
-  const int* card_hands;       // slots holding each card, ascending
-  const int4* ha;              // [n] {base, lo, hi, len} of the first card
-  const int4* hb;              // [n] same for the second card (unused when cph == 1)
-  const int2* tie;             // [n] {glo, ghi}
-  const void* card_img;        // card_begin (padded to 4 ints) then card_hands, for 16-byte staging
-  int card_img16;              // its size in 16-byte units
-  int chand_off;               // offset of card_hands in the image, in ints
+  const uint4* htab;           // [n]
+  const unsigned* hpos;        // [n]
   double invZ;                 // 1 / sum of b1 b2 over compatible deals
 };
 
@@ -204,6 +207,7 @@ struct HostPlayer {
   std::vector<TermRec> term_rec;         // [n_seq][max(1, max_terms_per_seq)]
   std::vector<TermItem> term_items;      // work items of the looping product kernel (at most two terminals each)
   std::vector<int> anc;                  // [n_seq][kMaxDepth]
+  std::vector<int> seq_nact;             // [n_seq] actions of the sequence's node
   std::vector<std::string> seq_keys;
 };
 
@@ -243,6 +247,8 @@ struct MixedTables {
 struct egt_game {
   int n = 0, ld = 0, cph = 0, n_cards = 0;
   int n_cu = 256;  // compute units of the game's device
+  int lds_per_block = 64 * 1024;  // the device's largest LDS allocation of one block
+  int lds_per_cu = 64 * 1024;     // LDS of one compute unit
   double pot = 0, stack = 0, Z = 0;
   int64_t n_fold = 0, n_show = 0;
   egt::HostPlayer hp[2];
@@ -290,8 +296,9 @@ hipError_t launch_sum_partials(const egt_game* g, const double* partial, int cou
 hipError_t launch_top_down(const egt_game* g, int player, const void* QB, void* q_out, const void* x_prev,
                            double tau, void* comb_out, hipStream_t s, Prec prec = kF64);
 
-// QB = 1 / (number of actions) everywhere (the uniform point's q_bar).
-hipError_t launch_uniform_qbar(const egt_game* g, int player, double* QB, hipStream_t s);
+// The uniform point x_omega: every sequence's mass is its parent's divided by
+// the number of actions of its node (written 0 in the row padding).
+hipError_t launch_uniform(const egt_game* g, int player, double* out, hipStream_t s);
 
 // out = a * X + b * Y over count elements (Y may be null).
 hipError_t launch_axpby(int64_t count, double a, const void* X, double b, const void* Y, void* out, hipStream_t s,

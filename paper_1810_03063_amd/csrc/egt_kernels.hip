@@ -1,7 +1,5 @@
 // HIP kernels of the EGT hot path for gfx950 (CDNA4, 64-lane wavefronts).
 //
-//  * gradient_kernel   : payoff products A y / A^T x (Section 2's gradient
-//    operators) on fold and showdown terminals, O(n) per terminal;
 //  * sbr_fused_kernel  : for trees whose tables fit in LDS, a whole smoothed
 //    best response (Section 4, Eq. 4 and the leaf / internal-simplex
 //    derivation) in one launch: bottom-up over every level, root-value
@@ -30,306 +28,33 @@ namespace egt {
 
 namespace {
 
-constexpr int kGroupThreads = 256;     // one wave group evaluates one terminal
-constexpr int kMaxHandsPerThread = 8;  // n <= 2048 = 256 threads x 8 contiguous hands
 constexpr int kPassThreads = 64;       // per-level pass: one wavefront per (node, 64 hands)
 constexpr int kInternalWaves = 8;       // level path: wavefronts per node block (4 blocks fill a CU's 32 wave slots)
 constexpr int kFusedSlots = 64;        // fused pass: node slots per block (x HB hands per slot)
 
-// Explicit fused multiply-adds for the expressions that the level-path kernel
-// variants share, so that every variant rounds them identically.
-__device__ inline double fmadd(double a, double b, double c) { return __builtin_fma(a, b, c); }
-__device__ inline float fmadd(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
-
-__device__ inline double wave_inclusive_scan(double x, int lane) {
-#pragma unroll
-  for (int off = 1; off < 64; off <<= 1) {
-    const double y = __shfl_up(x, off, 64);
-    if (lane >= off) x += y;
-  }
-  return x;
+// The per-information-set arithmetic of Section 4's smoothed best response in
+// the association of its formulas, every operation rounded on its own (the
+// library is built without floating-point contraction), so that every pass
+// form below rounds exactly like a plain evaluation of those formulas:
+//   weight of action a   w_a = exp((m - g~_a) / (mu beta)), m = min_a g~_a,
+//                        so the largest weight is exactly 1;
+//   node value           V = (m - mu beta log S) + mu beta log n, S = sum_a w_a
+//                        added in action order;
+//   local probability    q_bar_a = w_a / S.
+// The precision form takes the exponential in FP32 (of the FP64 argument)
+// and keeps S, the logarithm and V in FP64.
+template <class TG>
+__device__ inline double lse_weight(double m, double g, double temp) {
+  if constexpr (std::is_same<TG, float>::value)
+    return (double)expf((float)((m - g) / temp));
+  else
+    return exp((m - g) / temp);
 }
-
-// ---------------------------------------------------------------------------
-// Payoff product.  One block per output sequence s of `own`; the block holds
-// `groups` wave groups of 256 threads and group g evaluates the terminals
-// g, g + groups, ... of s's fixed-stride terminal list concurrently with the
-// others (every table the block needs is requested at its start).  For a
-// terminal z the opponent's reach r(h') = b_o(h') v_o[sigma_o(z)][h'] is
-// staged in LDS, each thread keeping its contiguous chunk of hands in
-// registers; then
-//   fold:     sum of r over compatible h' = T - C[a] - C[b] + r(h)
-//             (T total, C[c] the mass of hands holding card c; the hand's own
-//             slot holds both of its cards and is added back once);
-//   showdown: (compatible mass stronger) - (compatible mass weaker), from the
-//             exclusive prefix sum over strength order (built in place over r)
-//             and, per card, over the strength-ordered hands holding that card
-//             (one thread walks one card's list); a tie group [glo, ghi)
-//             counts as neither.
-// out[s][h] = b_own(h) / Z * sum_z coef(z) * op_z(h), the showdown op negated
-// for player 2 (its gradient sums over player 1's hands).  Group partial sums
-// are combined in a fixed order, so the result is bitwise repeatable.  When
-// the blocks loop over many sequences, they walk work items instead
-// (TermItem): a two-terminal sequence still takes both groups, but two
-// one-terminal sequences share a block, one per group, so no group idles.
-// ---------------------------------------------------------------------------
-template <class TV, class TO>
-struct GradArgs {
-  DPlayer own;
-  const double* b_opp;
-  DHands H;
-  const TV* v_opp;
-  TO* out;
-  double show_sign;
-  int groups;
-  int fold_only;  // skip showdown terminals (their part is added by the BF16 GEMM)
-  const TermItem* items;  // work items instead of whole sequences (two groups, blocks looping), or null
-  int n_items;
-};
-
-// HPT = hands per thread (n <= 256 HPT).  MINW = the waves per SIMD the
-// register allocation must leave room for: 4 lets two blocks share a compute
-// unit (a few per-hand values then live in scratch between uses), which pays
-// when each block loops over many sequences.
-template <class TV, class TO, int HPT, int MINW>
-__global__ __launch_bounds__(2 * kGroupThreads, MINW) void gradient_kernel(GradArgs<TV, TO> a) {
-  constexpr int kCU = 2;  // card-image loads per thread in the first batch
-  constexpr int kWalk = MINW > 1 ? 4 : 8;  // LDS loads in flight per card walk step (fewer under the VGPR cap)
-  extern __shared__ __align__(16) double lds[];
-  __shared__ double wave_total[2][kGroupThreads / 64];
-  const int n = a.H.n, ld = a.H.ld;
-  const int groups = a.groups;
-  const int per_group = (n + 1) + a.H.n_card_slots;
-  const int tid = threadIdx.x;
-  const int grp = tid / kGroupThreads, gt = tid % kGroupThreads;
-  const int lane = tid & 63, wig = gt >> 6;
-  double* R = lds + (size_t)grp * per_group;  // r, then its exclusive prefix in place [n + 1]
-  double* Pc = R + (n + 1);                   // per-card exclusive prefixes [n_card_slots]
-  int* cbeg = (int*)(lds + (size_t)(groups * per_group + 1) / 2 * 2);  // 16-byte aligned card image
-  const int* chand = cbeg + a.H.chand_off;
-
-  const int MT = a.own.term_stride, n_seq = a.own.n_seq;
-  const int chunk = (n + kGroupThreads - 1) / kGroupThreads;
-  const int beg = min(gt * chunk, n), end = min(beg + chunk, n), cnt = end - beg;
-  const TermRec none{-1, -1, 0.0};
-
-  // Everything the block reads from global memory is requested up front, so
-  // the loads overlap: this group's first terminal, the hand tables and own
-  // beliefs of this thread's chunk, the opponent's prior at the strided
-  // positions this thread stages, and the card image (into LDS).  The tables
-  // stay for every sequence the block then processes.
-  // A work unit w is sequence w (both groups add into its row when there are
-  // two groups), or work item w (each group its own (sequence, terminal)).
-  const bool by_items = a.items != nullptr;
-  const int n_work = by_items ? a.n_items : n_seq;
-  auto work_of = [&](int w, TermRec& t, int& so, bool& comb) {
-    if (by_items) {
-      const TermItem& it = a.items[w];
-      t = it.t[grp];
-      so = it.seq[grp];
-      comb = it.seq[0] == it.seq[1];
-    } else {
-      t = grp < MT ? a.own.term_rec[(size_t)w * MT + grp] : none;
-      so = w;
-      comb = groups == 2;
-    }
-  };
-  TermRec tr = none;
-  int s_out = -1;       // the row this group's result goes to
-  bool combine = false;  // group 1's result is added to group 0's (block-uniform)
-  if ((int)blockIdx.x < n_work) work_of((int)blockIdx.x, tr, s_out, combine);
-  int4 HA[HPT], HB[HPT];
-  int2 TG[HPT];
-  double bown[HPT];
-#pragma unroll
-  for (int k = 0; k < HPT; ++k) {
-    HA[k] = make_int4(0, 0, 0, 0);
-    HB[k] = make_int4(0, 0, 0, 0);
-    TG[k] = make_int2(0, 0);
-    bown[k] = 0.0;
-    if (k < cnt) {
-      HA[k] = a.H.ha[beg + k];
-      if (a.H.cph == 2) HB[k] = a.H.hb[beg + k];
-      TG[k] = a.H.tie[beg + k];
-      bown[k] = a.own.belief[beg + k];
-    }
-  }
-  {
-    const uint4* img = (const uint4*)a.H.card_img;
-    uint4* dst = (uint4*)cbeg;
-    const int C16 = a.H.card_img16;
-    uint4 cv[kCU];
-#pragma unroll
-    for (int u = 0; u < kCU; ++u) {
-      const int i = u * (int)blockDim.x + tid;
-      cv[u] = i < C16 ? img[i] : make_uint4(0u, 0u, 0u, 0u);
-    }
-#pragma unroll
-    for (int u = 0; u < kCU; ++u) {
-      const int i = u * (int)blockDim.x + tid;
-      if (i < C16) dst[i] = cv[u];
-    }
-    for (int i = kCU * (int)blockDim.x + tid; i < C16; i += blockDim.x) dst[i] = img[i];
-  }
-  const int rounds = by_items ? 1 : (MT + groups - 1) / groups;
-  for (int w = blockIdx.x; w < n_work; w += gridDim.x) {
-  // the next work unit's first terminal, requested while this one runs
-  const int w_next = w + (int)gridDim.x;
-  TermRec tr_next = none;
-  int s_next = -1;
-  bool comb_next = false;
-  if (w_next < n_work) work_of(w_next, tr_next, s_next, comb_next);
-  double acc[HPT];
-#pragma unroll
-  for (int k = 0; k < HPT; ++k) acc[k] = 0.0;
-  for (int rd = 0; rd < rounds; ++rd) {
-    const int j = rd * groups + grp;
-    if (rd > 0) tr = j < MT ? a.own.term_rec[(size_t)w * MT + j] : none;  // sequence units only
-    // uniform within a group
-    const bool active = tr.kind >= 0 && !(a.fold_only && tr.kind != 0);
-    const int kind = tr.kind;
-    const double coef = tr.coef;
-    if (active) {
-      const TV* v = tr.opp >= 0 ? a.v_opp + (size_t)tr.opp * ld : nullptr;
-      // the opponent's prior is read with the row (it stays in the caches)
-      double vv[HPT], bo[HPT];
-#pragma unroll
-      for (int k = 0; k < HPT; ++k) {
-        const int i = gt + k * kGroupThreads;
-        vv[k] = (v && i < n) ? (double)v[i] : 1.0;
-        bo[k] = i < n ? a.b_opp[i] : 0.0;
-      }
-#pragma unroll
-      for (int k = 0; k < HPT; ++k) {
-        const int i = gt + k * kGroupThreads;
-        if (i < n) R[i] = bo[k] * vv[k];
-      }
-    }
-    __syncthreads();
-    double rloc[HPT];
-#pragma unroll
-    for (int k = 0; k < HPT; ++k) rloc[k] = 0.0;
-    if (active) {
-#pragma unroll
-      for (int k = 0; k < HPT; ++k) rloc[k] = k < cnt ? R[beg + k] : 0.0;
-      // Per-card exclusive prefixes over the card's strength-ordered hands:
-      // four lanes per card, each a contiguous quarter of the list; the
-      // quarter offsets are added in a fixed order.
-      const int sub = gt & 3;
-      for (int c = gt >> 2; c - (gt >> 2) < a.H.n_cards; c += kGroupThreads / 4) {
-        const bool valid = c < a.H.n_cards;
-        const int cb = valid ? cbeg[c] : 0;
-        const int len = valid ? cbeg[c + 1] - cb : 0;
-        const int base = cb + c;
-        const int qlen = (len + 3) >> 2;
-        const int lo = min(sub * qlen, len), hi = min(lo + qlen, len);
-        double part = 0.0;
-        int k = lo;
-        for (; k + kWalk <= hi; k += kWalk) {
-          double v[kWalk];
-#pragma unroll
-          for (int j = 0; j < kWalk; ++j) v[j] = R[chand[cb + k + j]];
-#pragma unroll
-          for (int j = 0; j < kWalk; ++j) part += v[j];
-        }
-        for (; k < hi; ++k) part += R[chand[cb + k]];
-        const int l0 = lane & ~3;
-        const double p0 = __shfl(part, l0, 64), p1 = __shfl(part, l0 + 1, 64), p2 = __shfl(part, l0 + 2, 64);
-        double run = sub == 0 ? 0.0 : sub == 1 ? p0 : sub == 2 ? p0 + p1 : (p0 + p1) + p2;
-        k = lo;
-        for (; k + kWalk <= hi; k += kWalk) {
-          double v[kWalk];
-#pragma unroll
-          for (int j = 0; j < kWalk; ++j) v[j] = R[chand[cb + k + j]];
-#pragma unroll
-          for (int j = 0; j < kWalk; ++j) {
-            Pc[base + k + j] = run;
-            run += v[j];
-          }
-        }
-        for (; k < hi; ++k) {
-          Pc[base + k] = run;
-          run += R[chand[cb + k]];
-        }
-        if (valid && sub == 3) Pc[base + len] = run;
-      }
-    }
-    __syncthreads();  // the card walks have finished reading r
-    double local = 0.0, incl = 0.0;
-    if (active) {
-#pragma unroll
-      for (int k = 0; k < HPT; ++k) local += rloc[k];
-      incl = wave_inclusive_scan(local, lane);
-      if (lane == 63) wave_total[grp][wig] = incl;
-    }
-    __syncthreads();
-    if (active) {
-      double run = incl - local;
-      for (int w = 0; w < wig; ++w) run += wave_total[grp][w];
-#pragma unroll
-      for (int k = 0; k < HPT; ++k) {
-        if (k < cnt) {
-          R[beg + k] = run;
-          run += rloc[k];
-        }
-      }
-      if (cnt > 0 && end == n) R[n] = run;
-    }
-    __syncthreads();
-    if (active) {
-      const double T = R[n];
-#pragma unroll
-      for (int k = 0; k < HPT; ++k) {
-        if (k < cnt) {
-          const int4 A = HA[k];
-          double op;
-          if (kind == 0) {
-            op = T - Pc[A.x + A.w];
-            if (a.H.cph == 2) op = op - Pc[HB[k].x + HB[k].w] + rloc[k];
-          } else {
-            const int2 tg = TG[k];
-            double weaker = R[tg.x] - Pc[A.x + A.y];
-            double stronger = (T - R[tg.y]) - (Pc[A.x + A.w] - Pc[A.x + A.z]);
-            if (a.H.cph == 2) {
-              const int4 B = HB[k];
-              weaker -= Pc[B.x + B.y];
-              stronger -= Pc[B.x + B.w] - Pc[B.x + B.z];
-            }
-            op = a.show_sign * (stronger - weaker);
-          }
-          acc[k] += coef * op;
-        }
-      }
-    }
-    __syncthreads();  // the next round rewrites R and Pc
-  }
-  if (combine) {
-    if (grp == 1) {
-#pragma unroll
-      for (int k = 0; k < HPT; ++k)
-        if (k < cnt) R[beg + k] = acc[k];
-    }
-    __syncthreads();
-    if (grp == 0) {
-      const double* R1 = lds + per_group;
-#pragma unroll
-      for (int k = 0; k < HPT; ++k)
-        if (k < cnt) acc[k] += R1[beg + k];
-    }
-  }
-  if ((!combine || grp == 0) && s_out >= 0) {
-    TO* row = a.out + (size_t)s_out * ld;
-#pragma unroll
-    for (int k = 0; k < HPT; ++k)
-      if (k < cnt) row[beg + k] = (TO)(acc[k] * (bown[k] * a.H.invZ));
-    for (int i = n + gt; i < ld; i += kGroupThreads) row[i] = (TO)0;
-  }
-  tr = tr_next;
-  s_out = s_next;
-  combine = comb_next;
-  __syncthreads();  // the next unit rewrites R of both groups
-  }
+__device__ inline double lse_value(double m, double temp, double sum, double logn) {
+  return (m - temp * log(sum)) + temp * logn;
 }
+// cA a + cB b (the mixed gradient of the prox, or a single scaled gradient).
+__device__ inline double lin2(double cA, double a, double cB, double b) { return cA * a + cB * b; }
 
 // ---------------------------------------------------------------------------
 // One information set (node v, hand h) of a bottom-up pass:
@@ -340,8 +65,9 @@ __global__ __launch_bounds__(2 * kGroupThreads, MINW) void gradient_kernel(GradA
 //   best response (mu = 0): V[v] = min_a g~_a.
 // The action with the smallest g~ has the largest q_bar (weight exactly 1), so
 // V is the value g~_i + temp log q_bar_i + temp log n_v at that action, and
-// every exponent is <= 0.  Both pass forms below evaluate exactly this, with
-// 1 / temp taken as (1 / mu) (1 / beta_v).
+// every exponent is <= 0.  Both pass forms below evaluate exactly this through
+// lse_weight / lse_value, the children of an action added in betting order
+// (the order of the child CSR).
 // ---------------------------------------------------------------------------
 
 // ---------------------------------------------------------------------------
@@ -386,10 +112,10 @@ __device__ inline int xcd_spread(int L, int total) {
 // One (node, hand) task of the node phase: g~ of the node's actions in Gl,
 // value to the node's slot in Vs, q_bar to Ql (smoothed, want_q).  Every
 // action's g~ is read up front (indices clamped into the node), so the reads
-// overlap.  temp = mu beta_v; the exponent uses (1 / mu) (1 / beta_v).
+// overlap.  temp = mu beta_v.
 template <class TG, int HB>
 __device__ __forceinline__ void fused_node(const int4* rec, const double2* prm, const double* Gl, double* Ql,
-                                           double* Vs, int v, int hl, double mu, double inv_mu, bool want_q) {
+                                           double* Vs, int v, int hl, double mu, bool want_q) {
   const int4 r = rec[v];
   const int s0 = r.x, na = r.y;
   double g[kMaxActions];
@@ -405,32 +131,19 @@ __device__ __forceinline__ void fused_node(const int4* rec, const double2* prm, 
   }
   const double2 p0 = prm[2 * v], p1 = prm[2 * v + 1];  // {beta, 1 / beta}, {log n_v, 0}
   const double temp = mu * p0.x;
-  const double inv_temp = inv_mu * p0.y;
   double sum = 0.0;
-  if constexpr (std::is_same<TG, float>::value) {
-    // precision form: FP32 exponentials, FP64 normaliser and value
 #pragma unroll
-    for (int k = 0; k < kMaxActions; ++k) {
-      if (k < na) {
-        g[k] = (double)expf((float)((m - g[k]) * inv_temp));
-        sum += g[k];
-      }
-    }
-  } else {
-#pragma unroll
-    for (int k = 0; k < kMaxActions; ++k) {
-      if (k < na) {
-        g[k] = exp((m - g[k]) * inv_temp);
-        sum += g[k];
-      }
+  for (int k = 0; k < kMaxActions; ++k) {
+    if (k < na) {
+      g[k] = lse_weight<TG>(m, g[k], temp);
+      sum += g[k];
     }
   }
-  Vs[r.z * HB + hl] = (m - temp * log(sum)) + temp * p1.x;
+  Vs[r.z * HB + hl] = lse_value(m, temp, sum, p1.x);
   if (want_q) {
-    const double inv_sum = 1.0 / sum;
 #pragma unroll
     for (int k = 0; k < kMaxActions; ++k)
-      if (k < na) Ql[(s0 + k) * HB + hl] = (double)(TG)(g[k] * inv_sum);
+      if (k < na) Ql[(s0 + k) * HB + hl] = (double)(TG)(g[k] / sum);
   }
 }
 
@@ -500,8 +213,7 @@ __global__ __launch_bounds__(kFusedSlots * HB) void sbr_fused_kernel(FusedArgs a
     for (int u = 0; u < kU; ++u) {
       const int i = base + u * kThreads + tid;
       if (i < SH) {
-        double x = t.cA * va[u];
-        if (gB) x += t.cB * vb[u];
+        const double x = gB ? lin2(t.cA, va[u], t.cB, vb[u]) : t.cA * va[u];
         Gl[i] = x;
         if (want_x) Xl[i] = vx[u];
         if (g_out) g_out[(size_t)(i / HB) * ld + h0 + i % HB] = (TG)(x * e.g_scale);  // 0 in the padding
@@ -521,7 +233,6 @@ __global__ __launch_bounds__(kFusedSlots * HB) void sbr_fused_kernel(FusedArgs a
   // 2. bottom-up
   const bool want_q = (e.q_out || e.comb_out) && t.mu > 0.0;
   const double mu = t.mu;
-  const double inv_mu = mu > 0.0 ? 1.0 / mu : 0.0;
   for (int l = 0; l < t.n_levels; ++l) {
     if (l > 0) {
       const int sb0 = t.seq_level_begin[l], cnt = (t.seq_level_begin[l + 1] - sb0) * HB;
@@ -547,7 +258,7 @@ __global__ __launch_bounds__(kFusedSlots * HB) void sbr_fused_kernel(FusedArgs a
     const int nb0 = t.level_begin[l], cnt = (t.level_begin[l + 1] - nb0) * HB;
     for (int i = tid; i < cnt; i += kThreads) {
       const int v = nb0 + i / HB, hl = i % HB;
-      if (h0 + hl < n) fused_node<TG, HB>(rec, prm, Gl, Ql, Vs, v, hl, mu, inv_mu, want_q);
+      if (h0 + hl < n) fused_node<TG, HB>(rec, prm, Gl, Ql, Vs, v, hl, mu, want_q);
     }
     __syncthreads();
   }
@@ -626,8 +337,7 @@ __global__ __launch_bounds__(kPassThreads) void bottom_up_level_kernel(PassSet a
   for (int j = 0; j < kMaxActions; ++j) {
     if (j < na) {
       const size_t idx = (size_t)(s0 + j) * ld + h;
-      double x = t.cA * (double)gA[idx];
-      if (gB) x = fmadd(t.cB, (double)gB[idx], x);
+      double x = gB ? lin2(t.cA, (double)gA[idx], t.cB, (double)gB[idx]) : t.cA * (double)gA[idx];
       if (g_out) g_out[idx] = (TG)(x * t.g_scale);
       const int c1 = cbeg[s0 + j + 1];
       for (int c = cbeg[s0 + j]; c < c1; ++c) x += t.V[(size_t)c * ld + h];
@@ -640,31 +350,19 @@ __global__ __launch_bounds__(kPassThreads) void bottom_up_level_kernel(PassSet a
     return;
   }
   const double temp = t.mu * p0.x;
-  const double inv_temp = (1.0 / t.mu) * p0.y;
   double sum = 0.0;
-  if constexpr (std::is_same<TG, float>::value) {
 #pragma unroll
-    for (int j = 0; j < kMaxActions; ++j) {
-      if (j < na) {
-        g[j] = (double)expf((float)((m - g[j]) * inv_temp));
-        sum += g[j];
-      }
-    }
-  } else {
-#pragma unroll
-    for (int j = 0; j < kMaxActions; ++j) {
-      if (j < na) {
-        g[j] = exp((m - g[j]) * inv_temp);
-        sum += g[j];
-      }
+  for (int j = 0; j < kMaxActions; ++j) {
+    if (j < na) {
+      g[j] = lse_weight<TG>(m, g[j], temp);
+      sum += g[j];
     }
   }
-  t.V[(size_t)r.z * ld + h] = fmadd(temp, p1.x, fmadd(-temp, log(sum), m));
+  t.V[(size_t)r.z * ld + h] = lse_value(m, temp, sum, p1.x);
   if (t.QB) {
-    const double inv_sum = 1.0 / sum;
 #pragma unroll
     for (int j = 0; j < kMaxActions; ++j)
-      if (j < na) ((TG*)t.QB)[(size_t)(s0 + j) * ld + h] = (TG)(g[j] * inv_sum);
+      if (j < na) ((TG*)t.QB)[(size_t)(s0 + j) * ld + h] = (TG)(g[j] / sum);
   }
 }
 
@@ -717,8 +415,8 @@ __global__ __launch_bounds__(kPassThreads) void bottom_up_leaf_pair_kernel(PassS
       double x0 = t.cA * (double)A.x, x1 = t.cA * (double)A.y;
       if (gB) {
         const V2 B = *(const V2*)(gB + idx);
-        x0 = fmadd(t.cB, (double)B.x, x0);
-        x1 = fmadd(t.cB, (double)B.y, x1);
+        x0 = lin2(t.cA, (double)A.x, t.cB, (double)B.x);
+        x1 = lin2(t.cA, (double)A.y, t.cB, (double)B.y);
       }
       if (g_out) store_pair(g_out + idx, x0 * t.g_scale, x1 * t.g_scale, both);
       g0[j] = x0;
@@ -733,29 +431,21 @@ __global__ __launch_bounds__(kPassThreads) void bottom_up_leaf_pair_kernel(PassS
     return;
   }
   const double temp = t.mu * p0.x;
-  const double inv_temp = (1.0 / t.mu) * p0.y;
   double sum0 = 0.0, sum1 = 0.0;
 #pragma unroll
   for (int j = 0; j < kMaxActions; ++j) {
     if (j < na) {
-      if constexpr (std::is_same<TG, float>::value) {
-        g0[j] = (double)expf((float)((m0 - g0[j]) * inv_temp));
-        g1[j] = (double)expf((float)((m1 - g1[j]) * inv_temp));
-      } else {
-        g0[j] = exp((m0 - g0[j]) * inv_temp);
-        g1[j] = exp((m1 - g1[j]) * inv_temp);
-      }
+      g0[j] = lse_weight<TG>(m0, g0[j], temp);
+      g1[j] = lse_weight<TG>(m1, g1[j], temp);
       sum0 += g0[j];
       sum1 += g1[j];
     }
   }
-  store_pair(Vrow, fmadd(temp, p1.x, fmadd(-temp, log(sum0), m0)), fmadd(temp, p1.x, fmadd(-temp, log(sum1), m1)),
-             both);
+  store_pair(Vrow, lse_value(m0, temp, sum0, p1.x), lse_value(m1, temp, sum1, p1.x), both);
   if (t.QB) {
-    const double inv0 = 1.0 / sum0, inv1 = 1.0 / sum1;
 #pragma unroll
     for (int j = 0; j < kMaxActions; ++j)
-      if (j < na) store_pair((TG*)t.QB + (size_t)(s0 + j) * ld + h, g0[j] * inv0, g1[j] * inv1, both);
+      if (j < na) store_pair((TG*)t.QB + (size_t)(s0 + j) * ld + h, g0[j] / sum0, g1[j] / sum1, both);
   }
 }
 
@@ -818,12 +508,13 @@ __global__ __launch_bounds__(kPassThreads * kMaxActions) void bottom_up_internal
     const size_t idx = (size_t)(s0 + jj) * ld + h;
     double x0, x1, b0, b1;
     load2((const TG*)t.gA + idx, x0, x1);
-    x0 = t.cA * x0;
-    x1 = t.cA * x1;
     if (t.gB) {
       load2((const TG*)t.gB + idx, b0, b1);
-      x0 = fmadd(t.cB, b0, x0);
-      x1 = fmadd(t.cB, b1, x1);
+      x0 = lin2(t.cA, x0, t.cB, b0);
+      x1 = lin2(t.cA, x1, t.cB, b1);
+    } else {
+      x0 = t.cA * x0;
+      x1 = t.cA * x1;
     }
     if (t.g_out) store2((TG*)t.g_out + idx, x0 * t.g_scale, x1 * t.g_scale);
     const int c0 = cbeg[s0 + jj], c1 = cbeg[s0 + jj + 1];
@@ -867,16 +558,10 @@ __global__ __launch_bounds__(kPassThreads * kMaxActions) void bottom_up_internal
     return;
   }
   const double temp = t.mu * p0.x;
-  const double inv_temp = (1.0 / t.mu) * p0.y;
   for (int jj = j; live && jj < na; jj += nw) {
-    double w0, w1 = 0.0;
-    if constexpr (std::is_same<TG, float>::value) {
-      w0 = (double)expf((float)((m0 - gl[jj][lane]) * inv_temp));
-      if constexpr (HP == 2) w1 = (double)expf((float)((m1 - gl[jj][kPassThreads + lane]) * inv_temp));
-    } else {
-      w0 = exp((m0 - gl[jj][lane]) * inv_temp);
-      if constexpr (HP == 2) w1 = exp((m1 - gl[jj][kPassThreads + lane]) * inv_temp);
-    }
+    double w1 = 0.0;
+    const double w0 = lse_weight<TG>(m0, gl[jj][lane], temp);
+    if constexpr (HP == 2) w1 = lse_weight<TG>(m1, gl[jj][kPassThreads + lane], temp);
     wl[jj][lane] = w0;
     if constexpr (HP == 2) wl[jj][kPassThreads + lane] = w1;
   }
@@ -888,12 +573,11 @@ __global__ __launch_bounds__(kPassThreads * kMaxActions) void bottom_up_internal
       if constexpr (HP == 2) sum1 += wl[i][kPassThreads + lane];
     }
     if (j == 0)
-      store2(Vrow, fmadd(temp, p1.x, fmadd(-temp, log(sum0), m0)),
-             HP == 2 ? fmadd(temp, p1.x, fmadd(-temp, log(sum1), m1)) : 0.0);
+      store2(Vrow, lse_value(m0, temp, sum0, p1.x), HP == 2 ? lse_value(m1, temp, sum1, p1.x) : 0.0);
     if (t.QB)
       for (int jj = j; jj < na; jj += nw)
-        store2((TG*)t.QB + (size_t)(s0 + jj) * ld + h, wl[jj][lane] * (1.0 / sum0),
-               HP == 2 ? wl[jj][kPassThreads + lane] * (1.0 / sum1) : 0.0);
+        store2((TG*)t.QB + (size_t)(s0 + jj) * ld + h, wl[jj][lane] / sum0,
+               HP == 2 ? wl[jj][kPassThreads + lane] / sum1 : 0.0);
   }
 }
 
@@ -986,7 +670,7 @@ __global__ __launch_bounds__(kPassThreads) void top_down_kernel(DownArgs a) {
     if (path[j] >= 0) val *= f[j];
   const TS xp = comb_out ? x_prev[idx] : (TS)0;
   if (q_out) q_out[idx] = val;
-  if (comb_out) comb_out[idx] = fmadd((TS)a.tau, val, (TS)(1.0 - a.tau) * xp);
+  if (comb_out) comb_out[idx] = (TS)(1.0 - a.tau) * xp + (TS)a.tau * val;
 }
 
 // The same with two adjacent hands per lane (one 16-byte access per row for
@@ -1033,26 +717,29 @@ __global__ __launch_bounds__(kPassThreads) void top_down_pair_kernel(DownArgs a)
   if (comb_out) {
     const V2 xp = *(const V2*)(x_prev + idx);
     V2 o;
-    o.x = live0 ? fmadd((TS)a.tau, v0, (TS)(1.0 - a.tau) * xp.x) : (TS)0;
-    o.y = live1 ? fmadd((TS)a.tau, v1, (TS)(1.0 - a.tau) * xp.y) : (TS)0;
+    o.x = live0 ? (TS)(1.0 - a.tau) * xp.x + (TS)a.tau * v0 : (TS)0;
+    o.y = live1 ? (TS)(1.0 - a.tau) * xp.y + (TS)a.tau * v1 : (TS)0;
     *(V2*)(comb_out + idx) = o;
   }
 }
 
+// The uniform point: q[s] = q[parent] / n for every sequence s of a node with n
+// actions, from the root down along the sequence's root-first path.
 struct UniformArgs {
-  const int* node_first_seq;
-  const int* node_nact;
+  const int* anc;
+  const int* seq_nact;
   int n, ld;
-  double* QB;
+  double* out;
 };
 
-__global__ __launch_bounds__(kPassThreads) void uniform_qbar_kernel(UniformArgs a) {
+__global__ __launch_bounds__(kPassThreads) void uniform_kernel(UniformArgs a) {
   const int h = blockIdx.x * kPassThreads + threadIdx.x;
-  const int v = blockIdx.y;
+  const int s = blockIdx.y;
   if (h >= a.ld) return;
-  const int s0 = a.node_first_seq[v], na = a.node_nact[v];
-  const double val = h < a.n ? 1.0 / (double)na : 0.0;
-  for (int k = 0; k < na; ++k) a.QB[(size_t)(s0 + k) * a.ld + h] = val;
+  const int* path = a.anc + (size_t)s * kMaxDepth;
+  double val = 1.0;
+  for (int j = 0; j < kMaxDepth && path[j] >= 0; ++j) val = val / (double)a.seq_nact[path[j]];
+  a.out[(size_t)s * a.ld + h] = h < a.n ? val : 0.0;
 }
 
 constexpr int kRedThreads = 1024;
@@ -1090,57 +777,6 @@ __global__ __launch_bounds__(256) void convert_kernel(int64_t count, const TI* i
 // ---------------------------------------------------------------------------
 // Launchers
 // ---------------------------------------------------------------------------
-
-template <class TV, class TO>
-static hipError_t gradient_launch(const egt_game* g, int player, const TV* v_opp, TO* grad_out, int fold_only,
-                                  hipStream_t s) {
-  GradArgs<TV, TO> a;
-  a.own = g->dp[player];
-  a.b_opp = g->dp[1 - player].belief;
-  a.H = g->dh;
-  a.v_opp = v_opp;
-  a.out = grad_out;
-  a.show_sign = player == 0 ? 1.0 : -1.0;
-  a.fold_only = fold_only;
-  a.items = nullptr;
-  a.n_items = 0;
-  const size_t per_group = (size_t)(g->n + 1 + g->dh.n_card_slots);  // doubles
-  const size_t card_bytes = 16 * (size_t)g->dh.card_img16;
-  auto lds_bytes = [&](int gr) { return sizeof(double) * ((gr * per_group + 1) / 2 * 2) + card_bytes; };
-  int groups = g->hp[player].max_terms_per_seq >= 2 ? 2 : 1;
-  if (groups == 2 && lds_bytes(2) > kGradLdsLimit) groups = 1;
-  a.groups = groups;
-  const size_t lds = lds_bytes(groups);
-  // one block per sequence up to two blocks per compute unit; beyond that each
-  // block loops over sequences (the tables are staged once per block), then
-  // over work items that keep both groups busy
-  const bool looping = g->dp[player].n_seq > g->n_cu;  // blocks of the second round would wait for a CU
-  if (looping && groups == 2 && g->dp[player].term_items) {
-    a.items = g->dp[player].term_items;
-    a.n_items = g->dp[player].n_items;
-  }
-  const int blocks = std::min(a.items ? a.n_items : g->dp[player].n_seq, 2 * g->n_cu);
-  const dim3 grid(blocks), block(kGroupThreads * groups);
-  if (g->n <= 2 * kGroupThreads)
-    hipLaunchKernelGGL((gradient_kernel<TV, TO, 2, 1>), grid, block, lds, s, a);
-  else if (g->n <= 5 * kGroupThreads && looping)
-    hipLaunchKernelGGL((gradient_kernel<TV, TO, 5, 4>), grid, block, lds, s, a);
-  else if (g->n <= 5 * kGroupThreads)
-    hipLaunchKernelGGL((gradient_kernel<TV, TO, 5, 1>), grid, block, lds, s, a);
-  else
-    hipLaunchKernelGGL((gradient_kernel<TV, TO, kMaxHandsPerThread, 1>), grid, block, lds, s, a);
-  return hipGetLastError();
-}
-
-hipError_t launch_gradient(const egt_game* g, int player, const double* v_opp, double* grad_out,
-                           hipStream_t s) {
-  return gradient_launch<double, double>(g, player, v_opp, grad_out, 0, s);
-}
-
-hipError_t launch_gradient_fold_f32(const egt_game* g, int player, const float* v_opp, float* grad_out,
-                                    hipStream_t s) {
-  return gradient_launch<float, float>(g, player, v_opp, grad_out, 1, s);
-}
 
 static void fill_pass_set(const egt_game* g, const Pass* p, int count, PassSet& a) {
   a.count = count;
@@ -1308,15 +944,16 @@ hipError_t launch_top_down(const egt_game* g, int player, const void* QB, void* 
   return hipGetLastError();
 }
 
-hipError_t launch_uniform_qbar(const egt_game* g, int player, double* QB, hipStream_t s) {
+hipError_t launch_uniform(const egt_game* g, int player, double* out, hipStream_t s) {
   UniformArgs a;
-  a.node_first_seq = g->dp[player].node_first_seq;
-  a.node_nact = g->dp[player].node_nact;
+  a.anc = g->dp[player].anc;
+  a.seq_nact = g->dp[player].seq_nact;
   a.n = g->n;
   a.ld = g->ld;
-  a.QB = QB;
+  a.out = out;
+  if (g->dp[player].n_seq == 0) return hipSuccess;
   const unsigned bx = (unsigned)((g->ld + kPassThreads - 1) / kPassThreads);
-  hipLaunchKernelGGL(uniform_qbar_kernel, dim3(bx, g->dp[player].n_nodes), dim3(kPassThreads), 0, s, a);
+  hipLaunchKernelGGL(uniform_kernel, dim3(bx, g->dp[player].n_seq), dim3(kPassThreads), 0, s, a);
   return hipGetLastError();
 }
 

@@ -67,7 +67,6 @@ struct egt_state {
   double* Vb[2] = {};       // node values of the best-response passes
   double* X64[2] = {};      // FP64 iterates for the gap (precision form; else scratch aliases)
   double* G64[2] = {};      // FP64 products for the gap (precision form; else scratch aliases)
-  double* S64 = nullptr;    // FP64 q_bar scratch of the start-up (precision form)
   double* dscal = nullptr;  // device scalars
   double* hscal = nullptr;  // pinned host mirror (also the summed tree values)
   double* hpart = nullptr;      // pinned root partial sums [trees][n_partials], written by the kernels
@@ -326,16 +325,12 @@ int state_create_in(const egt_game* g, const egt_solve_opts* o, hipStream_t s, v
       st->G64[p] = (double*)take(sizeof(double) * (size_t)vec_elems(g, p));
     }
   }
-  if (mixed) {
-    st->S64 = (double*)take(sizeof(double) * (size_t)std::max(vec_elems(g, 0), vec_elems(g, 1)));
-  } else {  // FP64: the start-up scratch lives in buffers that are free then
+  if (!mixed) {  // FP64: the start-up scratch lives in buffers that are free then
     for (int p = 0; p < 2; ++p) {
       st->X64[p] = (double*)st->Xbar[p];
       st->G64[p] = (double*)st->Xhat[p];
     }
   }
-  // FP64 q_bar scratch of player p during the start-up
-  auto qscratch = [&](int p) { return mixed ? st->S64 : (double*)st->T1[p]; };
   st->dscal = (double*)take(64 * sizeof(double));
   st->hpart = st->hscal + 64;
   st->hpart2 = st->hpart + (size_t)kMaxTrees * kMaxPartials;
@@ -350,14 +345,12 @@ int state_create_in(const egt_game* g, const egt_solve_opts* o, hipStream_t s, v
 
   // x_omega and A^T x_omega with the FP64 operator: the start of Algorithms 1/3
   int rc;
-  EGT_TRY(launch_uniform_qbar(g, 0, qscratch(0), s));
-  EGT_TRY(launch_top_down(g, 0, qscratch(0), st->X64[0], nullptr, 0.0, nullptr, s));
+  EGT_TRY(launch_uniform(g, 0, st->X64[0], s));
   EGT_TRY(launch_gradient(g, 1, st->X64[0], st->G64[1], s));
   if (auto_mu) {
     // mu0 = 1e-3 max(|A y_omega|_inf, |A^T x_omega|_inf) / max beta, then double
     // both until the excessive gap condition holds at (x0, y0).
-    EGT_TRY(launch_uniform_qbar(g, 1, qscratch(1), s));
-    EGT_TRY(launch_top_down(g, 1, qscratch(1), st->X64[1], nullptr, 0.0, nullptr, s));
+    EGT_TRY(launch_uniform(g, 1, st->X64[1], s));
     EGT_TRY(launch_gradient(g, 0, st->X64[1], st->G64[0], s));
     EGT_TRY(launch_max_abs(vec_elems(g, 0), st->G64[0], st->dscal, s));
     EGT_TRY(launch_max_abs(vec_elems(g, 1), st->G64[1], st->dscal + 1, s));
@@ -513,25 +506,35 @@ static int attempt_v(egt_state* st, const View& v, int p, double tau, const doub
   const double r = tau / (1.0 - tau);
   if ((rc = sbr(st, p, v.G[p], kSg[p], st->T1[p], kSg[p] * r, mu[p], nullptr, v.X[p], tau, v.Xn[p], s))) return rc;
   if ((rc = grad(st, o, v.Xn[p], v.T2[o], s))) return rc;
+  const bool fresh = st->opts.fresh_products != 0;
+  if (fresh && (rc = grad(st, p, v.Xn[o], v.T2[p], s))) return rc;  // p's gradient at y_+, recomputed
   const double mu_new = (1.0 - tau) * mu[p];
   // one launch for the value passes: EGV at (x_+, y_+) with mu_p+ and the
   // unchanged mu_o, and (FP64) the two best responses of the candidate's gap
   Pass ps[4];
-  ps[0] = Pass{p, v.G[p], kSg[p] * (1.0 - tau), st->T1[p], kSg[p] * tau, mu_new, st->V[p], nullptr};
+  if (fresh)
+    ps[0] = Pass{p, v.T2[p], kSg[p], nullptr, 0.0, mu_new, st->V[p], nullptr};
+  else
+    ps[0] = Pass{p, v.G[p], kSg[p] * (1.0 - tau), st->T1[p], kSg[p] * tau, mu_new, st->V[p], nullptr};
   ps[1] = Pass{o, v.T2[o], kSg[o], nullptr, 0.0, mu[o], st->V[o], nullptr};
   int trees = 2;
   if (st->prec == kF64) {
-    if (p == 0)
+    if (fresh)
+      gap_passes(st, v.T2[0], 1.0, nullptr, 0.0, v.T2[1], 1.0, nullptr, 0.0, ps + 2);
+    else if (p == 0)
       gap_passes(st, v.G[0], 1.0 - tau, st->T1[0], tau, v.T2[1], 1.0, nullptr, 0.0, ps + 2);
     else
       gap_passes(st, v.T2[0], 1.0, nullptr, 0.0, v.G[1], 1.0 - tau, st->T1[1], tau, ps + 2);
     trees = 4;
   }
-  // the value launch also writes the accepted product (1-tau) G[p] + tau T1[p]
-  // of tree 0 into T2[p], so accepting the step is a rotation of buffers
+  // without fresh products the value launch also writes the accepted product
+  // (1-tau) G[p] + tau T1[p] of tree 0 into T2[p], so accepting the step is a
+  // rotation of buffers either way
   Epilogue epi[4] = {};
-  epi[0].g_out = v.T2[p];
-  epi[0].g_scale = kSg[p];
+  if (!fresh) {
+    epi[0].g_out = v.T2[p];
+    epi[0].g_scale = kSg[p];
+  }
   EGT_TRY(launch_passes(g, ps, trees, epi, v.part_dev, s, st->prec));
   if (with_gap && st->prec == kF32) {
     // precision form: the candidate's saddle gap in FP64 (widened iterates,
@@ -548,6 +551,8 @@ static int attempt_v(egt_state* st, const View& v, int p, double tau, const doub
   *trees_out = trees;
   return EGT_OK;
 }
+
+int products_per_attempt(const egt_state* st) { return st->opts.fresh_products ? 4 : 3; }
 
 // Side and step size of an iteration after t accepted steps (the variant's
 // rule: alternate with 2 / (t + 3), the larger mu with 2 / (t + 3), or the
@@ -584,7 +589,7 @@ int step_launch(egt_state* st, int player, hipStream_t s) {
   }
   int rc, trees = 0;
   if ((rc = attempt_v(st, current_view(st), st->step_p, st->step_tau, st->mu, first, s, &trees))) return rc;
-  st->products += 3;
+  st->products += products_per_attempt(st);
   return enqueue_values(st, trees, s, st->hpart);
 }
 
@@ -782,7 +787,7 @@ int solve_loop_pipelined(egt_state* st, hipStream_t s, const std::atomic<bool>* 
     st->pending_trees = trees;
     st->pending_part = st->hpart;
     if ((rc = read_values(st))) return rc;
-    st->products += 3;
+    st->products += products_per_attempt(st);
     const double egv = st->hscal[0] + st->hscal[1];
     if (op.variant == EGT_VARIANT_AS && egv < 0.0) {
       tau *= 0.5;
@@ -862,7 +867,7 @@ int64_t state_bytes(const egt_game* g, bool mixed) {
   size_t bytes = 0;
   for (int p = 0; p < 2; ++p) {
     bytes += esz * 11 * (size_t)vec_elems(g, p) + sizeof(double) * 2 * (size_t)g->hp[p].n_nodes * g->ld;
-    if (mixed) bytes += sizeof(double) * 3 * (size_t)vec_elems(g, p);
+    if (mixed) bytes += sizeof(double) * 2 * (size_t)vec_elems(g, p);
     bytes += 15 * 256;
   }
   bytes += 64 * sizeof(double) + 256;

@@ -35,6 +35,12 @@ class EgtError(RuntimeError):
         self.code = code
 
 
+class BetAbstraction(ctypes.Structure):
+    _fields_ = [
+        ("n_fracs", (_i32 * 4) * 2), ("fracs", (_p * 4) * 2), ("allin", (_i32 * 4) * 2), ("open_fold", _i32 * 2),
+    ]
+
+
 class GameDesc(ctypes.Structure):
     _fields_ = [
         ("n_cards", _i32), ("cards_per_hand", _i32), ("n_hands", _i32),
@@ -42,13 +48,14 @@ class GameDesc(ctypes.Structure):
         ("pot", _f64), ("stack", _f64),
         ("n_bet_fracs", _i32), ("bet_fracs", _p),
         ("allin", _i32), ("max_raises", _i32),
+        ("abstraction", ctypes.POINTER(BetAbstraction)),
     ]
 
 
 class SolveOpts(ctypes.Structure):
     _fields_ = [
         ("variant", _i32), ("precision", _i32), ("eps", _f64), ("max_iters", _i64),
-        ("mu0_x", _f64), ("mu0_y", _f64), ("tau0", _f64), ("gap_every", _i32), ("reserved", _i32),
+        ("mu0_x", _f64), ("mu0_y", _f64), ("tau0", _f64), ("gap_every", _i32), ("fresh_products", _i32),
     ]
 
 
@@ -100,6 +107,21 @@ _state_gap = _decl("egt_state_gap", ctypes.c_int, _p, ctypes.POINTER(_f64), ctyp
 _solve = _decl("egt_solve", ctypes.c_int, _p, ctypes.POINTER(SolveOpts), ctypes.POINTER(SolveResult),
                ctypes.POINTER(_p), _p)
 
+_cfr_create = _decl("egt_cfr_create", ctypes.c_int, _p, _i32, _p, ctypes.POINTER(_p))
+_cfr_destroy = _decl("egt_cfr_destroy", ctypes.c_int, _p)
+_cfr_step = _decl("egt_cfr_step", ctypes.c_int, _p, _i32, _p)
+_cfr_gap = _decl("egt_cfr_gap", ctypes.c_int, _p, ctypes.POINTER(_f64), ctypes.POINTER(_f64), ctypes.POINTER(_f64),
+                 _p)
+_cfr_get = _decl("egt_cfr_get", ctypes.c_int, _p, _p, _p, _p, _p, ctypes.POINTER(_i64), _p)
+_cfr_solve = _decl("egt_cfr_solve", ctypes.c_int, _p, _i32, _f64, _i64, _i32, ctypes.POINTER(SolveResult), _p)
+
+_fom_create = _decl("egt_fom_create", ctypes.c_int, _p, _i32, _f64, _f64, _p, ctypes.POINTER(_p))
+_fom_destroy = _decl("egt_fom_destroy", ctypes.c_int, _p)
+_fom_step = _decl("egt_fom_step", ctypes.c_int, _p, _i32, _p)
+_fom_get = _decl("egt_fom_get", ctypes.c_int, _p, _p, _p, _p, _p, ctypes.POINTER(_i64), ctypes.POINTER(_i64), _p)
+_fom_gap = _decl("egt_fom_gap", ctypes.c_int, _p, ctypes.POINTER(_f64), ctypes.POINTER(_f64), ctypes.POINTER(_f64),
+                 _p)
+
 _state_bytes = _decl("egt_state_bytes", ctypes.c_int, _p, ctypes.POINTER(SolveOpts), ctypes.POINTER(_i64))
 _batch_create = _decl("egt_batch_create", ctypes.c_int, _i64, _i32, ctypes.POINTER(_p))
 _batch_destroy = _decl("egt_batch_destroy", ctypes.c_int, _p)
@@ -108,6 +130,7 @@ _batch_tick = _decl("egt_batch_tick", ctypes.c_int, _p, ctypes.POINTER(_i32), ct
 _batch_poll = _decl("egt_batch_poll", ctypes.c_int, _p, _i32, ctypes.POINTER(_i32), ctypes.POINTER(_i32),
                     ctypes.POINTER(SolveResult))
 _batch_retire = _decl("egt_batch_retire", ctypes.c_int, _p, _i32)
+_batch_strategies = _decl("egt_batch_strategies", ctypes.c_int, _p, _i32, _p, _p, _p)
 _batch_usage = _decl("egt_batch_usage", ctypes.c_int, _p, ctypes.POINTER(_i64), ctypes.POINTER(_i32),
                      ctypes.POINTER(_i32))
 
@@ -119,6 +142,8 @@ EXPORTED = [
     "egt_state_get", "egt_state_get_products", "egt_state_set", "egt_state_gap", "egt_solve",
     "egt_state_bytes", "egt_batch_create", "egt_batch_destroy", "egt_batch_admit", "egt_batch_tick",
     "egt_batch_poll", "egt_batch_retire", "egt_batch_usage", "egt_saddle_gap_noalloc",
+    "egt_batch_strategies", "egt_cfr_create", "egt_cfr_destroy", "egt_cfr_step", "egt_cfr_gap", "egt_cfr_get",
+    "egt_cfr_solve", "egt_fom_create", "egt_fom_destroy", "egt_fom_step", "egt_fom_get", "egt_fom_gap",
 ]
 
 
@@ -167,6 +192,20 @@ class Game:
         d.bet_fracs = fr.ctypes.data if len(fr) else None
         d.allin = 1 if inst.allin else 0
         d.max_raises = inst.max_raises
+        keep = []  # host arrays that must live until egt_build_game returns
+        ab = getattr(inst, "abstraction", None)
+        if ab is not None:
+            a = BetAbstraction()
+            for p in (0, 1):
+                a.open_fold[p] = 1 if ab.open_fold[p] else 0
+                for k in range(4):
+                    fr_k = np.ascontiguousarray(ab.fracs[p][k], dtype=np.float64)
+                    keep.append(fr_k)
+                    a.n_fracs[p][k] = len(fr_k)
+                    a.fracs[p][k] = fr_k.ctypes.data if len(fr_k) else None
+                    a.allin[p][k] = 1 if ab.allin[p][k] else 0
+            keep.append(a)
+            d.abstraction = ctypes.pointer(a)
         h = _p()
         _check(_build_game(ctypes.byref(d), _stream(stream), ctypes.byref(h)))
         self._h = h
@@ -299,7 +338,8 @@ def saddle_gap_noalloc(game: Game, x, y, out3=None, stream=None):
 PRECISIONS = {"fp64": 0, "mixed": 1}
 
 
-def make_opts(variant="AS", eps=None, max_iters=100000, mu0=None, tau0=0.5, gap_every=1, precision="fp64"):
+def make_opts(variant="AS", eps=None, max_iters=100000, mu0=None, tau0=0.5, gap_every=1, precision="fp64",
+              fresh_products=False):
     o = SolveOpts()
     _default_opts(ctypes.byref(o))
     o.variant = VARIANTS[variant] if isinstance(variant, str) else int(variant)
@@ -310,6 +350,7 @@ def make_opts(variant="AS", eps=None, max_iters=100000, mu0=None, tau0=0.5, gap_
         o.mu0_x, o.mu0_y = float(mu0[0]), float(mu0[1])
     o.tau0 = float(tau0)
     o.gap_every = int(gap_every)
+    o.fresh_products = 1 if fresh_products else 0
     return o
 
 
@@ -429,6 +470,12 @@ class Batch:
     def retire(self, slot: int):
         _check(_batch_retire(self._h, int(slot)))
 
+    def strategies(self, slot: int, game: Game, stream=None):
+        """Final (x, y) of a finished slot as FP64 device tensors."""
+        x, y = game.empty(0), game.empty(1)
+        _check(_batch_strategies(self._h, int(slot), _dptr(x), _dptr(y), _stream(stream)))
+        return x, y
+
     def usage(self):
         u, live, done = _i64(), _i32(), _i32()
         _check(_batch_usage(self._h, ctypes.byref(u), ctypes.byref(live), ctypes.byref(done)))
@@ -437,6 +484,103 @@ class Batch:
     def close(self):
         if self._h is not None:
             _check(_batch_destroy(self._h))
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+CFR_VARIANTS = {"CFR": 0, "CFR_RMP": 1, "CFR_PLUS": 2}
+
+
+class Cfr:
+    """A CFR(RM) / CFR(RM+) / CFR+ run on the device (egt_cfr_*)."""
+
+    def __init__(self, game: Game, variant="CFR_PLUS", stream=None):
+        self.game = game
+        self._h = None
+        h = _p()
+        _check(_cfr_create(game.handle, CFR_VARIANTS[variant], _stream(stream), ctypes.byref(h)))
+        self._h = h
+
+    def step(self, iters=1, stream=None):
+        _check(_cfr_step(self._h, int(iters), _stream(stream)))
+
+    def gap(self, stream=None):
+        g, a, b = _f64(), _f64(), _f64()
+        _check(_cfr_gap(self._h, ctypes.byref(g), ctypes.byref(a), ctypes.byref(b), _stream(stream)))
+        return g.value, a.value, b.value
+
+    def get(self, stream=None):
+        G = self.game
+        xa, ya, xc, yc = G.empty(0), G.empty(1), G.empty(0), G.empty(1)
+        it = _i64()
+        _check(_cfr_get(self._h, _dptr(xa), _dptr(ya), _dptr(xc), _dptr(yc), ctypes.byref(it), _stream(stream)))
+        torch.cuda.synchronize()
+        return dict(x_avg=xa, y_avg=ya, x=xc, y=yc, iters=it.value)
+
+    def close(self):
+        if self._h is not None:
+            _check(_cfr_destroy(self._h))
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def cfr_solve(game: Game, variant="CFR_PLUS", eps=None, max_iters=100000, gap_every=10, stream=None):
+    """egt_cfr_solve: result dict with status."""
+    res = SolveResult()
+    rc = _cfr_solve(game.handle, CFR_VARIANTS[variant], 0.0 if eps is None else float(eps), int(max_iters),
+                    int(gap_every), ctypes.byref(res), _stream(stream))
+    _check(rc, allow=(-5,))
+    out = res.as_dict()
+    out["status"] = ERRORS.get(rc, "EGT_OK") if rc else "EGT_OK"
+    return out
+
+
+FOM_METHODS = {"MP": 0, "CP": 1}
+
+
+class Fom:
+    """Mirror prox ("MP", steps eta_x, eta_y) or Chambolle-Pock ("CP", steps
+    tau, sigma) on the device (egt_fom_*)."""
+
+    def __init__(self, game: Game, method="MP", step_x=1.0, step_y=None, stream=None):
+        self.game = game
+        self._h = None
+        h = _p()
+        sy = step_x if step_y is None else step_y
+        _check(_fom_create(game.handle, FOM_METHODS[method], float(step_x), float(sy), _stream(stream),
+                           ctypes.byref(h)))
+        self._h = h
+
+    def step(self, iters=1, stream=None):
+        _check(_fom_step(self._h, int(iters), _stream(stream)))
+
+    def gap(self, stream=None):
+        g, a, b = _f64(), _f64(), _f64()
+        _check(_fom_gap(self._h, ctypes.byref(g), ctypes.byref(a), ctypes.byref(b), _stream(stream)))
+        return g.value, a.value, b.value
+
+    def get(self, stream=None):
+        G = self.game
+        xa, ya, xc, yc = G.empty(0), G.empty(1), G.empty(0), G.empty(1)
+        it, pr = _i64(), _i64()
+        _check(_fom_get(self._h, _dptr(xa), _dptr(ya), _dptr(xc), _dptr(yc), ctypes.byref(it), ctypes.byref(pr),
+                        _stream(stream)))
+        torch.cuda.synchronize()
+        return dict(x_avg=xa, y_avg=ya, x=xc, y=yc, iters=it.value, products=pr.value)
+
+    def close(self):
+        if self._h is not None:
+            _check(_fom_destroy(self._h))
             self._h = None
 
     def __del__(self):

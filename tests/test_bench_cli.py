@@ -19,6 +19,6 @@ def test_bench_refuses_more_than_one_gpu():
 
 def test_bench_and_trace_cli_parse():
     r = _run("bench.py", "--help")
-    assert r.returncode == 0 and "--no-large-tree" in r.stdout and "--serve-rate" in r.stdout
+    assert r.returncode == 0 and "--second-config" in r.stdout and "--serve-rate" in r.stdout
     r = _run("-m", "paper_1810_03063_amd.serve_trace", "--help")
     assert r.returncode == 0 and "--mode" in r.stdout

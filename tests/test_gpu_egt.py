@@ -11,7 +11,12 @@ meaningful:
       max|x_gpu - x_oracle| <= 1e-10 max|x_oracle|  (same for y),
       |EGV_gpu - EGV_oracle|, |gap_gpu - gap_oracle| <= 1e-10 (|BR terms|)
   with the saddle gap of the new point measured independently by the oracle;
-* whole-trajectory parity over prefixes shorter than the amplification;
+* whole-trajectory parity over prefixes shorter than the amplification, at
+  1e-10 relative;
+* full-length trajectories (2000 EGT iterations, 20 EGT/as iterations of the
+  1081-hand endgame), where the bar is derived from the GPU's measured
+  per-product error: the oracle re-run with product noise of that size shows
+  how far such errors carry (test_full_trajectory_parity);
 * complete solves: the GPU's reported final gap re-measured by the oracle at
   the GPU's final strategies, and the value within the two gaps of the
   oracle's own solve;
@@ -54,6 +59,9 @@ ONE_STEP = [
     ("c0", 0, "ALT", 2000, 50),
     ("c0", 4, "BAL", 300, 10),
     ("c1", 0, "AS", 40, 13),
+    ("kuhn_open_fold", 0, "AS", 150, 3),
+    ("lib_micro", 0, "AS", 300, 5),
+    ("lib", 0, "AS", 30, 10),
 ]
 
 
@@ -148,6 +156,7 @@ PREFIX = [
     ("c0", 0, "ALT", 0.0, 500),
     ("c0", 4, "BAL", 0.0, 300),
     ("c1", 0, "AS", 0.0, 12),
+    ("lib_micro", 0, "AS", 0.0, 20),
 ]
 
 
@@ -173,7 +182,102 @@ def test_trajectory_prefix_parity(egt, cfg, seed, variant, eps, iters):
     assert np.abs(y - tr.y).max() <= 1e-10 * np.abs(tr.y).max()
 
 
-@pytest.mark.parametrize("cfg,seed,with_oracle_solve", [("c0", 1, True), ("c0", 3, True), ("c1", 0, False)])
+def abs_sum_bound(P, p, v_opp):
+    """Per entry of p's gradient: (b_own(h)/Z) * sum over the terminals at the
+    sequence of |u(z)| * sum_h' |b_opp(h') v_opp[sigma_opp(z), h']|, the sum of
+    the absolute values of the terms the entry adds up."""
+    o = 1 - p
+    S = np.zeros(P.n_seq[p])
+    for z in P.game.terminals:
+        row = np.ones(P.n) if z.seq[o] < 0 else v_opp[z.seq[o]]
+        S[z.seq[p]] += abs(z.u) * np.sum(np.abs(P.b[o] * row))
+    return (P.b[p] / P.Z)[None, :] * S[:, None]
+
+
+def oracle_trajectory(P, variant, iters, mu0=None, noise=0.0, seed=0):
+    """The oracle's iterates (shift-free prox, the form the GPU computes)
+    with, when noise > 0, every product entry moved by a seeded uniform draw
+    of at most noise times its absolute-term sum: a model of another correct
+    FP64 evaluation of A y whose per-entry error is `noise`."""
+    if noise > 0.0:
+        rng = np.random.default_rng(seed)
+        gx0, gy0 = P.grad_x, P.grad_y
+        P.grad_x = lambda v: gx0(v) + rng.uniform(-1.0, 1.0, (P.n_seq[0], P.n)) * noise * abs_sum_bound(P, 0, v)
+        P.grad_y = lambda v: gy0(v) + rng.uniform(-1.0, 1.0, (P.n_seq[1], P.n)) * noise * abs_sum_bound(P, 1, v)
+    xs = []
+    try:
+        tr = solve(P, variant, eps=0.0, max_iters=iters, mu0=mu0, literal=False,
+                   on_iterate=lambda t, x, y, *r: xs.append((x.copy(), y.copy())))
+    finally:
+        if noise > 0.0:
+            P.grad_x, P.grad_y = gx0, gy0
+    return tr, xs
+
+
+def drift(a, b):
+    return [max(np.abs(x0 - x1).max() / np.abs(x1).max(), np.abs(y0 - y1).max() / np.abs(y1).max())
+            for (x0, y0), (x1, y1) in zip(a, b)]
+
+
+FULL = [("c0", 0, "ALT", 2000), ("c1", 0, "AS", 20)]
+
+
+@pytest.mark.parametrize("cfg,seed,variant,iters", FULL)
+def test_full_trajectory_parity(egt, cfg, seed, variant, iters):
+    """Whole trajectories: the 105-hand endgame's 2000 EGT iterations and the
+    1081-hand endgame's first 20 EGT/as iterations, GPU against oracle at
+    every iterate.
+
+    EGT amplifies rounding along a trajectory roughly in proportion to the
+    per-operation error (one unit in the last place of every product entry
+    moves the 105-hand run by ~1e-10 of max |x| after 2000 iterations; see
+    test_trajectory_sensitivity_to_product_rounding).  The GPU's smoothed best
+    response follows the oracle's formulas operation by operation, but its
+    O(n) products add their terms in another order than the dense
+    definition.  So the test (1) measures the GPU's per-product error at
+    iterates along the oracle's trajectory, (2) re-runs the oracle with
+    product noise of that size, and (3) bounds the GPU's drift by
+    max(1e-10, 3 x the drift that noise causes).  The GPU runs with fresh
+    products at every iterate and the oracle's initial mu, like the oracle."""
+    inst = make_instance(cfg, seed)
+    print(f"[case] full trajectory {cfg} seed={seed} {variant} {iters}", flush=True)
+    P = Problem(inst)
+    tr, xs = oracle_trajectory(P, variant, iters)
+    G = egt.Game(inst)
+    L = Layout(G, P)
+    # (1) per-product error at five iterates, relative to the absolute-term sums
+    eps_prod = 0.0
+    for t in np.linspace(0, iters, 5).astype(int):
+        x, y = xs[t]
+        ay = L.from_lib(0, egt.gradient(G, 0, dev(L.to_lib(1, y))).cpu().numpy())
+        atx = L.from_lib(1, egt.gradient(G, 1, dev(L.to_lib(0, x))).cpu().numpy())
+        eps_prod = max(eps_prod, (np.abs(ay - P.grad_x(y)) / np.maximum(abs_sum_bound(P, 0, y), 1e-300)).max(),
+                       (np.abs(atx - P.grad_y(x)) / np.maximum(abs_sum_bound(P, 1, x), 1e-300)).max())
+    # (2) the oracle's own drift under product noise of that size
+    _, xn = oracle_trajectory(P, variant, iters, mu0=tr.mu0, noise=eps_prod, seed=seed + 1)
+    d_noise = max(drift(xn, xs))
+    # (3) the GPU trajectory
+    st = egt.State(G, variant=variant, eps=0.0, max_iters=10**9, mu0=tr.mu0, fresh_products=True)
+    gx = []
+    for t in range(iters + 1):
+        g = st.get()
+        gx.append((L.from_lib(0, g["x"].cpu().numpy()), L.from_lib(1, g["y"].cpu().numpy())))
+        if t < iters:
+            st.step()
+    st.close()
+    d_gpu = drift(gx, xs)
+    bar = max(1e-10, 3.0 * d_noise)
+    print(f"  per-product error {eps_prod:.2e} of the absolute-term sums; oracle drift under that noise "
+          f"{d_noise:.2e}; GPU drift {max(d_gpu):.2e} (t=100: {d_gpu[min(100, iters)]:.2e}); bar {bar:.2e}")
+    assert eps_prod <= 1e-13
+    assert d_gpu[min(10, iters)] <= 1e-12
+    assert max(d_gpu) <= bar
+    G.close()
+
+
+@pytest.mark.parametrize("cfg,seed,with_oracle_solve", [("c0", 1, True), ("c0", 3, True), ("c1", 0, False),
+                                                        ("c3", 0, False), ("lib_micro", 0, True),
+                                                        ("lib", 0, False)])
 def test_solve_verified_by_oracle(egt, cfg, seed, with_oracle_solve):
     inst = make_instance(cfg, seed)
     print(f"[case] egt_solve {cfg} seed={seed}", flush=True)
@@ -195,9 +299,13 @@ def test_solve_verified_by_oracle(egt, cfg, seed, with_oracle_solve):
     assert brmin_o <= -r["value_p1"] + 1e-12 * sc <= brmax_o + 2e-12 * sc
     assert r["products"] == 3 * (r["iters"] + r["backtracks"])
     if with_oracle_solve:
+        # the values of both solves lie within their gaps of the game value;
+        # the number of EGT/as iterations to the target depends on rounding
+        # (trajectories part after a few dozen iterations), so it is only
+        # required to be of the same size as the oracle's
         tr = solve(P, "AS")
         assert abs(r["value_p1"] + tr.value_p2) <= r["gap"] + tr.gap
-        assert 0.65 * tr.iters <= r["iters"] <= 1.35 * tr.iters, (r["iters"], tr.iters)
+        assert 0.5 * tr.iters <= r["iters"] <= 2.0 * tr.iters, (r["iters"], tr.iters)
     st.close()
 
 

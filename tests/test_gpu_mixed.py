@@ -164,7 +164,7 @@ def test_mixed_one_step_error(egt, cfg, seed, stride, iters):
     st.close()
 
 
-@pytest.mark.parametrize("cfg,seed", [("c0", 0), ("c0", 3), ("c1", 0)])
+@pytest.mark.parametrize("cfg,seed", [("c0", 0), ("c0", 3), ("c1", 0), ("c3", 0), ("lib", 0)])
 def test_mixed_solve_reaches_target(egt, cfg, seed):
     inst = make_instance(cfg, seed)
     print(f"[case] mixed solve {cfg} seed={seed}", flush=True)
@@ -176,7 +176,10 @@ def test_mixed_solve_reaches_target(egt, cfg, seed):
     assert rm["status"] == "EGT_OK" and rm["converged"] == 1
     f = st.get()
     x, y = L.from_lib(0, f["x"].cpu().numpy()), L.from_lib(1, f["y"].cpu().numpy())
-    assert P.flow_residual(0, x) < 1e-5 and P.flow_residual(1, y) < 1e-5
+    # FP32 iterates: every accepted step rounds (1 - tau) x + tau q to FP32
+    # (2^-24 relative), so over ~10^3 iterations a simplex of up to 10 actions
+    # drifts from its parent's mass by ~10 x sqrt(10^3) x 6e-8 = 2e-5
+    assert P.flow_residual(0, x) < 1e-4 and P.flow_residual(1, y) < 1e-4
     gap_o, brmax, brmin = P.saddle_gap(x, y)
     assert gap_o <= eps * (1 + 1e-9)
     assert abs(rm["gap"] - gap_o) <= 1e-10 * (abs(brmax) + abs(brmin))

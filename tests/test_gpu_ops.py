@@ -80,7 +80,10 @@ def grad_bound(P, p, v_opp):
     return (P.b[p] / P.Z)[None, :] * S[:, None]
 
 
-CASES = [("kuhn", 0), ("micro", 0), ("micro", 5), ("c0", 0), ("c0", 3), ("c1", 0), ("c3", 0)]
+# the last three use the situation-dependent (Libratus-style) bet abstraction
+# with open folds: Kuhn with open folds, the 10-hand and the 1081-hand river
+CASES = [("kuhn", 0), ("micro", 0), ("micro", 5), ("c0", 0), ("c0", 3), ("c1", 0), ("c3", 0),
+         ("kuhn_open_fold", 0), ("lib_micro", 0), ("lib", 0)]
 
 
 @pytest.mark.parametrize("cfg,seed", CASES)

@@ -7,12 +7,16 @@
 * A solve admitted while others are running joins the running batch and
   can finish before them.
 * The request loop serves a Poisson trace end to end.
+* A batched solve's final strategies, re-measured by the CPU oracle, meet the
+  gap target, and the gap the batch reported agrees with the oracle's.
 """
 import numpy as np
 import pytest
 
 from instances import make_instance
 from instances.endgames import serving_trace
+from oracle import Problem
+from tests.layout import Layout
 
 pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
@@ -111,3 +115,36 @@ def test_request_loop_serves_a_poisson_trace(egt):
     assert s["converged"] == len(reqs)
     assert all(r.result["gap"] <= 1e-3 * r.payload.pot for r in out)
     eng.close()
+
+
+@pytest.mark.parametrize("prec,ge", [("fp64", 1), ("mixed", 10)])
+def test_batched_solve_verified_by_oracle(egt, prec, ge):
+    """Three solves run together (two 105-hand endgames and a 1081-hand one);
+    each one's final strategies come back from the batch and the oracle
+    re-measures their saddle gap."""
+    cases = [("c0", 6), ("c1", 2), ("c0", 7)]
+    insts = [make_instance(c, s) for c, s in cases]
+    games = [egt.Game(i) for i in insts]
+    b = egt.Batch(budget_bytes=4 << 30, max_slots=8)
+    print(f"[case] batched solves verified by the oracle, {prec}", flush=True)
+    slots = [b.admit(G, precision=prec, gap_every=ge) for G in games]
+    assert None not in slots
+    while b.usage()[1] > 0:
+        b.tick()
+    for (c, s), inst, G, slot in zip(cases, insts, games, slots):
+        status, r = b.poll(slot)
+        assert status == "EGT_OK" and r["converged"] == 1
+        x, y = b.strategies(slot, G)
+        P = Problem(inst)
+        L = Layout(G, P)
+        x, y = L.from_lib(0, x.cpu().numpy()), L.from_lib(1, y.cpu().numpy())
+        gap_o, brmax, brmin = P.saddle_gap(x, y)
+        sc = abs(brmax) + abs(brmin)
+        print(f"  {c} seed {s}: {r['iters']} iterations, gap {r['gap']:.6g}, oracle {gap_o:.6g}")
+        assert gap_o <= 1e-3 * inst.pot * (1 + 1e-9)
+        assert abs(r["gap"] - gap_o) <= 1e-10 * sc
+        assert abs(-r["value_p1"] - P.value(x, y)) <= 1e-9 * sc
+        b.retire(slot)
+    with pytest.raises(egt.EgtError):
+        b.strategies(slots[0], games[0])  # retired
+    b.close()
