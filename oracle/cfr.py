@@ -15,9 +15,12 @@ definitions; they are restated here from the sequence form:
   g~_a = g[v, a] + sum over the child sets k of V[k], and the set's loss is
   V[v] = sum_a q_bar_a g~_a;
 * the instantaneous regret of a is V[v] - g~_a, taken as exactly zero when it
-  is within 1e-12 of |V[v]| + |g~_a| (where actions tie exactly, e.g. by the
-  game's symmetry, its sign would otherwise be decided by rounding and would
-  flip regret matching between a uniform and a pure strategy); regret matching adds it to
+  is within 1e-12 of |V[v]| + |g~_a| + S, S the largest |g| entry of the
+  player's gradient in this iteration (where actions tie exactly, by the
+  game's symmetry or because no opponent mass reaches them, a product
+  computed in another order leaves a rounding residue of the order of
+  1e-16 S whose sign would flip regret matching between a uniform and a pure
+  strategy); regret matching adds it to
   the cumulative regret R_a and plays q_bar_a proportional to max(R_a, 0)
   (uniform when no R_a is positive); regret matching+ floors the cumulative
   regret at zero after each addition, R_a <- max(R_a + r_a, 0);
@@ -103,6 +106,7 @@ class Cfr:
         t = self.P.tp[p]
         V = np.zeros((len(t.nodes), self.P.n))
         R, qbar = self.R[p], self.qbar[p]
+        S = float(np.abs(g).max()) if g.size else 0.0
         for v in t.post_order:  # children first
             node = t.nodes[v]
             sl = slice(node.first_seq, node.first_seq + node.n_act)
@@ -113,8 +117,9 @@ class Cfr:
             V[v] = (qbar[sl] * gt).sum(axis=0)
             r = V[v][None, :] - gt
             # exact ties: a regret within 1e-12 of the values it is the
-            # difference of is zero (its sign would be rounding noise)
-            r = np.where(np.abs(r) <= 1e-12 * (np.abs(V[v])[None, :] + np.abs(gt)), 0.0, r)
+            # difference of, or of the gradient's scale, is zero (its sign
+            # would be rounding noise)
+            r = np.where(np.abs(r) <= 1e-12 * (np.abs(V[v])[None, :] + np.abs(gt) + S), 0.0, r)
             R[sl] = R[sl] + r
             if self.plus:
                 R[sl] = np.maximum(R[sl], 0.0)

@@ -9,8 +9,10 @@
 //   information set (node v, hand h) and its actions in order:
 //     g~_a  = g[v, a] + sum of the values of a's child sets (betting order),
 //     V[v]  = sum_a q_bar_a g~_a            (q_bar the current local strategy),
-//     r_a   = V[v] - g~_a, or 0 within 1e-12 of |V[v]| + |g~_a| (an exact tie,
-//             whose sign rounding would otherwise decide),
+//     r_a   = V[v] - g~_a, or 0 within 1e-12 of |V[v]| + |g~_a| + S, S the
+//             largest |g| entry (an exact tie, or actions no opponent mass
+//             reaches, whose sign the products' rounding would otherwise
+//             decide),
 //     R_a  <- R_a + r_a                     (regret matching+: then max(R_a, 0)),
 //     q_bar_a = max(R_a, 0) / sum_a' max(R_a', 0), or 1 / n_v when no R_a is positive;
 //   top-down, x[s] = x[parent] q_bar[s] (the pass the smoothed best response uses).
@@ -47,8 +49,27 @@ struct RegretArgs {
   double* V;        // node values by value slot
   double* R;        // cumulative regrets [n_seq][ld]
   double* QB;       // local strategy [n_seq][ld], read then overwritten
+  const double* gscale;  // max |g| over the real hands (device scalar)
   int plus;         // regret matching+
 };
+
+// S = max |g| over p's gradient (real hands only) into *out, which holds 0.0
+// beforehand; |g| >= 0, so the bit patterns order as the values do.
+__global__ __launch_bounds__(256) void absmax_kernel(const double* g, int64_t count, int n, int ld,
+                                                     unsigned long long* out) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  double m = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += stride)
+    if ((int)(i % ld) < n) m = fmax(m, fabs(g[i]));
+  for (int off = 32; off > 0; off >>= 1) m = fmax(m, __shfl_xor(m, off));
+  __shared__ double wmax[4];
+  if ((threadIdx.x & 63) == 0) wmax[threadIdx.x >> 6] = m;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    m = fmax(fmax(wmax[0], wmax[1]), fmax(wmax[2], wmax[3]));
+    atomicMax(out, (unsigned long long)__double_as_longlong(m));
+  }
+}
 
 __global__ __launch_bounds__(kLanes) void regret_level_kernel(RegretArgs a) {
   const int h = blockIdx.x * kLanes + threadIdx.x;
@@ -74,6 +95,7 @@ __global__ __launch_bounds__(kLanes) void regret_level_kernel(RegretArgs a) {
     }
   }
   a.V[(size_t)r.z * ld + h] = val;
+  const double S = *a.gscale;
   double pos[kMaxActions];
   double tot = 0.0;
 #pragma unroll
@@ -81,7 +103,7 @@ __global__ __launch_bounds__(kLanes) void regret_level_kernel(RegretArgs a) {
     if (j < na) {
       const size_t idx = (size_t)(s0 + j) * ld + h;
       double r = val - gt[j];
-      if (fabs(r) <= 1e-12 * (fabs(val) + fabs(gt[j]))) r = 0.0;  // an exact tie
+      if (fabs(r) <= 1e-12 * (fabs(val) + fabs(gt[j]) + S)) r = 0.0;  // an exact tie
       double R = a.R[idx] + r;
       if (a.plus) R = fmax(R, 0.0);
       a.R[idx] = R;
@@ -127,6 +149,7 @@ struct egt_cfr {
   double* Vb[2] = {};   // node values of the gap's best responses
   double* part = nullptr;    // device partial sums [2][kMaxPartials]
   double* scal = nullptr;    // device sums [2]
+  double* gmax = nullptr;    // device max |g| [2]
   double* hscal = nullptr;   // pinned host copy
   void* block = nullptr;
 };
@@ -151,6 +174,15 @@ int cfr_update(egt_cfr* c, int p, hipStream_t s) {
   a.R = c->R[p];
   a.QB = c->QB[p];
   a.plus = c->variant != EGT_CFR_RM;
+  a.gscale = c->gmax + p;
+  {
+    const int64_t cnt = vec_elems_of(g, p);
+    hipLaunchKernelGGL(fill_kernel, dim3(1), dim3(256), 0, s, c->gmax + p, (int64_t)1, 0.0);
+    const unsigned fb = (unsigned)std::max<int64_t>(1, std::min<int64_t>((cnt + 255) / 256, 2048));
+    hipLaunchKernelGGL(absmax_kernel, dim3(fb), dim3(256), 0, s, (const double*)c->G[p], cnt, g->n, g->ld,
+                       (unsigned long long*)(c->gmax + p));
+    EGT_HIP(hipGetLastError());
+  }
   for (int l = 0; l < hp.n_levels; ++l) {
     a.node0 = hp.level_begin[l];
     const int cnt = hp.level_begin[l + 1] - hp.level_begin[l];
@@ -220,7 +252,7 @@ int egt_cfr_create(const egt_game* g, int32_t variant, hipStream_t s, egt_cfr** 
     bytes += 5 * al(sizeof(double) * (size_t)vec_elems_of(g, p));
     bytes += 2 * al(sizeof(double) * (size_t)g->hp[p].n_nodes * g->ld);
   }
-  bytes += al(sizeof(double) * 2 * kMaxPartials) + al(2 * sizeof(double));
+  bytes += al(sizeof(double) * 2 * kMaxPartials) + 2 * al(2 * sizeof(double));
   hipError_t e = hipMalloc(&c->block, bytes);
   if (e != hipSuccess) return fail(EGT_ENOMEM, std::string("hipMalloc (CFR state): ") + hipGetErrorString(e));
   e = hipHostMalloc((void**)&c->hscal, 2 * sizeof(double), hipHostMallocDefault);
@@ -246,6 +278,7 @@ int egt_cfr_create(const egt_game* g, int32_t variant, hipStream_t s, egt_cfr** 
   }
   c->part = take(sizeof(double) * 2 * kMaxPartials);
   c->scal = take(2 * sizeof(double));
+  c->gmax = take(2 * sizeof(double));
   // zero regrets, uniform local strategies, x_1 = the uniform point, avg = x_1
   for (int p = 0; p < 2; ++p) {
     const int64_t cnt = vec_elems_of(g, p);
