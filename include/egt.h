@@ -398,9 +398,9 @@ int egt_state_bytes(const egt_game* game, const egt_solve_opts* opts, int64_t* b
 
 /* A batch of at most max_slots (1..1024) concurrent solves whose states
  * together stay within budget_bytes of device memory.  Reserves the budget
- * as one device arena, a stream (default priority) and pinned host scalars
- * per slot, and starts min(max_slots, 16) host worker threads; nothing is
- * allocated after this call.  EGT_ENOMEM when the reservation fails. */
+ * as one device arena, a non-blocking stream (default priority) and pinned
+ * host scalars per slot, and starts min(max_slots, 16) host worker threads;
+ * nothing is allocated on the device after this call.  EGT_ENOMEM when the reservation fails. */
 int egt_batch_create(int64_t budget_bytes, int32_t max_slots, egt_batch** out);
 
 /* Stops the workers (a running solve stops after its current iteration),
@@ -416,6 +416,17 @@ int egt_batch_destroy(egt_batch* batch);
  * after a retire.  The precision-form tables of `game` are built here. */
 int egt_batch_admit(egt_batch* batch, const egt_game* game, const egt_solve_opts* opts,
                     int32_t* slot);
+
+/* Admission by description: like egt_batch_admit, but the batch builds the
+ * game itself.  The host part (betting tree, tables, and W for the precision
+ * form) runs in this call; the device tables are placed in the slot's arena
+ * range ahead of the state -- their bytes are charged to the budget with the
+ * state's -- and uploaded by the worker on the slot's stream, so admission
+ * performs no device allocation and no synchronisation.  The game is freed
+ * (host tables only) when the slot is retired.  EGT_EINVAL on a bad
+ * description, EGT_EBUDGET as egt_batch_admit. */
+int egt_batch_admit_desc(egt_batch* batch, const egt_game_desc* desc, const egt_solve_opts* opts,
+                         int32_t* slot);
 
 /* Waits up to about 2 ms for a solve to finish (returns at once when one
  * finished since the last tick or none is live).  n_active: queued and

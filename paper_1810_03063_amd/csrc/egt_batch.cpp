@@ -36,6 +36,10 @@ int state_get(const egt_state* st, double* x, double* y, double* mu_x, double* m
               hipStream_t s);
 int64_t state_bytes(const egt_game* g, bool mixed);
 size_t state_host_doubles();
+int build_game_host(const egt_game_desc* d, egt_game** out);
+size_t game_device_bytes(const egt_game* g);
+int upload_game(egt_game* g, void* dev, bool owned, hipStream_t stream);
+int free_game(egt_game* g);
 }  // namespace egt
 
 namespace {
@@ -45,6 +49,10 @@ enum Phase { kFree = 0, kQueued, kRunning, kDone };
 struct Slot {
   Phase phase = kFree;
   const egt_game* g = nullptr;
+  egt_game* own_game = nullptr;  // admitted by description: the batch's, tables in the arena
+  std::vector<unsigned char> mx_img;  // its precision-form tables, uploaded by the worker
+  size_t mx_off[2][4] = {};
+  int64_t game_bytes = 0, mx_bytes = 0;  // arena bytes ahead of the state
   egt_solve_opts opts{};
   egt_state* st = nullptr;
   hipStream_t stream = nullptr;  // created with the batch, default priority
@@ -115,9 +123,16 @@ void arena_give(egt_batch* b, int64_t off, int64_t len) {
 void run_slot(egt_batch* b, Slot& sl) {
   hipError_t e = hipSetDevice(b->device);
   int rc = e == hipSuccess ? EGT_OK : hip_fail(e, "hipSetDevice");
+  unsigned char* base = (unsigned char*)b->arena + sl.off;
+  if (rc == EGT_OK && sl.own_game) {
+    // the game's tables (and precision-form tables) into the slot's arena range, on its stream
+    rc = upload_game(sl.own_game, base, false, sl.stream);
+    if (rc == EGT_OK && sl.mx_bytes > 0)
+      rc = mixed_tables_upload(sl.own_game, sl.mx_img, sl.mx_off, base + sl.game_bytes, false, sl.stream);
+  }
   egt_state* st = nullptr;
   if (rc == EGT_OK)
-    rc = state_create_in(sl.g, &sl.opts, sl.stream, (unsigned char*)b->arena + sl.off, sl.host, &st);
+    rc = state_create_in(sl.g, &sl.opts, sl.stream, base + sl.game_bytes + sl.mx_bytes, sl.host, &st);
   bool converged = false;
   if (rc == EGT_OK) rc = solve_loop(st, sl.stream, &b->stop, &converged);
   egt_result res{};
@@ -180,7 +195,8 @@ int egt_batch_create(int64_t budget_bytes, int32_t max_slots, egt_batch** out) {
   b->free_list.push_back(Range{0, b->budget});
   b->slots.resize((size_t)max_slots);
   for (Slot& sl : b->slots) {
-    e = hipStreamCreate(&sl.stream);
+    // non-blocking: the slots' work never orders itself against the null stream
+    e = hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking);
     if (e == hipSuccess)
       e = hipHostMalloc((void**)&sl.host, sizeof(double) * state_host_doubles(), hipHostMallocDefault);
     if (e != hipSuccess) {
@@ -205,6 +221,7 @@ int egt_batch_retire(egt_batch* b, int32_t slot) {
   Slot& sl = b->slots[(size_t)slot];
   if (sl.phase != kDone) return fail(EGT_EINVAL, "only a finished solve can be retired");
   if (sl.st) state_destroy(sl.st);  // its memory stays with the batch
+  if (sl.own_game) free_game(sl.own_game);  // host tables only: its device tables lie in the arena
   arena_give(b, sl.off, sl.bytes);
   b->used -= sl.bytes;
   hipStream_t stream = sl.stream;
@@ -229,6 +246,10 @@ int egt_batch_destroy(egt_batch* b) {
     if (sl.st) {
       state_destroy(sl.st);
       sl.st = nullptr;
+    }
+    if (sl.own_game) {
+      free_game(sl.own_game);
+      sl.own_game = nullptr;
     }
     if (sl.stream) {
       const hipError_t e = hipStreamDestroy(sl.stream);
@@ -263,6 +284,54 @@ int egt_batch_admit(egt_batch* b, const egt_game* g, const egt_solve_opts* opts,
   Slot& sl = b->slots[k];
   sl.phase = kQueued;
   sl.g = g;
+  sl.opts = o;
+  sl.off = off;
+  sl.bytes = need;
+  sl.status = EGT_OK;
+  sl.t0 = std::chrono::steady_clock::now();
+  b->used += need;
+  b->queue.push_back((int)k);
+  b->work_cv.notify_one();
+  *slot = (int32_t)k;
+  return EGT_OK;
+}
+
+int egt_batch_admit_desc(egt_batch* b, const egt_game_desc* desc, const egt_solve_opts* opts, int32_t* slot) {
+  if (!b || !desc || !slot) return fail(EGT_EINVAL, "null argument");
+  *slot = -1;
+  egt_solve_opts o;
+  egt_default_opts(&o);
+  if (opts) o = *opts;
+  const bool mixed = o.precision == EGT_PRECISION_MIXED;
+  // host work only: the betting tree, the tables and (precision form) W
+  egt_game* g = nullptr;
+  int rc = build_game_host(desc, &g);
+  if (rc) return rc;
+  std::vector<unsigned char> mx_img;
+  size_t mx_off[2][4] = {};
+  if (mixed && (rc = mixed_tables_image(g, mx_img, mx_off))) {
+    free_game(g);
+    return rc;
+  }
+  const int64_t gbytes = (int64_t)((game_device_bytes(g) + kAlign - 1) / kAlign * kAlign);
+  const int64_t mbytes = (int64_t)((mx_img.size() + kAlign - 1) / kAlign * kAlign);
+  const int64_t need = gbytes + mbytes + (state_bytes(g, mixed) + kAlign - 1) / kAlign * kAlign;
+  std::lock_guard<std::mutex> lk(b->mu);
+  size_t k = 0;
+  while (k < b->slots.size() && b->slots[k].phase != kFree) ++k;
+  int64_t off = 0;
+  if (k == b->slots.size() || b->used + need > b->budget || !arena_take(b, need, &off)) {
+    free_game(g);
+    return fail(EGT_EBUDGET, k == b->slots.size() ? "no free slot" : "the solve does not fit the memory budget now");
+  }
+  Slot& sl = b->slots[k];
+  sl.phase = kQueued;
+  sl.g = g;
+  sl.own_game = g;
+  sl.mx_img.swap(mx_img);
+  std::memcpy(sl.mx_off, mx_off, sizeof(mx_off));
+  sl.game_bytes = gbytes;
+  sl.mx_bytes = mbytes;
   sl.opts = o;
   sl.off = off;
   sl.bytes = need;

@@ -305,8 +305,10 @@ int hip_fail(hipError_t e, const char* what) {
 }
 const char* last_error_cstr() { return g_last_error.c_str(); }
 
-// Builds every table of a game on the host, then uploads them in one block.
-int build_game(const egt_game_desc* d, hipStream_t stream, egt_game** out) {
+// Builds every table of a game on the host and lays them out as one image
+// (g->img, offsets in g->offs) for a single upload; no device memory is
+// touched.
+int build_game_host(const egt_game_desc* d, egt_game** out) {
   if (!d || !out) return fail(EGT_EINVAL, "null argument");
   *out = nullptr;
   const int n = d->n_hands, cph = d->cards_per_hand, nc = d->n_cards;
@@ -496,6 +498,8 @@ int build_game(const egt_game_desc* d, hipStream_t stream, egt_game** out) {
     b[p].assign(g->ld, 0.0);
     for (int i = 0; i < n; ++i) b[p][i] = d->belief[p][perm[i]];
   }
+  g->hbelief[0] = b[0];
+  g->hbelief[1] = b[1];
   double Z = 0.0;
   for (int i = 0; i < n; ++i) {
     if (b[0][i] == 0.0) continue;
@@ -526,10 +530,7 @@ int build_game(const egt_game_desc* d, hipStream_t stream, egt_game** out) {
     total = align_up(total + std::max<size_t>(bytes, 1), 256);
     return off;
   };
-  struct Offs {
-    size_t first, nact, beta, logn, spar, cbeg, child, tbeg, topp, tkind, tcoef, roots, belief, ftab, trec, anc, titems,
-        snact;
-  } po[2];
+  GameOffsets::Player* po = g->offs.p;
   for (int p = 0; p < 2; ++p) {
     HostPlayer& hp = g->hp[p];
     po[p].first = add(hp.node_first_seq.data(), hp.node_first_seq.size() * sizeof(int));
@@ -551,13 +552,19 @@ int build_game(const egt_game_desc* d, hipStream_t stream, egt_game** out) {
     po[p].titems = add(hp.term_items.data(), hp.term_items.size() * sizeof(TermItem));
     po[p].snact = add(hp.seq_nact.data(), hp.seq_nact.size() * sizeof(int));
   }
-  const size_t o_cbeg = add(card_begin.data(), card_begin.size() * sizeof(int));
-  const size_t o_htab = add(htab.data(), htab.size() * sizeof(uint4));
-  const size_t o_hpos = add(hpos.data(), hpos.size() * sizeof(unsigned));
+  g->offs.cbeg = add(card_begin.data(), card_begin.size() * sizeof(int));
+  g->offs.htab = add(htab.data(), htab.size() * sizeof(uint4));
+  g->offs.hpos = add(hpos.data(), hpos.size() * sizeof(unsigned));
 
-  std::vector<unsigned char> staging(total, 0);
+  g->img.assign(total, 0);
   for (const Piece& pc : pieces)
-    if (pc.bytes) std::memcpy(staging.data() + pc.off, pc.src, pc.bytes);
+    if (pc.bytes) std::memcpy(g->img.data() + pc.off, pc.src, pc.bytes);
+  g->dh.n = n;
+  g->dh.ld = g->ld;
+  g->dh.cph = cph;
+  g->dh.n_cards = nc;
+  g->dh.n_card_slots = card_begin[nc] + nc;
+  g->dh.invZ = 1.0 / Z;
   EGT_HIP(hipGetDevice(&g->device));
   EGT_HIP(hipDeviceGetAttribute(&g->n_cu, hipDeviceAttributeMultiprocessorCount, g->device));
   if (g->n_cu < 1) g->n_cu = 1;
@@ -565,19 +572,22 @@ int build_game(const egt_game_desc* d, hipStream_t stream, egt_game** out) {
   EGT_HIP(hipDeviceGetAttribute(&g->lds_per_cu, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, g->device));
   if (g->lds_per_block < 64 * 1024) g->lds_per_block = 64 * 1024;
   if (g->lds_per_cu < g->lds_per_block) g->lds_per_cu = g->lds_per_block;
-  void* dev = nullptr;
-  hipError_t e = hipMalloc(&dev, total);
-  if (e != hipSuccess) return fail(EGT_ENOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
+  *out = guard.release();
+  return EGT_OK;
+}
+
+size_t game_device_bytes(const egt_game* g) { return g->img.size(); }
+
+// Copies the table image into `dev` (game_device_bytes(g) bytes, 256-byte
+// aligned, owned by the caller when owned == false) on `stream` and points
+// the device views at it.  The host image must stay until the copy is done.
+int upload_game(egt_game* g, void* dev, bool owned, hipStream_t stream) {
   g->mem.base = dev;
-  g->mem.bytes = total;
-  e = hipMemcpyAsync(dev, staging.data(), total, hipMemcpyHostToDevice, stream);
-  if (e == hipSuccess) e = hipStreamSynchronize(stream);
-  if (e != hipSuccess) {
-    (void)hipFree(dev);
-    g->mem.base = nullptr;
-    return hip_fail(e, "upload of game tables");
-  }
+  g->mem.bytes = g->img.size();
+  g->owns_mem = owned;
+  EGT_HIP(hipMemcpyAsync(dev, g->img.data(), g->img.size(), hipMemcpyHostToDevice, stream));
   auto at = [&](size_t off) { return (const void*)((const unsigned char*)dev + off); };
+  const GameOffsets::Player* po = g->offs.p;
   for (int p = 0; p < 2; ++p) {
     HostPlayer& hp = g->hp[p];
     DPlayer& dp = g->dp[p];
@@ -606,16 +616,33 @@ int build_game(const egt_game_desc* d, hipStream_t stream, egt_game** out) {
     dp.term_items = dp.n_items > 0 ? (const TermItem*)at(po[p].titems) : nullptr;
     dp.seq_nact = (const int*)at(po[p].snact);
   }
-  DHands& dh = g->dh;
-  dh.n = n;
-  dh.ld = g->ld;
-  dh.cph = cph;
-  dh.n_cards = nc;
-  dh.n_card_slots = card_begin[nc] + nc;
-  dh.card_begin = (const int*)at(o_cbeg);
-  dh.htab = (const uint4*)at(o_htab);
-  dh.hpos = (const unsigned*)at(o_hpos);
-  dh.invZ = 1.0 / Z;
+  g->dh.card_begin = (const int*)at(g->offs.cbeg);
+  g->dh.htab = (const uint4*)at(g->offs.htab);
+  g->dh.hpos = (const unsigned*)at(g->offs.hpos);
+  return EGT_OK;
+}
+
+// Host tables, one device block, upload, synchronise.
+int build_game(const egt_game_desc* d, hipStream_t stream, egt_game** out) {
+  if (!out) return fail(EGT_EINVAL, "null argument");
+  *out = nullptr;
+  egt_game* g = nullptr;
+  int rc = build_game_host(d, &g);
+  if (rc) return rc;
+  std::unique_ptr<egt_game> guard(g);
+  void* dev = nullptr;
+  hipError_t e = hipMalloc(&dev, game_device_bytes(g));
+  if (e != hipSuccess) return fail(EGT_ENOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
+  rc = upload_game(g, dev, true, stream);
+  if (rc == EGT_OK) {
+    e = hipStreamSynchronize(stream);
+    if (e != hipSuccess) rc = hip_fail(e, "upload of game tables");
+  }
+  if (rc) {
+    (void)hipFree(dev);
+    g->mem.base = nullptr;
+    return rc;
+  }
   *out = guard.release();
   return EGT_OK;
 }
@@ -623,10 +650,11 @@ int build_game(const egt_game_desc* d, hipStream_t stream, egt_game** out) {
 int free_game(egt_game* g) {
   if (!g) return EGT_OK;
   int st = EGT_OK;
-  if (g->mem.base || g->ws.block || g->ws.hscal || g->mx.block) {
+  const bool dev_owned = (g->mem.base && g->owns_mem) || (g->mx.block && g->mx.owned);
+  if (dev_owned || g->ws.block || g->ws.hscal) {
     hipError_t e = hipDeviceSynchronize();
-    if (e == hipSuccess && g->mem.base) e = hipFree(g->mem.base);
-    if (e == hipSuccess && g->mx.block) e = hipFree(g->mx.block);
+    if (e == hipSuccess && g->mem.base && g->owns_mem) e = hipFree(g->mem.base);
+    if (e == hipSuccess && g->mx.block && g->mx.owned) e = hipFree(g->mx.block);
     if (e == hipSuccess && g->ws.block) e = hipFree(g->ws.block);
     if (e == hipSuccess && g->ws.hscal) e = hipHostFree(g->ws.hscal);
     if (e != hipSuccess) st = hip_fail(e, "free_game");

@@ -195,6 +195,7 @@ enum Prec { kF64 = 0, kF32 = 1 };
 // ---------------------------------------------------------------------------
 struct HostPlayer {
   int n_seq = 0, n_nodes = 0, n_levels = 0, max_chain = 0, max_terms_per_seq = 0, max_level_width = 0;
+  int n_show_cols = 0;  // showdown columns of the precision form (set when its tables are built)
   std::vector<int> node_first_seq, node_nact, node_level;
   std::vector<double> node_beta, node_logn;
   std::vector<int> level_begin;  // [n_levels + 1]
@@ -211,9 +212,18 @@ struct HostPlayer {
   std::vector<std::string> seq_keys;
 };
 
-struct DeviceBlock {  // one hipMalloc holding many tables
+struct DeviceBlock {  // one device allocation holding many tables
   void* base = nullptr;
   size_t bytes = 0;
+};
+
+// Offsets of every table in a game's upload image.
+struct GameOffsets {
+  struct Player {
+    size_t first, nact, beta, logn, spar, cbeg, child, tbeg, topp, tkind, tcoef, roots, belief, ftab, trec, anc,
+        titems, snact;
+  } p[2];
+  size_t cbeg, htab, hpos;
 };
 
 // Scratch of the single-operation entry points (egt_smoothed_br,
@@ -233,6 +243,7 @@ struct Workspace {
 // order, padded to kpad x kpad, and per player the showdown columns.
 struct MixedTables {
   void* block = nullptr;
+  bool owned = true;  // false: the block lies in a serving batch's arena
   int kpad = 0;
   const unsigned short* W = nullptr;
   int L[2] = {0, 0};
@@ -254,9 +265,13 @@ struct egt_game {
   egt::HostPlayer hp[2];
   std::vector<int> perm;  // slot -> caller hand index
   std::vector<int> slot_cards, slot_strength;  // cards [n * cph] and strengths [n] in slot order
+  std::vector<double> hbelief[2];              // priors in slot order, [ld]
   egt::DPlayer dp[2];
   egt::DHands dh;
   egt::DeviceBlock mem;
+  bool owns_mem = true;            // false: mem lies in a serving batch's arena
+  std::vector<unsigned char> img;  // the tables' upload image
+  egt::GameOffsets offs;
   egt::Workspace ws;
   egt::MixedTables mx;
   int device = 0;
@@ -316,6 +331,11 @@ hipError_t launch_gradient_fold_f32(const egt_game* g, int player, const float* 
 // Precision form: W and the showdown columns (once per game); the product
 // fold part (FP32 O(n)) + showdown part (BF16 hi/lo MFMA GEMM, FP32 output).
 int ensure_mixed_tables(const egt_game* g);
+// The same tables as a host image (no device work): its size, then the upload
+// into caller memory (owned = false: the memory is not the game's to free).
+int mixed_tables_image(const egt_game* g, std::vector<unsigned char>& img, size_t off[2][4]);
+int mixed_tables_upload(egt_game* g, const std::vector<unsigned char>& img, const size_t off[2][4], void* dev,
+                        bool owned, hipStream_t s);
 hipError_t launch_show_gemm(const egt_game* g, int player, const float* v_opp, float* grad_out, hipStream_t s);
 hipError_t launch_gradient_mixed(const egt_game* g, int player, const float* v_opp, float* grad_out, hipStream_t s);
 

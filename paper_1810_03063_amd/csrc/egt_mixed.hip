@@ -337,11 +337,10 @@ __global__ __launch_bounds__(256) void show_gemm_tiled_kernel(GemmArgs a) {
 
 }  // namespace
 
-// Builds W (BF16 bits) and the per-player showdown column lists on the host
-// and uploads them.  Called once per game on the first precision-form use.
-int ensure_mixed_tables(const egt_game* cg) {
-  egt_game* g = const_cast<egt_game*>(cg);  // cached tables owned by the game
-  if (g->mx.block) return EGT_OK;
+// W (BF16 bits) and the per-player showdown column lists as one host image:
+// W at 0, then per player the FP32 prior (off[p][3]) and the column lists
+// (own sequence off[p][0], opponent sequence off[p][1], chips off[p][2]).
+int mixed_tables_image(const egt_game* g, std::vector<unsigned char>& img, size_t off[2][4]) {
   const int n = g->n;
   const int kpad = g->ld;  // rows and columns padded like every vector
   // slot order: strength ascending; compatibility from the cards of the slots
@@ -374,55 +373,81 @@ int ensure_mixed_tables(const egt_game* cg) {
   }
   // FP32 copies of the priors (the reach b v is formed in FP32)
   std::vector<float> b32[2];
-  for (int p = 0; p < 2; ++p) {
-    std::vector<double> b64((size_t)g->ld);
-    const hipError_t e = hipMemcpy(b64.data(), g->dp[p].belief, sizeof(double) * b64.size(), hipMemcpyDeviceToHost);
-    if (e != hipSuccess) return hip_fail(e, "read-back of the priors");
-    b32[p].assign(b64.begin(), b64.end());
-  }
-  size_t bytes = sizeof(unsigned short) * W.size();
+  for (int p = 0; p < 2; ++p) b32[p].assign(g->hbelief[p].begin(), g->hbelief[p].end());
   auto al = [](size_t x) { return (x + 255) / 256 * 256; };
-  size_t off_cols[2][3], off_b32[2];
-  size_t total = al(bytes);
+  const size_t wbytes = sizeof(unsigned short) * W.size();
+  size_t total = al(wbytes);
   for (int p = 0; p < 2; ++p) {
-    off_b32[p] = total;
+    off[p][3] = total;
     total += al(sizeof(float) * b32[p].size());
   }
   for (int p = 0; p < 2; ++p) {
-    off_cols[p][0] = total;
+    off[p][0] = total;
     total += al(sizeof(int) * std::max<size_t>(own[p].size(), 1));
-    off_cols[p][1] = total;
+    off[p][1] = total;
     total += al(sizeof(int) * std::max<size_t>(opp[p].size(), 1));
-    off_cols[p][2] = total;
+    off[p][2] = total;
     total += al(sizeof(double) * std::max<size_t>(coef[p].size(), 1));
   }
-  std::vector<unsigned char> staging(total, 0);
-  std::memcpy(staging.data(), W.data(), bytes);
-  for (int p = 0; p < 2; ++p) std::memcpy(staging.data() + off_b32[p], b32[p].data(), sizeof(float) * b32[p].size());
+  img.assign(total, 0);
+  std::memcpy(img.data(), W.data(), wbytes);
   for (int p = 0; p < 2; ++p) {
+    std::memcpy(img.data() + off[p][3], b32[p].data(), sizeof(float) * b32[p].size());
     if (!own[p].empty()) {
-      std::memcpy(staging.data() + off_cols[p][0], own[p].data(), sizeof(int) * own[p].size());
-      std::memcpy(staging.data() + off_cols[p][1], opp[p].data(), sizeof(int) * opp[p].size());
-      std::memcpy(staging.data() + off_cols[p][2], coef[p].data(), sizeof(double) * coef[p].size());
+      std::memcpy(img.data() + off[p][0], own[p].data(), sizeof(int) * own[p].size());
+      std::memcpy(img.data() + off[p][1], opp[p].data(), sizeof(int) * opp[p].size());
+      std::memcpy(img.data() + off[p][2], coef[p].data(), sizeof(double) * coef[p].size());
     }
   }
+  for (int p = 0; p < 2; ++p) const_cast<egt_game*>(g)->hp[p].n_show_cols = (int)own[p].size();
+  return EGT_OK;
+}
+
+int mixed_tables_upload(egt_game* g, const std::vector<unsigned char>& img, const size_t off[2][4], void* dev,
+                        bool owned, hipStream_t s) {
+  EGT_HIP(hipMemcpyAsync(dev, img.data(), img.size(), hipMemcpyHostToDevice, s));
+  g->mx.kpad = g->ld;
+  g->mx.W = (const unsigned short*)dev;
+  for (int p = 0; p < 2; ++p) {
+    g->mx.L[p] = g->hp[p].n_show_cols;
+    g->mx.col_own[p] = (const int*)((unsigned char*)dev + off[p][0]);
+    g->mx.col_opp[p] = (const int*)((unsigned char*)dev + off[p][1]);
+    g->mx.col_coef[p] = (const double*)((unsigned char*)dev + off[p][2]);
+    g->mx.belief32[p] = (const float*)((unsigned char*)dev + off[p][3]);
+  }
+  g->mx.owned = owned;
+  g->mx.block = dev;
+  return EGT_OK;
+}
+
+// Builds and uploads the precision-form tables once per game, on first use
+// (synchronous upload).
+int ensure_mixed_tables(const egt_game* cg) {
+  egt_game* g = const_cast<egt_game*>(cg);  // cached tables owned by the game
+  if (g->mx.block) return EGT_OK;
+  std::vector<unsigned char> img;
+  size_t off[2][4];
+  int rc = mixed_tables_image(g, img, off);
+  if (rc) return rc;
   void* dev = nullptr;
-  hipError_t e = hipMalloc(&dev, total);
+  hipError_t e = hipMalloc(&dev, img.size());
   if (e != hipSuccess) return fail(EGT_ENOMEM, std::string("hipMalloc (precision tables): ") + hipGetErrorString(e));
-  e = hipMemcpy(dev, staging.data(), total, hipMemcpyHostToDevice);
+  e = hipMemcpy(dev, img.data(), img.size(), hipMemcpyHostToDevice);
   if (e != hipSuccess) {
     (void)hipFree(dev);
     return hip_fail(e, "upload of precision tables");
   }
-  g->mx.kpad = kpad;
+  // the image is on the device now: point the tables at it (no second copy)
+  g->mx.kpad = g->ld;
   g->mx.W = (const unsigned short*)dev;
   for (int p = 0; p < 2; ++p) {
-    g->mx.L[p] = (int)own[p].size();
-    g->mx.col_own[p] = (const int*)((unsigned char*)dev + off_cols[p][0]);
-    g->mx.col_opp[p] = (const int*)((unsigned char*)dev + off_cols[p][1]);
-    g->mx.col_coef[p] = (const double*)((unsigned char*)dev + off_cols[p][2]);
-    g->mx.belief32[p] = (const float*)((unsigned char*)dev + off_b32[p]);
+    g->mx.L[p] = g->hp[p].n_show_cols;
+    g->mx.col_own[p] = (const int*)((unsigned char*)dev + off[p][0]);
+    g->mx.col_opp[p] = (const int*)((unsigned char*)dev + off[p][1]);
+    g->mx.col_coef[p] = (const double*)((unsigned char*)dev + off[p][2]);
+    g->mx.belief32[p] = (const float*)((unsigned char*)dev + off[p][3]);
   }
+  g->mx.owned = true;
   g->mx.block = dev;
   return EGT_OK;
 }

@@ -177,21 +177,6 @@ __global__ __launch_bounds__(2 * kGroupThreads, MINW) void product_kernel(ProdAr
   double acc[HPT];
 #pragma unroll
   for (int k = 0; k < HPT; ++k) acc[k] = 0.0;
-  // A finished unit's row is stored at the start of the next round, so that
-  // the wait for the next opponent row (at the top of a round) does not also
-  // wait for those stores to complete; until then the accumulators hold it.
-  int pend_row = -1;
-  auto flush = [&]() {
-    if (pend_row >= 0) {
-      TO* row = a.out + (size_t)pend_row * ld;
-#pragma unroll
-      for (int k = 0; k < HPT; ++k)
-        if (k < cnt) row[beg + k] = (TO)(acc[k] * ((TAB ? bown_l[beg + k] : bown[k]) * a.H.invZ));
-      for (int i = n + gt; i < ld; i += kGroupThreads) row[i] = (TO)0;
-    }
-    pend_row = -1;
-  };
-
   while (w < n_work) {
     // uniform within a group
     const bool active = tr.kind >= 0 && !(a.fold_only && tr.kind != 0);
@@ -210,13 +195,7 @@ __global__ __launch_bounds__(2 * kGroupThreads, MINW) void product_kernel(ProdAr
         }
       }
     }
-    // the previous unit's row, then the next round's opponent row and the
-    // terminal two rounds ahead, all in flight while this round runs
-    if (pend_row >= 0) {
-      flush();
-#pragma unroll
-      for (int k = 0; k < HPT; ++k) acc[k] = 0.0;
-    }
+    // the next round's row, and the terminal two rounds ahead, loaded while this round runs
     load_row(tr1, vv);
     int w2 = w1, rd2 = rd1;
     advance(w2, rd2);
@@ -330,11 +309,15 @@ __global__ __launch_bounds__(2 * kGroupThreads, MINW) void product_kernel(ProdAr
             if (k < cnt) acc[k] += R1[beg + k];
         }
       }
-      pend_row = (!combine || grp == 0) ? s_out : -1;
-      if (pend_row < 0) {
+      if ((!combine || grp == 0) && s_out >= 0) {
+        TO* row = a.out + (size_t)s_out * ld;
 #pragma unroll
-        for (int k = 0; k < HPT; ++k) acc[k] = 0.0;
+        for (int k = 0; k < HPT; ++k)
+          if (k < cnt) row[beg + k] = (TO)(acc[k] * ((TAB ? bown_l[beg + k] : bown[k]) * a.H.invZ));
+        for (int i = n + gt; i < ld; i += kGroupThreads) row[i] = (TO)0;
       }
+#pragma unroll
+      for (int k = 0; k < HPT; ++k) acc[k] = 0.0;
     }
     __syncthreads();  // the next round rewrites R and E of both groups
     w = w1;
@@ -350,7 +333,6 @@ __global__ __launch_bounds__(2 * kGroupThreads, MINW) void product_kernel(ProdAr
     s1 = s2;
     comb1 = comb2;
   }
-  flush();
 }
 
 size_t align2(size_t x) { return (x + 1) / 2 * 2; }

@@ -130,6 +130,8 @@ _batch_tick = _decl("egt_batch_tick", ctypes.c_int, _p, ctypes.POINTER(_i32), ct
 _batch_poll = _decl("egt_batch_poll", ctypes.c_int, _p, _i32, ctypes.POINTER(_i32), ctypes.POINTER(_i32),
                     ctypes.POINTER(SolveResult))
 _batch_retire = _decl("egt_batch_retire", ctypes.c_int, _p, _i32)
+_batch_admit_desc = _decl("egt_batch_admit_desc", ctypes.c_int, _p, ctypes.POINTER(GameDesc),
+                          ctypes.POINTER(SolveOpts), ctypes.POINTER(_i32))
 _batch_strategies = _decl("egt_batch_strategies", ctypes.c_int, _p, _i32, _p, _p, _p)
 _batch_usage = _decl("egt_batch_usage", ctypes.c_int, _p, ctypes.POINTER(_i64), ctypes.POINTER(_i32),
                      ctypes.POINTER(_i32))
@@ -143,7 +145,7 @@ EXPORTED = [
     "egt_state_bytes", "egt_batch_create", "egt_batch_destroy", "egt_batch_admit", "egt_batch_tick",
     "egt_batch_poll", "egt_batch_retire", "egt_batch_usage", "egt_saddle_gap_noalloc",
     "egt_batch_strategies", "egt_cfr_create", "egt_cfr_destroy", "egt_cfr_step", "egt_cfr_gap", "egt_cfr_get",
-    "egt_cfr_solve", "egt_fom_create", "egt_fom_destroy", "egt_fom_step", "egt_fom_get", "egt_fom_gap",
+    "egt_cfr_solve", "egt_batch_admit_desc", "egt_fom_create", "egt_fom_destroy", "egt_fom_step", "egt_fom_get", "egt_fom_gap",
 ]
 
 
@@ -169,45 +171,53 @@ def _dptr(t, shape=None, dtype=torch.float64):
     return ctypes.c_void_p(t.data_ptr())
 
 
+def game_desc(inst):
+    """egt_game_desc of an instance, and the host arrays it points into (keep
+    them alive while the description is in use)."""
+    cards = np.ascontiguousarray(inst.hand_cards, dtype=np.int32)
+    strength = np.ascontiguousarray(inst.strength, dtype=np.int32)
+    b = [np.ascontiguousarray(inst.belief[p], dtype=np.float64) for p in (0, 1)]
+    fr = np.ascontiguousarray(inst.bet_fracs, dtype=np.float64)
+    d = GameDesc()
+    d.n_cards = inst.n_cards
+    d.cards_per_hand = inst.cards_per_hand
+    d.n_hands = inst.n_hands
+    d.hand_cards = cards.ctypes.data
+    d.strength = strength.ctypes.data
+    d.belief[0] = b[0].ctypes.data
+    d.belief[1] = b[1].ctypes.data
+    d.pot = inst.pot
+    d.stack = inst.stack
+    d.n_bet_fracs = len(fr)
+    d.bet_fracs = fr.ctypes.data if len(fr) else None
+    d.allin = 1 if inst.allin else 0
+    d.max_raises = inst.max_raises
+    keep = [cards, strength, b, fr]
+    ab = getattr(inst, "abstraction", None)
+    if ab is not None:
+        a = BetAbstraction()
+        for p in (0, 1):
+            a.open_fold[p] = 1 if ab.open_fold[p] else 0
+            for k in range(4):
+                fr_k = np.ascontiguousarray(ab.fracs[p][k], dtype=np.float64)
+                keep.append(fr_k)
+                a.n_fracs[p][k] = len(fr_k)
+                a.fracs[p][k] = fr_k.ctypes.data if len(fr_k) else None
+                a.allin[p][k] = 1 if ab.allin[p][k] else 0
+        keep.append(a)
+        d.abstraction = ctypes.pointer(a)
+    return d, keep
+
+
 class Game:
     """A river endgame uploaded to the current device (egt_build_game)."""
 
     def __init__(self, inst, stream=None):
         self._h = None
-        cards = np.ascontiguousarray(inst.hand_cards, dtype=np.int32)
-        strength = np.ascontiguousarray(inst.strength, dtype=np.int32)
-        b = [np.ascontiguousarray(inst.belief[p], dtype=np.float64) for p in (0, 1)]
-        fr = np.ascontiguousarray(inst.bet_fracs, dtype=np.float64)
-        d = GameDesc()
-        d.n_cards = inst.n_cards
-        d.cards_per_hand = inst.cards_per_hand
-        d.n_hands = inst.n_hands
-        d.hand_cards = cards.ctypes.data
-        d.strength = strength.ctypes.data
-        d.belief[0] = b[0].ctypes.data
-        d.belief[1] = b[1].ctypes.data
-        d.pot = inst.pot
-        d.stack = inst.stack
-        d.n_bet_fracs = len(fr)
-        d.bet_fracs = fr.ctypes.data if len(fr) else None
-        d.allin = 1 if inst.allin else 0
-        d.max_raises = inst.max_raises
-        keep = []  # host arrays that must live until egt_build_game returns
-        ab = getattr(inst, "abstraction", None)
-        if ab is not None:
-            a = BetAbstraction()
-            for p in (0, 1):
-                a.open_fold[p] = 1 if ab.open_fold[p] else 0
-                for k in range(4):
-                    fr_k = np.ascontiguousarray(ab.fracs[p][k], dtype=np.float64)
-                    keep.append(fr_k)
-                    a.n_fracs[p][k] = len(fr_k)
-                    a.fracs[p][k] = fr_k.ctypes.data if len(fr_k) else None
-                    a.allin[p][k] = 1 if ab.allin[p][k] else 0
-            keep.append(a)
-            d.abstraction = ctypes.pointer(a)
+        d, keep = game_desc(inst)
         h = _p()
         _check(_build_game(ctypes.byref(d), _stream(stream), ctypes.byref(h)))
+        del keep
         self._h = h
         self.inst = inst
         self.pot = inst.pot
@@ -447,6 +457,19 @@ class Batch:
         o = make_opts(**opts)
         slot = _i32()
         rc = _batch_admit(self._h, game.handle, ctypes.byref(o), ctypes.byref(slot))
+        if rc == -6:
+            return None
+        _check(rc)
+        return slot.value
+
+    def admit_desc(self, inst, **opts):
+        """Admission by description (the batch builds the game in its arena):
+        slot index, or None when it does not fit the budget / slots now."""
+        o = make_opts(**opts)
+        d, keep = game_desc(inst)
+        slot = _i32()
+        rc = _batch_admit_desc(self._h, ctypes.byref(d), ctypes.byref(o), ctypes.byref(slot))
+        del keep
         if rc == -6:
             return None
         _check(rc)

@@ -114,26 +114,18 @@ def serve_sequential(solve_one, requests, clock=time.perf_counter, sleep=time.sl
 
 
 class LibEngine:
-    """egt_batch_* engine: builds each request's game at admission (host
-    tables + upload), keeps it until the request is retired."""
+    """egt_batch_* engine: each request is admitted by its description; the
+    batch builds the game's tables into its own arena (charged to the budget
+    with the solve's state), so admission and retirement allocate and
+    synchronise nothing on the device."""
 
     def __init__(self, egt_module, budget_bytes, max_slots=64, **solve_opts):
         self.egt = egt_module
         self.batch = egt_module.Batch(budget_bytes, max_slots)
         self.opts = solve_opts
-        self.games = {}
-        self._next_game = None
 
     def admit(self, req):
-        if self._next_game is None or self._next_game[0] is not req:
-            self._next_game = (req, self.egt.Game(req.payload))
-        game = self._next_game[1]
-        slot = self.batch.admit(game, **self.opts)
-        if slot is None:
-            return None
-        self.games[slot] = game
-        self._next_game = None
-        return slot
+        return self.batch.admit_desc(req.payload, **self.opts)
 
     def tick(self):
         return self.batch.tick()
@@ -143,7 +135,6 @@ class LibEngine:
 
     def retire(self, slot):
         self.batch.retire(slot)
-        self.games.pop(slot).close()
 
     def live(self):
         return self.batch.usage()[1]

@@ -148,3 +148,33 @@ def test_batched_solve_verified_by_oracle(egt, prec, ge):
     with pytest.raises(egt.EgtError):
         b.strategies(slots[0], games[0])  # retired
     b.close()
+
+
+def test_admission_by_description_matches_lone_solves(egt):
+    """egt_batch_admit_desc builds each game into the batch's arena; every
+    result is bitwise the lone egt_solve's on a separately built game, the
+    game's bytes are charged with the state's, and retiring frees them."""
+    cases = [("c0", 8, "fp64", 1), ("lib_micro", 2, "mixed", 5), ("c1", 3, "fp64", 1), ("c0", 9, "mixed", 10)]
+    insts = [make_instance(c, s) for c, s, _, _ in cases]
+    alone = []
+    for inst, (c, s, prec, ge) in zip(insts, cases):
+        G = egt.Game(inst)
+        r, _ = egt.solve(G, precision=prec, gap_every=ge)
+        alone.append((r, egt.state_bytes(G, precision=prec)))
+        G.close()
+    print("[case] admission by description", flush=True)
+    b = egt.Batch(budget_bytes=4 << 30, max_slots=8)
+    slots = [b.admit_desc(inst, precision=prec, gap_every=ge) for inst, (c, s, prec, ge) in zip(insts, cases)]
+    assert None not in slots
+    used = b.usage()[0]
+    assert used > sum(sb for _, sb in alone)  # the games' tables are charged too
+    while b.usage()[1] > 0:
+        b.tick()
+    for slot, (r, _), (c, s, prec, _) in zip(slots, alone, cases):
+        status, m = b.poll(slot)
+        assert status == r["status"] == "EGT_OK"
+        for k in ("iters", "backtracks", "products", "gap", "value_p1", "mu_x", "mu_y", "tau"):
+            assert m[k] == r[k], (c, s, prec, k, m[k], r[k])
+        b.retire(slot)
+    assert b.usage() == (0, 0, 0)
+    b.close()
