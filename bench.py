@@ -42,6 +42,9 @@ CSRC = os.path.join(ROOT, "paper_1810_03063_amd", "csrc")
 COUNTERS = {
     ("sbr_fused_kernel", "c1"): dict(fetch_kib=1133.5, write_kib=1895.5, fetch_factor=2.0, write_factor=1.0,
                                      source="egt_kernels.hip", sha256=None),
+    ("product_kernel", "c3"): dict(fetch_kib=25837.9, write_kib=50473.4, fetch_factor=2.0, write_factor=1.0,
+                                   source="egt_product.hip",
+                                   sha256="36a52d7905ed8d07af55c0094c68d1b8ccf3effe85b6c59359a151d8f8445dfb"),
 }
 
 
@@ -110,7 +113,7 @@ def _timed(torch, fn, reps):
 
 
 def product_roofline(egt, torch, G, reps, config):
-    """The payoff product (gradient_kernel), A y at the uniform point.
+    """The payoff product (product_kernel), A y at the uniform point.
     Algorithmic bytes: one opponent row per terminal read and one output row
     per sequence written, 8-byte doubles over the n hands."""
     y = egt.uniform(G, 1)
@@ -119,8 +122,8 @@ def product_roofline(egt, torch, G, reps, config):
     n_fold, n_show = G.terminals()
     bytes_ = 8.0 * G.n * ((n_fold + n_show) + G.n_seq[0])
     gbs = bytes_ / avg_s / 1e9
-    traffic = traffic_bytes("gradient_kernel", config)
-    return dict(kernel="gradient_kernel", bound="hbm", achieved=round(gbs, 3), peak=HBM_PEAK_GBS, unit="GB/s",
+    traffic = traffic_bytes("product_kernel", config)
+    return dict(kernel="product_kernel", bound="hbm", achieved=round(gbs, 3), peak=HBM_PEAK_GBS, unit="GB/s",
                 frac=round(gbs / HBM_PEAK_GBS, 6), traffic=round(traffic) if traffic else None,
                 avg_us=round(avg_s * 1e6, 3), algorithmic_bytes=int(bytes_),
                 launch="egt_gradient, player 0 (A y): one opponent row read per terminal, one row written per "

@@ -742,19 +742,31 @@ __global__ __launch_bounds__(kPassThreads) void uniform_kernel(UniformArgs a) {
   a.out[(size_t)s * a.ld + h] = h < a.n ? val : 0.0;
 }
 
-constexpr int kRedThreads = 1024;
-
-__global__ __launch_bounds__(kRedThreads) void max_abs_kernel(int64_t count, const double* X, double* out) {
-  __shared__ double scratch[kRedThreads];
-  double m = 0.0;
-  for (int64_t i = threadIdx.x; i < count; i += kRedThreads) m = fmax(m, fabs(X[i]));
-  scratch[threadIdx.x] = m;
-  __syncthreads();
-  for (int w = kRedThreads / 2; w > 0; w >>= 1) {
-    if ((int)threadIdx.x < w) scratch[threadIdx.x] = fmax(scratch[threadIdx.x], scratch[threadIdx.x + w]);
-    __syncthreads();
+// max |X| into *out, which holds +0.0 beforehand.  |x| >= 0, so the bit
+// patterns order as the values do; a NaN (positive after fabs) orders above
+// every number and so reaches the result instead of being skipped.
+__global__ __launch_bounds__(256) void max_abs_kernel(int64_t count, const double* X, unsigned long long* out) {
+  __shared__ unsigned long long wmax[4];
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  unsigned long long m = 0;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += stride) {
+    const unsigned long long b = (unsigned long long)__double_as_longlong(fabs(X[i]));
+    m = b > m ? b : m;
   }
-  if (threadIdx.x == 0) out[0] = scratch[0];
+  for (int off = 32; off > 0; off >>= 1) {
+    const unsigned long long o = __shfl_xor(m, off);
+    m = o > m ? o : m;
+  }
+  if ((threadIdx.x & 63) == 0) wmax[threadIdx.x >> 6] = m;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int w = 1; w < 4; ++w) m = wmax[w] > m ? wmax[w] : m;
+    atomicMax(out, m);
+  }
+}
+
+__global__ __launch_bounds__(64) void zero_kernel(double* p) {
+  if (threadIdx.x == 0) p[0] = 0.0;
 }
 
 template <class T>
@@ -983,7 +995,9 @@ hipError_t launch_convert(int64_t count, const void* in, Prec in_prec, void* out
 }
 
 hipError_t launch_max_abs(int64_t count, const double* X, double* out, hipStream_t s) {
-  hipLaunchKernelGGL(max_abs_kernel, dim3(1), dim3(kRedThreads), 0, s, count, X, out);
+  hipLaunchKernelGGL(zero_kernel, dim3(1), dim3(64), 0, s, out);
+  const unsigned blocks = (unsigned)std::max<int64_t>(1, std::min<int64_t>((count + 255) / 256, 2048));
+  hipLaunchKernelGGL(max_abs_kernel, dim3(blocks), dim3(256), 0, s, count, X, (unsigned long long*)out);
   return hipGetLastError();
 }
 

@@ -356,7 +356,8 @@ int state_create_in(const egt_game* g, const egt_solve_opts* o, hipStream_t s, v
     EGT_TRY(launch_max_abs(vec_elems(g, 1), st->G64[1], st->dscal + 1, s));
     if ((rc = fetch(st, 2, s))) return rc;
     const double m0 = 1e-3 * std::max(st->hscal[0], st->hscal[1]) / g->max_beta;
-    if (!(m0 > 0)) return fail(EGT_ENUMERIC, "automatic mu is zero (all-zero payoffs?)");
+    if (!(m0 > 0) || !std::isfinite(m0))
+      return fail(EGT_ENUMERIC, "automatic mu is zero or not finite (all-zero or non-finite payoffs?)");
     st->mu[0] = st->mu[1] = m0;
   } else {
     st->mu[0] = opts.mu0_x;
