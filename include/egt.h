@@ -122,6 +122,39 @@ typedef struct {
  * actions, all-zero beliefs or no compatible deal). */
 int egt_build_game(const egt_game_desc* desc, hipStream_t stream, egt_game** out);
 
+/* A general two-player zero-sum extensive-form game in sequence form
+ * (Section 3's treeplexes, Definition 2; Section 6's route through an
+ * explicit sparse payoff matrix).  All arrays are HOST memory, read during
+ * the call only.
+ * n_infosets[p]         player p's information sets (simplexes), >= 1.
+ * parent_seq[p][k]      the sequence leading to information set k, -1 for the
+ *                       empty sequence; it must belong to an earlier set.
+ * n_actions[p][k]       1 .. 16.  Player p's sequences are numbered set by
+ *                       set: set k owns first_k .. first_k + n_actions - 1,
+ *                       first_k = the sum of the earlier sets' n_actions.
+ * a_row, a_col, a_val   nnz triples (player-1 sequence, player-2 sequence,
+ *                       value) of A = player 2's expected payoff (player 1's
+ *                       loss), chance folded in; repeated pairs add up.
+ * scale                 payoff scale (> 0): egt_solve's default target gap
+ *                       is 1e-3 * scale.
+ * The game runs with one live slot per row (n_hands = 1) through every
+ * FP64 entry point; the products use a CSR SpMV instead of the river
+ * kernels.  The precision form and serving admission by description are
+ * river-only (EGT_EINVAL).  Layout keys are the caller's sequence indices in
+ * decimal.  Synchronises `stream`.  EGT_EINVAL on a bad description. */
+typedef struct {
+  int32_t n_infosets[2];
+  const int32_t* parent_seq[2];
+  const int32_t* n_actions[2];
+  int64_t nnz;
+  const int32_t* a_row;
+  const int32_t* a_col;
+  const double* a_val;
+  double scale;
+} egt_general_desc;
+
+int egt_build_general_game(const egt_general_desc* desc, hipStream_t stream, egt_game** out);
+
 /* Releases a game (synchronises the device first).  NULL is accepted. */
 int egt_free_game(egt_game* game);
 

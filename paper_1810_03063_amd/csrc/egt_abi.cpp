@@ -10,6 +10,7 @@
 
 namespace egt {
 int build_game(const egt_game_desc* d, hipStream_t stream, egt_game** out);
+int build_general_game(const egt_general_desc* d, hipStream_t stream, egt_game** out);
 int free_game(egt_game* g);
 const char* last_error_cstr();
 int state_create(const egt_game* g, const egt_solve_opts* o, hipStream_t s, egt_state** out);
@@ -95,6 +96,10 @@ void egt_default_opts(egt_solve_opts* o) {
 
 int egt_build_game(const egt_game_desc* desc, hipStream_t stream, egt_game** out) {
   return guarded([&]() -> int { return build_game(desc, stream, out); });
+}
+
+int egt_build_general_game(const egt_general_desc* desc, hipStream_t stream, egt_game** out) {
+  return guarded([&]() -> int { return build_general_game(desc, stream, out); });
 }
 
 int egt_free_game(egt_game* game) {

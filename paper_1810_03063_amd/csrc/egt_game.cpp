@@ -305,6 +305,73 @@ int hip_fail(hipError_t e, const char* what) {
 }
 const char* last_error_cstr() { return g_last_error.c_str(); }
 
+// The upload image of every table (one device block), the device views' sizes
+// and the device attributes the launchers use.
+int finish_image(egt_game* g, const std::vector<int>& card_begin, const std::vector<uint4>& htab,
+                 const std::vector<unsigned>& hpos, const std::vector<double> (&b)[2]) {
+  const int n = g->n, cph = g->cph, nc = g->n_cards;
+  const double Z = g->Z;
+  struct Piece {
+    const void* src;
+    size_t bytes;
+    size_t off;
+  };
+  std::vector<Piece> pieces;
+  size_t total = 0;
+  auto add = [&](const void* src, size_t bytes) {
+    const size_t off = total;
+    pieces.push_back({src, bytes, off});
+    total = align_up(total + std::max<size_t>(bytes, 1), 256);
+    return off;
+  };
+  GameOffsets::Player* po = g->offs.p;
+  for (int p = 0; p < 2; ++p) {
+    HostPlayer& hp = g->hp[p];
+    po[p].first = add(hp.node_first_seq.data(), hp.node_first_seq.size() * sizeof(int));
+    po[p].nact = add(hp.node_nact.data(), hp.node_nact.size() * sizeof(int));
+    po[p].beta = add(hp.node_beta.data(), hp.node_beta.size() * sizeof(double));
+    po[p].logn = add(hp.node_logn.data(), hp.node_logn.size() * sizeof(double));
+    po[p].spar = add(hp.seq_parent.data(), hp.seq_parent.size() * sizeof(int));
+    po[p].cbeg = add(hp.child_begin.data(), hp.child_begin.size() * sizeof(int));
+    po[p].child = add(hp.child.data(), hp.child.size() * sizeof(int));
+    po[p].tbeg = add(hp.term_begin.data(), hp.term_begin.size() * sizeof(int));
+    po[p].topp = add(hp.term_opp.data(), hp.term_opp.size() * sizeof(int));
+    po[p].tkind = add(hp.term_kind.data(), hp.term_kind.size() * sizeof(int));
+    po[p].tcoef = add(hp.term_coef.data(), hp.term_coef.size() * sizeof(double));
+    po[p].roots = add(hp.roots.data(), hp.roots.size() * sizeof(int));
+    po[p].belief = add(b[p].data(), b[p].size() * sizeof(double));
+    po[p].ftab = add(hp.fused_tab.data(), hp.fused_tab.size());
+    po[p].trec = add(hp.term_rec.data(), hp.term_rec.size() * sizeof(TermRec));
+    po[p].anc = add(hp.anc.data(), hp.anc.size() * sizeof(int));
+    po[p].titems = add(hp.term_items.data(), hp.term_items.size() * sizeof(TermItem));
+    po[p].snact = add(hp.seq_nact.data(), hp.seq_nact.size() * sizeof(int));
+    po[p].sptr = add(hp.sp_ptr.data(), hp.sp_ptr.size() * sizeof(int64_t));
+    po[p].scol = add(hp.sp_col.data(), hp.sp_col.size() * sizeof(int));
+    po[p].sval = add(hp.sp_val.data(), hp.sp_val.size() * sizeof(double));
+  }
+  g->offs.cbeg = add(card_begin.data(), card_begin.size() * sizeof(int));
+  g->offs.htab = add(htab.data(), htab.size() * sizeof(uint4));
+  g->offs.hpos = add(hpos.data(), hpos.size() * sizeof(unsigned));
+
+  g->img.assign(total, 0);
+  for (const Piece& pc : pieces)
+    if (pc.bytes) std::memcpy(g->img.data() + pc.off, pc.src, pc.bytes);
+  g->dh.n = n;
+  g->dh.ld = g->ld;
+  g->dh.cph = cph;
+  g->dh.n_cards = nc;
+  g->dh.n_card_slots = card_begin[nc] + nc;
+  g->dh.invZ = 1.0 / Z;
+  EGT_HIP(hipGetDevice(&g->device));
+  EGT_HIP(hipDeviceGetAttribute(&g->n_cu, hipDeviceAttributeMultiprocessorCount, g->device));
+  if (g->n_cu < 1) g->n_cu = 1;
+  EGT_HIP(hipDeviceGetAttribute(&g->lds_per_block, hipDeviceAttributeMaxSharedMemoryPerBlock, g->device));
+  EGT_HIP(hipDeviceGetAttribute(&g->lds_per_cu, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, g->device));
+  if (g->lds_per_block < 64 * 1024) g->lds_per_block = 64 * 1024;
+  if (g->lds_per_cu < g->lds_per_block) g->lds_per_cu = g->lds_per_block;
+  return EGT_OK;
+}
+
 // Builds every table of a game on the host and lays them out as one image
 // (g->img, offsets in g->offs) for a single upload; no device memory is
 // touched.
@@ -516,62 +583,123 @@ int build_game_host(const egt_game_desc* d, egt_game** out) {
   if (!(Z > 0) || !std::isfinite(Z)) return fail(EGT_EINVAL, "no compatible deal has positive belief");
   g->Z = Z;
 
-  // ---- one device block for every table ----
-  struct Piece {
-    const void* src;
-    size_t bytes;
-    size_t off;
+  int rc = finish_image(g, card_begin, htab, hpos, b);
+  if (rc) return rc;
+  *out = guard.release();
+  return EGT_OK;
+}
+
+// A general game (egt_general_desc) on the host: the two treeplexes through
+// the same level ordering as a river endgame, the payoff operator as CSR rows
+// per player, one live slot per row and no terminal or hand tables.
+int build_general_host(const egt_general_desc* d, egt_game** out) {
+  if (!d || !out) return fail(EGT_EINVAL, "null argument");
+  *out = nullptr;
+  if (!(d->scale > 0) || !std::isfinite(d->scale)) return fail(EGT_EINVAL, "scale must be finite and > 0");
+  if (d->nnz < 0 || (d->nnz > 0 && (!d->a_row || !d->a_col || !d->a_val)))
+    return fail(EGT_EINVAL, "bad payoff triples");
+  Enumerator en;  // only its node and sequence lists
+  for (int p = 0; p < 2; ++p) {
+    const int ni = d->n_infosets[p];
+    if (ni < 1 || !d->parent_seq[p] || !d->n_actions[p])
+      return fail(EGT_EINVAL, "every player needs at least one information set");
+    int seqs = 0;
+    for (int k = 0; k < ni; ++k) {
+      const int na = d->n_actions[p][k], ps = d->parent_seq[p][k];
+      if (na < 1 || na > kMaxActions) return fail(EGT_EINVAL, "an information set needs 1 to 16 actions");
+      if (ps < -1 || ps >= seqs)
+        return fail(EGT_EINVAL, "a parent sequence must belong to an earlier information set (or be -1)");
+      if (seqs > (1 << 26) - na) return fail(EGT_EINVAL, "too many sequences");
+      RawNode rn;
+      rn.key = std::to_string(k);
+      rn.parent_seq = ps;
+      rn.first_seq = seqs;
+      rn.acts.assign(na, Act{'p', 0.0, false});
+      en.nodes[p].push_back(rn);
+      for (int a = 0; a < na; ++a) en.seq_key[p].push_back(std::to_string(seqs + a));
+      seqs += na;
+    }
+  }
+  egt_game* g = new (std::nothrow) egt_game();
+  if (!g) return fail(EGT_ENOMEM, "host allocation failed");
+  std::unique_ptr<egt_game> guard(g);
+  g->general = true;
+  g->n = 1;
+  g->ld = 32;
+  g->cph = 1;
+  g->n_cards = 1;
+  g->pot = d->scale;
+  g->stack = 0.0;
+  std::vector<int> raw2new[2];
+  for (int p = 0; p < 2; ++p) {
+    const int st = finish_player(en, p, g->hp[p], raw2new[p]);
+    if (st != EGT_OK) return st;
+    HostPlayer& hp = g->hp[p];
+    hp.term_begin.assign(hp.n_seq + 1, 0);
+    hp.max_terms_per_seq = 0;
+    hp.term_rec.assign((size_t)hp.n_seq, TermRec{-1, -1, 0.0});
+    hp.term_items.clear();
+  }
+  // payoff triples in library numbering; repeated pairs added in input order
+  struct Trip {
+    int r, c;
+    int64_t i;
   };
-  std::vector<Piece> pieces;
-  size_t total = 0;
-  auto add = [&](const void* src, size_t bytes) {
-    const size_t off = total;
-    pieces.push_back({src, bytes, off});
-    total = align_up(total + std::max<size_t>(bytes, 1), 256);
-    return off;
-  };
-  GameOffsets::Player* po = g->offs.p;
+  std::vector<Trip> t((size_t)d->nnz);
+  for (int64_t i = 0; i < d->nnz; ++i) {
+    const int r = d->a_row[i], c = d->a_col[i];
+    if (r < 0 || r >= g->hp[0].n_seq || c < 0 || c >= g->hp[1].n_seq)
+      return fail(EGT_EINVAL, "a payoff triple names a sequence out of range");
+    if (!std::isfinite(d->a_val[i])) return fail(EGT_EINVAL, "payoff values must be finite");
+    t[(size_t)i] = Trip{raw2new[0][r], raw2new[1][c], i};
+  }
   for (int p = 0; p < 2; ++p) {
     HostPlayer& hp = g->hp[p];
-    po[p].first = add(hp.node_first_seq.data(), hp.node_first_seq.size() * sizeof(int));
-    po[p].nact = add(hp.node_nact.data(), hp.node_nact.size() * sizeof(int));
-    po[p].beta = add(hp.node_beta.data(), hp.node_beta.size() * sizeof(double));
-    po[p].logn = add(hp.node_logn.data(), hp.node_logn.size() * sizeof(double));
-    po[p].spar = add(hp.seq_parent.data(), hp.seq_parent.size() * sizeof(int));
-    po[p].cbeg = add(hp.child_begin.data(), hp.child_begin.size() * sizeof(int));
-    po[p].child = add(hp.child.data(), hp.child.size() * sizeof(int));
-    po[p].tbeg = add(hp.term_begin.data(), hp.term_begin.size() * sizeof(int));
-    po[p].topp = add(hp.term_opp.data(), hp.term_opp.size() * sizeof(int));
-    po[p].tkind = add(hp.term_kind.data(), hp.term_kind.size() * sizeof(int));
-    po[p].tcoef = add(hp.term_coef.data(), hp.term_coef.size() * sizeof(double));
-    po[p].roots = add(hp.roots.data(), hp.roots.size() * sizeof(int));
-    po[p].belief = add(b[p].data(), b[p].size() * sizeof(double));
-    po[p].ftab = add(hp.fused_tab.data(), hp.fused_tab.size());
-    po[p].trec = add(hp.term_rec.data(), hp.term_rec.size() * sizeof(TermRec));
-    po[p].anc = add(hp.anc.data(), hp.anc.size() * sizeof(int));
-    po[p].titems = add(hp.term_items.data(), hp.term_items.size() * sizeof(TermItem));
-    po[p].snact = add(hp.seq_nact.data(), hp.seq_nact.size() * sizeof(int));
+    // this player's rows: (row, col) = (r, c) for player 1, (c, r) for player 2
+    std::vector<Trip> u(t);
+    if (p == 1)
+      for (Trip& x : u) std::swap(x.r, x.c);
+    std::stable_sort(u.begin(), u.end(), [](const Trip& a, const Trip& b) { return a.r != b.r ? a.r < b.r : a.c < b.c; });
+    hp.sp_ptr.assign(hp.n_seq + 1, 0);
+    hp.sp_col.clear();
+    hp.sp_val.clear();
+    for (size_t k = 0; k < u.size();) {
+      size_t e = k;
+      double v = 0.0;
+      while (e < u.size() && u[e].r == u[k].r && u[e].c == u[k].c) v += d->a_val[u[e++].i];
+      hp.sp_col.push_back(u[k].c);
+      hp.sp_val.push_back(v);
+      hp.sp_ptr[u[k].r + 1]++;
+      k = e;
+    }
+    hp.sp_max_row = 0;
+    for (int r = 0; r < hp.n_seq; ++r) {
+      hp.sp_max_row = std::max(hp.sp_max_row, hp.sp_ptr[r + 1]);
+      hp.sp_ptr[r + 1] += hp.sp_ptr[r];
+    }
   }
-  g->offs.cbeg = add(card_begin.data(), card_begin.size() * sizeof(int));
-  g->offs.htab = add(htab.data(), htab.size() * sizeof(uint4));
-  g->offs.hpos = add(hpos.data(), hpos.size() * sizeof(unsigned));
-
-  g->img.assign(total, 0);
-  for (const Piece& pc : pieces)
-    if (pc.bytes) std::memcpy(g->img.data() + pc.off, pc.src, pc.bytes);
-  g->dh.n = n;
-  g->dh.ld = g->ld;
-  g->dh.cph = cph;
-  g->dh.n_cards = nc;
-  g->dh.n_card_slots = card_begin[nc] + nc;
-  g->dh.invZ = 1.0 / Z;
-  EGT_HIP(hipGetDevice(&g->device));
-  EGT_HIP(hipDeviceGetAttribute(&g->n_cu, hipDeviceAttributeMultiprocessorCount, g->device));
-  if (g->n_cu < 1) g->n_cu = 1;
-  EGT_HIP(hipDeviceGetAttribute(&g->lds_per_block, hipDeviceAttributeMaxSharedMemoryPerBlock, g->device));
-  EGT_HIP(hipDeviceGetAttribute(&g->lds_per_cu, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, g->device));
-  if (g->lds_per_block < 64 * 1024) g->lds_per_block = 64 * 1024;
-  if (g->lds_per_cu < g->lds_per_block) g->lds_per_cu = g->lds_per_block;
+  g->fused_hands = 16;
+  g->fused_passes =
+      fused_lds_bytes(g->fused_hands, (int)std::max(g->hp[0].fused_tab.size(), g->hp[1].fused_tab.size()),
+                      std::max(g->hp[0].n_nodes, g->hp[1].n_nodes),
+                      std::max(g->hp[0].n_seq, g->hp[1].n_seq)) <= kFusedLdsLimit;
+  for (int p = 0; p < 2; ++p)
+    for (double b : g->hp[p].node_beta) g->max_beta = std::max(g->max_beta, b);
+  g->perm = {0};
+  g->slot_cards = {0};
+  g->slot_strength = {0};
+  std::vector<double> b[2];
+  for (int p = 0; p < 2; ++p) {
+    b[p].assign(g->ld, 0.0);
+    b[p][0] = 1.0;
+    g->hbelief[p] = b[p];
+  }
+  g->Z = 1.0;
+  const std::vector<int> card_begin = {0, 1};
+  const std::vector<uint4> htab = {make_uint4(0u, 0u, 0u, 0u)};
+  const std::vector<unsigned> hpos = {0u};
+  const int rc = finish_image(g, card_begin, htab, hpos, b);
+  if (rc) return rc;
   *out = guard.release();
   return EGT_OK;
 }
@@ -615,6 +743,9 @@ int upload_game(egt_game* g, void* dev, bool owned, hipStream_t stream) {
     dp.n_items = (int)hp.term_items.size();
     dp.term_items = dp.n_items > 0 ? (const TermItem*)at(po[p].titems) : nullptr;
     dp.seq_nact = (const int*)at(po[p].snact);
+    dp.sp_ptr = hp.sp_ptr.empty() ? nullptr : (const int64_t*)at(po[p].sptr);
+    dp.sp_col = (const int*)at(po[p].scol);
+    dp.sp_val = (const double*)at(po[p].sval);
   }
   g->dh.card_begin = (const int*)at(g->offs.cbeg);
   g->dh.htab = (const uint4*)at(g->offs.htab);
@@ -622,14 +753,12 @@ int upload_game(egt_game* g, void* dev, bool owned, hipStream_t stream) {
   return EGT_OK;
 }
 
-// Host tables, one device block, upload, synchronise.
-int build_game(const egt_game_desc* d, hipStream_t stream, egt_game** out) {
-  if (!out) return fail(EGT_EINVAL, "null argument");
-  *out = nullptr;
-  egt_game* g = nullptr;
-  int rc = build_game_host(d, &g);
-  if (rc) return rc;
+namespace {
+
+// One device block for a game built on the host, upload, synchronise.
+int place_game(egt_game* g, hipStream_t stream, egt_game** out) {
   std::unique_ptr<egt_game> guard(g);
+  int rc = EGT_OK;
   void* dev = nullptr;
   hipError_t e = hipMalloc(&dev, game_device_bytes(g));
   if (e != hipSuccess) return fail(EGT_ENOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
@@ -645,6 +774,27 @@ int build_game(const egt_game_desc* d, hipStream_t stream, egt_game** out) {
   }
   *out = guard.release();
   return EGT_OK;
+}
+
+}  // namespace
+
+// Host tables, one device block, upload, synchronise.
+int build_game(const egt_game_desc* d, hipStream_t stream, egt_game** out) {
+  if (!out) return fail(EGT_EINVAL, "null argument");
+  *out = nullptr;
+  egt_game* g = nullptr;
+  const int rc = build_game_host(d, &g);
+  if (rc) return rc;
+  return place_game(g, stream, out);
+}
+
+int build_general_game(const egt_general_desc* d, hipStream_t stream, egt_game** out) {
+  if (!out) return fail(EGT_EINVAL, "null argument");
+  *out = nullptr;
+  egt_game* g = nullptr;
+  const int rc = build_general_host(d, &g);
+  if (rc) return rc;
+  return place_game(g, stream, out);
 }
 
 int free_game(egt_game* g) {

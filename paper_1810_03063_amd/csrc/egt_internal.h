@@ -106,6 +106,11 @@ struct DPlayer {
   int n_items;
   int fused_tab16;             // its size in 16-byte units
   const int* seq_nact;         // [n_seq] number of actions of the sequence's decision node
+  // General games: this player's rows of the payoff operator in CSR (A for
+  // player 1, A^T for player 2), columns in the opponent's library order.
+  const int64_t* sp_ptr;       // [n_seq + 1], or null for a river endgame
+  const int* sp_col;
+  const double* sp_val;
 };
 
 // Hands in strength-ascending slot order, with the card tables the O(n) leaf
@@ -210,6 +215,10 @@ struct HostPlayer {
   std::vector<int> anc;                  // [n_seq][kMaxDepth]
   std::vector<int> seq_nact;             // [n_seq] actions of the sequence's node
   std::vector<std::string> seq_keys;
+  std::vector<int64_t> sp_ptr;           // general games: CSR rows of A (player 1) or A^T (player 2)
+  std::vector<int> sp_col;
+  std::vector<double> sp_val;
+  int64_t sp_max_row = 0;                // most entries of one row
 };
 
 struct DeviceBlock {  // one device allocation holding many tables
@@ -221,7 +230,7 @@ struct DeviceBlock {  // one device allocation holding many tables
 struct GameOffsets {
   struct Player {
     size_t first, nact, beta, logn, spar, cbeg, child, tbeg, topp, tkind, tcoef, roots, belief, ftab, trec, anc,
-        titems, snact;
+        titems, snact, sptr, scol, sval;
   } p[2];
   size_t cbeg, htab, hpos;
 };
@@ -276,6 +285,7 @@ struct egt_game {
   egt::MixedTables mx;
   int device = 0;
   double max_beta = 0;
+  bool general = false;       // a general game (egt_build_general_game): CSR products, one live slot
   bool fused_passes = false;  // both treeplexes' tables fit one block's LDS: single-launch passes
   int fused_hands = 4;        // hands per block of the single-launch pass (4 or 16)
 };
@@ -286,7 +296,9 @@ namespace egt {
 // Launchers (egt_kernels.hip).  All enqueue on `s` and return hipError_t.
 // ---------------------------------------------------------------------------
 
-// grad_out = A v_opp (player 0) or A^T v_opp (player 1).
+// grad_out = A v_opp (player 0) or A^T v_opp (player 1); general games take
+// the CSR product (launch_spmv).
+hipError_t launch_spmv(const egt_game* g, int player, const double* v_opp, double* grad_out, hipStream_t s);
 hipError_t launch_gradient(const egt_game* g, int player, const double* v_opp, double* grad_out,
                            hipStream_t s);
 

@@ -341,6 +341,7 @@ __global__ __launch_bounds__(256) void show_gemm_tiled_kernel(GemmArgs a) {
 // W at 0, then per player the FP32 prior (off[p][3]) and the column lists
 // (own sequence off[p][0], opponent sequence off[p][1], chips off[p][2]).
 int mixed_tables_image(const egt_game* g, std::vector<unsigned char>& img, size_t off[2][4]) {
+  if (g->general) return fail(EGT_EINVAL, "the precision form needs a river endgame");
   const int n = g->n;
   const int kpad = g->ld;  // rows and columns padded like every vector
   // slot order: strength ascending; compatibility from the cards of the slots

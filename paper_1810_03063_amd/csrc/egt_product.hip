@@ -1,5 +1,6 @@
 // Payoff products A y and A^T x (Section 2's gradient operators) on the fold
-// and showdown terminals of a river endgame, O(n) per terminal, for gfx950.
+// and showdown terminals of a river endgame, O(n) per terminal, for gfx950;
+// for a general game, a CSR SpMV over the explicit operator.
 //
 // For a terminal z with opponent sequence sigma_o(z) the opponent's reach is
 // r(h') = b_o(h') v_o[sigma_o(z)][h'] over the strength-ordered hands, and
@@ -337,7 +338,33 @@ __global__ __launch_bounds__(2 * kGroupThreads, MINW) void product_kernel(ProdAr
 
 size_t align2(size_t x) { return (x + 1) / 2 * 2; }
 
+// General games (Section 6's explicit sparse operator): one wavefront per CSR
+// row; lane l takes the row's entries l, l + 64, ... in column order, then a
+// fixed xor butterfly (every lane ends with the same sum); the row's slot 0
+// gets the sum and its padding slots 1 .. ld - 1 are written 0.
+__global__ __launch_bounds__(256) void spmv_kernel(const int64_t* ptr, const int* col, const double* val,
+                                                   const double* v, int ld, int n_rows, double* out) {
+  const int lane = threadIdx.x & 63;
+  const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (row >= n_rows) return;
+  const int64_t k0 = ptr[row], k1 = ptr[row + 1];
+  double acc = 0.0;
+  for (int64_t k = k0 + lane; k < k1; k += 64) acc += val[k] * v[(size_t)col[k] * ld];
+  for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
+  double* o = out + (size_t)row * ld;
+  for (int i = lane; i < ld; i += 64) o[i] = i == 0 ? acc : 0.0;
+}
+
 }  // namespace
+
+hipError_t launch_spmv(const egt_game* g, int player, const double* v_opp, double* grad_out, hipStream_t s) {
+  const DPlayer& P = g->dp[player];
+  if (!g->general || !P.sp_ptr) return hipErrorInvalidValue;
+  if (P.n_seq == 0) return hipSuccess;
+  hipLaunchKernelGGL(spmv_kernel, dim3((unsigned)((P.n_seq + 3) / 4)), dim3(256), 0, s, P.sp_ptr, P.sp_col, P.sp_val,
+                     v_opp, g->ld, P.n_seq, grad_out);
+  return hipGetLastError();
+}
 
 // Doubles of LDS one wave group of the product kernel takes.
 size_t product_group_doubles(const egt_game* g) { return align2((size_t)g->n + 1) + (size_t)g->dh.n_card_slots; }
@@ -396,11 +423,13 @@ static hipError_t product_launch(const egt_game* g, int player, const TV* v_opp,
 }
 
 hipError_t launch_gradient(const egt_game* g, int player, const double* v_opp, double* grad_out, hipStream_t s) {
+  if (g->general) return launch_spmv(g, player, v_opp, grad_out, s);
   return product_launch<double, double>(g, player, v_opp, grad_out, 0, s);
 }
 
 hipError_t launch_gradient_fold_f32(const egt_game* g, int player, const float* v_opp, float* grad_out,
                                     hipStream_t s) {
+  if (g->general) return hipErrorInvalidValue;  // the precision form is river-only
   return product_launch<float, float>(g, player, v_opp, grad_out, 1, s);
 }
 

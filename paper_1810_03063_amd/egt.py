@@ -52,6 +52,12 @@ class GameDesc(ctypes.Structure):
     ]
 
 
+class GeneralDesc(ctypes.Structure):
+    _fields_ = [("n_infosets", ctypes.c_int32 * 2), ("parent_seq", ctypes.c_void_p * 2),
+                ("n_actions", ctypes.c_void_p * 2), ("nnz", ctypes.c_int64), ("a_row", ctypes.c_void_p),
+                ("a_col", ctypes.c_void_p), ("a_val", ctypes.c_void_p), ("scale", ctypes.c_double)]
+
+
 class SolveOpts(ctypes.Structure):
     _fields_ = [
         ("variant", _i32), ("precision", _i32), ("eps", _f64), ("max_iters", _i64),
@@ -81,6 +87,8 @@ def _decl(name, restype, *args):
 _last_error = _decl("egt_last_error", ctypes.c_char_p)
 _default_opts = _decl("egt_default_opts", None, ctypes.POINTER(SolveOpts))
 _build_game = _decl("egt_build_game", ctypes.c_int, ctypes.POINTER(GameDesc), _p, ctypes.POINTER(_p))
+_build_general_game = _decl("egt_build_general_game", ctypes.c_int, ctypes.POINTER(GeneralDesc), _p,
+                            ctypes.POINTER(_p))
 _free_game = _decl("egt_free_game", ctypes.c_int, _p)
 _game_dims = _decl("egt_game_dims", ctypes.c_int, _p, ctypes.c_int, ctypes.POINTER(_i64),
                    ctypes.POINTER(_i64), ctypes.POINTER(_i64), ctypes.POINTER(_i64))
@@ -146,6 +154,7 @@ EXPORTED = [
     "egt_batch_poll", "egt_batch_retire", "egt_batch_usage", "egt_saddle_gap_noalloc",
     "egt_batch_strategies", "egt_cfr_create", "egt_cfr_destroy", "egt_cfr_step", "egt_cfr_gap", "egt_cfr_get",
     "egt_cfr_solve", "egt_batch_admit_desc", "egt_fom_create", "egt_fom_destroy", "egt_fom_step", "egt_fom_get", "egt_fom_gap",
+    "egt_build_general_game",
 ]
 
 
@@ -264,6 +273,61 @@ class Game:
             self.close()
         except Exception:
             pass
+
+
+def general_desc(inst):
+    """egt_general_desc of a general game (parents, action counts, payoff
+    triples) and the host arrays it points into."""
+    d = GeneralDesc()
+    keep = []
+    for p in (0, 1):
+        sets = inst.infosets[p]
+        par = np.ascontiguousarray([s_[0] for s_ in sets], dtype=np.int32)
+        nact = np.ascontiguousarray([s_[1] for s_ in sets], dtype=np.int32)
+        keep += [par, nact]
+        d.n_infosets[p] = len(sets)
+        d.parent_seq[p] = par.ctypes.data
+        d.n_actions[p] = nact.ctypes.data
+    e = inst.entries
+    rows = np.ascontiguousarray([t[0] for t in e], dtype=np.int32)
+    cols = np.ascontiguousarray([t[1] for t in e], dtype=np.int32)
+    vals = np.ascontiguousarray([t[2] for t in e], dtype=np.float64)
+    keep += [rows, cols, vals]
+    d.nnz = len(e)
+    d.a_row = rows.ctypes.data if len(e) else None
+    d.a_col = cols.ctypes.data if len(e) else None
+    d.a_val = vals.ctypes.data if len(e) else None
+    d.scale = inst.pot
+    return d, keep
+
+
+class GeneralGame(Game):
+    """A general extensive-form game uploaded to the current device
+    (egt_build_general_game): one live slot per row; every FP64 entry point
+    accepts it."""
+
+    def __init__(self, inst, stream=None):
+        self._h = None
+        d, keep = general_desc(inst)
+        h = _p()
+        _check(_build_general_game(ctypes.byref(d), _stream(stream), ctypes.byref(h)))
+        del keep
+        self._h = h
+        self.inst = inst
+        self.pot = inst.pot
+        dims = [self._dims(p) for p in (0, 1)]
+        self.n_seq = [d_[0] for d_ in dims]
+        self.n = dims[0][1]
+        self.ld = dims[0][2]
+        self.n_nodes = [d_[3] for d_ in dims]
+
+    def seq_order(self, p):
+        """library row of each of the caller's sequences."""
+        keys, _ = self.layout(p)
+        out = np.empty(len(keys), dtype=np.int64)
+        for lib, k in enumerate(keys):
+            out[int(k)] = lib
+        return out
 
 
 def gradient(game: Game, player: int, strat_other, out=None, stream=None):
