@@ -68,19 +68,24 @@ def parse():
     ap.add_argument("--config", default="c3", help="headline endgame (c3: 8 bet sizes, 4 raises)")
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--variant", default="AS")
-    ap.add_argument("--cpu-sample-iters", type=int, default=3,
+    ap.add_argument("--cpu-sample-iters", type=int, default=12,
                     help="oracle iterations timed for the CPU baseline (after its start-up)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--kernel-reps", type=int, default=50)
     ap.add_argument("--mixed-steps", type=int, default=2, help="precision-form solves of the headline endgame")
     ap.add_argument("--second-config", default="c1", help="second workload ('' = skip)")
     ap.add_argument("--second-steps", type=int, default=10)
-    ap.add_argument("--serve-requests", type=int, default=64, help="requests of the serving trace (0 = skip)")
+    ap.add_argument("--serve-requests", type=int, default=32, help="requests of the serving trace (0 = skip)")
     ap.add_argument("--serve-rate", type=float, default=0.0,
                     help="Poisson arrival rate (requests/s) of the loaded runs; 0 = 0.9 x the measured "
                          "saturated batched throughput")
     ap.add_argument("--serve-shapes", default="c0,c1,c2,c3")
     ap.add_argument("--serve-budget-gb", type=float, default=16.0)
+    ap.add_argument("--other-paths", type=int, default=1, help="CFR+, mirror prox and general-game measurements")
+    ap.add_argument("--cfr-iters", type=int, default=20000)
+    ap.add_argument("--fom-iters", type=int, default=2000)
+    ap.add_argument("--fom-step", type=float, default=20.0,
+                    help="mirror-prox step (the best of 2e-4 .. 20 in a sweep on the 3-size endgame)")
     ap.add_argument("--copy-calibration-mb", type=float, default=0.0,
                     help="run 5 plain device copies of this many MB first (scales HBM counters)")
     ap.add_argument("--roofline-only", action="store_true",
@@ -223,6 +228,78 @@ def second_workload(egt, torch, args):
     return out
 
 
+def spmv_roofline(egt, torch, G, reps):
+    """The general route's CSR product (spmv_kernel), A y.  Algorithmic bytes
+    per launch: per nonzero its value, its column and the gathered entry of y
+    (8 + 4 + 8), per row its two row pointers and the written output row of ld
+    doubles (slot 0 and the zero padding)."""
+    y = egt.uniform(G, 1)
+    out = G.empty(0)
+    avg_s = _timed(torch, lambda: egt.gradient(G, 0, y, out), reps)
+    nnz = len(G.inst.entries)
+    bytes_ = 20.0 * nnz + (16.0 + 8.0 * G.ld) * G.n_seq[0]
+    gbs = bytes_ / avg_s / 1e9
+    return dict(kernel="spmv_kernel", bound="hbm", achieved=round(gbs, 3), peak=HBM_PEAK_GBS, unit="GB/s",
+                frac=round(gbs / HBM_PEAK_GBS, 6), traffic=None, avg_us=round(avg_s * 1e6, 3),
+                algorithmic_bytes=int(bytes_), nnz=nnz, rows=G.n_seq[0],
+                launch="egt_gradient on a general game, player 0 (A y)")
+
+
+def other_paths(egt, torch, args):
+    """The paper's comparison methods and extensions, measured beside the
+    headline: CFR+ to the same gap target on the second endgame (gradient
+    computations against EGT's, the comparison of Section 7), mirror prox
+    there (Section 8), and the general route (Section 6): Leduc hold'em solved
+    to 1e-3 of its pot and the CSR product's roofline on a seeded random game
+    tree."""
+    from instances import make_instance
+    from instances.efg import leduc, random_efg
+
+    cfg = args.second_config or "c1"
+    inst = make_instance(cfg, args.seed)
+    G = egt.Game(inst)
+    eps = 1e-3 * inst.pot
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    r_egt, _ = egt.solve(G)
+    t1 = time.perf_counter()
+    r_cfr = egt.cfr_solve(G, "CFR_PLUS", eps=eps, max_iters=args.cfr_iters, gap_every=10)
+    t2 = time.perf_counter()
+    F = egt.Fom(G, "MP", args.fom_step)
+    torch.cuda.synchronize()
+    t3 = time.perf_counter()
+    F.step(args.fom_iters)
+    torch.cuda.synchronize()
+    t4 = time.perf_counter()
+    mp_gap = F.gap()[0]
+    F.close()
+    G.close()
+    out = dict(
+        workload=describe(cfg, inst, G),
+        egt_as=dict(iters=r_egt["iters"], products=r_egt["products"], gap=r_egt["gap"], seconds=t1 - t0),
+        cfr_plus=dict(iters=r_cfr["iters"], products=r_cfr["products"], gap=r_cfr["gap"],
+                      converged=r_cfr["converged"], seconds=t2 - t1, iters_per_sec=r_cfr["iters"] / (t2 - t1),
+                      note=f"to gap <= 1e-3*pot or {args.cfr_iters} iterations, gap tested every 10"),
+        mirror_prox=dict(iters=args.fom_iters, step=args.fom_step, gap=mp_gap, seconds=t4 - t3,
+                         iters_per_sec=args.fom_iters / (t4 - t3)),
+    )
+    lg = leduc()
+    GG = egt.GeneralGame(lg)
+    r = timed_solves(egt, torch, GG, 3, 1)
+    out["general_leduc"] = dict(workload=f"Leduc hold'em, {GG.n_seq[0]} + {GG.n_seq[1]} sequences, "
+                                         f"{len(lg.entries)} payoff entries; FP64 EGT/AS to gap <= 1e-3*pot",
+                                solves_per_sec=3 / r["elapsed"], iters_per_solve=sum(r["iters"]) / 3,
+                                ms_per_iteration=r["elapsed"] / sum(r["iters"]) * 1e3, final_gap=r["last"]["gap"])
+    GG.close()
+    rg = random_efg(5, depth=8, max_actions=4, n_types=20)
+    GR = egt.GeneralGame(rg)
+    out["general_spmv"] = dict(workload=f"seeded random game tree, {GR.n_seq[0]} x {GR.n_seq[1]} sequences, "
+                                        f"{len(rg.entries)} payoff entries",
+                               roofline=spmv_roofline(egt, torch, GR, args.kernel_reps * 4))
+    GR.close()
+    return out
+
+
 def serving(egt, args):
     """Trace of solve requests (shapes drawn uniformly), continuously batched
     under an HBM budget: all at t = 0 (the saturated capacity, batched and
@@ -253,13 +330,19 @@ def serving(egt, args):
         G.close()
         return res.get("status", "EGT_OK"), res
 
+    def note(what, res):
+        print(f"serving: {what}: {res['solves_per_sec']:.3f} solves/s", file=sys.stderr, flush=True)
+
     saturated = run(0.0)  # every request at t = 0
+    note("saturated, batched", saturated)
     seq_sat_out, seq_sat_wall = serve_sequential(solve_one, reqs_for(0.0))
     seq_saturated = summarize(seq_sat_out, seq_sat_wall)
+    note("saturated, one at a time", seq_saturated)
     rate = args.serve_rate if args.serve_rate > 0 else 0.9 * saturated["solves_per_sec"]
     loaded = run(rate)
+    note("Poisson arrivals, batched precision form", loaded)
     loaded64 = run(rate, "fp64")
-    print("serving: batched runs done", file=sys.stderr, flush=True)
+    note("Poisson arrivals, batched FP64", loaded64)
     seq_out, seq_wall = serve_sequential(solve_one, reqs_for(rate))
     baseline = summarize(seq_out, seq_wall)
     return dict(shapes=list(shapes), requests=n, budget_gb=args.serve_budget_gb, saturated=saturated,
@@ -381,6 +464,9 @@ def main():
     if args.second_config:
         out["second_workload"] = second_workload(egt, torch, args)
         print("second workload done", file=sys.stderr, flush=True)
+    if args.other_paths:
+        out["other_paths"] = other_paths(egt, torch, args)
+        print("other paths done", file=sys.stderr, flush=True)
     if args.serve_requests > 0:
         out["serving"] = serving(egt, args)
         print("serving done", file=sys.stderr, flush=True)
