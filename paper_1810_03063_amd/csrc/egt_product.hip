@@ -44,13 +44,29 @@ namespace egt {
 namespace {
 
 constexpr int kGroupThreads = 256;  // one wave group evaluates one terminal per round
+constexpr int kQR = 12;             // card-list quarters up to this long stay in registers
 
-__device__ inline double wave_inclusive_scan(double x, int lane) {
-#pragma unroll
-  for (int off = 1; off < 64; off <<= 1) {
-    const double y = __shfl_up(x, off, 64);
-    if (lane >= off) x += y;
-  }
+// A double moved across lanes by a DPP control (VALU, no LDS round trip);
+// lanes whose source is out of range or whose row is masked get 0.
+template <int CTRL, int ROW_MASK>
+__device__ inline double dpp_move(double x) {
+  const long long b = __double_as_longlong(x);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffll), CTRL, ROW_MASK, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, ROW_MASK, 0xf, false);
+  return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+
+// Inclusive scan over the 64 lanes of a wavefront (every lane active): within
+// each row of 16 lanes by shifts of 1, 2, 4, 8, then each row's total carried
+// to the rows after it (row broadcasts of lanes 15 and 31).  The additions are
+// fixed, so the result is repeatable.
+__device__ inline double wave_inclusive_scan(double x) {
+  x += dpp_move<0x111, 0xf>(x);  // row_shr:1
+  x += dpp_move<0x112, 0xf>(x);  // row_shr:2
+  x += dpp_move<0x114, 0xf>(x);  // row_shr:4
+  x += dpp_move<0x118, 0xf>(x);  // row_shr:8
+  x += dpp_move<0x142, 0xa>(x);  // row_bcast:15 into rows 1 and 3
+  x += dpp_move<0x143, 0xc>(x);  // row_bcast:31 into rows 2 and 3
   return x;
 }
 
@@ -219,39 +235,60 @@ __global__ __launch_bounds__(2 * kGroupThreads, MINW) void product_kernel(ProdAr
         double* L = E + cb + c;
         const int qlen = (len + 3) >> 2;
         const int lo = min(sub * qlen, len), hi = min(lo + qlen, len);
-        constexpr int kQ = 4;  // a quarter is read in batches of kQ
-        double part = 0.0;
-        for (int k0 = lo; k0 < hi; k0 += kQ) {
-          double v[kQ];
+        // the card's four lanes form an aligned quad: the quarter totals
+        // cross lanes by DPP quad permutes
+        if (qlen <= kQR) {  // uniform over the quad: the quarter stays in registers
+          double v[kQR];
+          double part = 0.0;
 #pragma unroll
-          for (int j = 0; j < kQ; ++j) v[j] = k0 + j < hi ? L[k0 + j] : 0.0;
+          for (int j = 0; j < kQR; ++j) v[j] = lo + j < hi ? L[lo + j] : 0.0;
 #pragma unroll
-          for (int j = 0; j < kQ; ++j)
-            if (k0 + j < hi) part += v[j];
-        }
-        const int l0 = lane & ~3;
-        const double p0 = __shfl(part, l0, 64), p1 = __shfl(part, l0 + 1, 64), p2 = __shfl(part, l0 + 2, 64);
-        double run = sub == 0 ? 0.0 : sub == 1 ? p0 : sub == 2 ? p0 + p1 : (p0 + p1) + p2;
-        for (int k0 = lo; k0 < hi; k0 += kQ) {
-          double v[kQ];
+          for (int j = 0; j < kQR; ++j)
+            if (lo + j < hi) part += v[j];
+          const double p0 = dpp_move<0x00, 0xf>(part), p1 = dpp_move<0x55, 0xf>(part), p2 = dpp_move<0xaa, 0xf>(part);
+          double run = sub == 0 ? 0.0 : sub == 1 ? p0 : sub == 2 ? p0 + p1 : (p0 + p1) + p2;
 #pragma unroll
-          for (int j = 0; j < kQ; ++j) v[j] = k0 + j < hi ? L[k0 + j] : 0.0;
-#pragma unroll
-          for (int j = 0; j < kQ; ++j) {
-            if (k0 + j < hi) {
-              L[k0 + j] = run;
+          for (int j = 0; j < kQR; ++j) {
+            if (lo + j < hi) {
+              L[lo + j] = run;
               run += v[j];
             }
           }
+          if (valid && sub == 3) L[len] = run;
+        } else {  // long lists: two passes over the quarter in batches of kQ
+          constexpr int kQ = 4;
+          double part = 0.0;
+          for (int k0 = lo; k0 < hi; k0 += kQ) {
+            double v[kQ];
+#pragma unroll
+            for (int j = 0; j < kQ; ++j) v[j] = k0 + j < hi ? L[k0 + j] : 0.0;
+#pragma unroll
+            for (int j = 0; j < kQ; ++j)
+              if (k0 + j < hi) part += v[j];
+          }
+          const double p0 = dpp_move<0x00, 0xf>(part), p1 = dpp_move<0x55, 0xf>(part), p2 = dpp_move<0xaa, 0xf>(part);
+          double run = sub == 0 ? 0.0 : sub == 1 ? p0 : sub == 2 ? p0 + p1 : (p0 + p1) + p2;
+          for (int k0 = lo; k0 < hi; k0 += kQ) {
+            double v[kQ];
+#pragma unroll
+            for (int j = 0; j < kQ; ++j) v[j] = k0 + j < hi ? L[k0 + j] : 0.0;
+#pragma unroll
+            for (int j = 0; j < kQ; ++j) {
+              if (k0 + j < hi) {
+                L[k0 + j] = run;
+                run += v[j];
+              }
+            }
+          }
+          if (valid && sub == 3) L[len] = run;
         }
-        if (valid && sub == 3) L[len] = run;
       }
       // 2b. the strength-order scan of this thread's contiguous hands
 #pragma unroll
       for (int k = 0; k < HPT; ++k) rloc[k] = k < cnt ? R[beg + k] : 0.0;
 #pragma unroll
       for (int k = 0; k < HPT; ++k) local += rloc[k];
-      incl = wave_inclusive_scan(local, lane);
+      incl = wave_inclusive_scan(local);
       if (lane == 63) wave_total[grp][wig] = incl;
     }
     __syncthreads();
