@@ -461,7 +461,7 @@ __global__ __launch_bounds__(kPassThreads) void bottom_up_leaf_pair_kernel(PassS
 // the weight sum and the value are then formed in the same order as above, so
 // per hand the result is bitwise the one the one-wavefront form gives.
 template <class TG, int HP>
-__global__ __launch_bounds__(kPassThreads * kMaxActions) void bottom_up_internal_kernel(PassSet a) {
+__global__ __launch_bounds__(kPassThreads * kInternalWaves) void bottom_up_internal_kernel(PassSet a) {
   static_assert(HP == 1 || HP == 2, "one or two hands per lane");
   using V2 = typename std::conditional<std::is_same<TG, float>::value, float2, double2>::type;
   constexpr int kChildBatch = 8;

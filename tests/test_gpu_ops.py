@@ -195,6 +195,12 @@ def _edge_instances():
     yield "no-bets", replace(base, bet_fracs=(), allin=False)
     # 16 actions at the first decision (check, 14 bet sizes, all-in): the most a node may have
     yield "max-actions", replace(base, bet_fracs=tuple(0.1 * (i + 1) for i in range(14)), max_raises=0)
+    # 16 actions at internal nodes on the level path: 13 bet sizes, two raises
+    # (facing a bet: fold, call, 13 raise sizes and all-in, with re-raises
+    # below), a tree of 7657 sequences per player whose tables exceed the
+    # single-launch pass's LDS
+    yield "max-actions-level", replace(base, bet_fracs=tuple(0.1 * (i + 1) for i in range(13)), max_raises=2,
+                                       stack=2000.0)
     # the largest hand count the library takes (2048): 65-card deck, 2048 of
     # its two-card hands, no board, ragged strength ties
     from instances.endgames import Instance
@@ -213,10 +219,14 @@ def _edge_instances():
 
 
 @pytest.mark.parametrize("name", ["zero-beliefs", "all-tied", "all-distinct", "no-raise", "no-bets", "max-actions",
-                                  "max-hands", "two-hands"])
+                                  "max-actions-level", "max-hands", "two-hands"])
 def test_edge_cases(egt, name):
     inst = dict(_edge_instances())[name]
     _, P, G, L = setup(egt, name, 0, inst=inst)
+    if name == "max-actions-level":
+        t = P.tp[0]
+        assert max(node.n_act for node in t.nodes if any(node.children)) == 16
+        assert P.n_seq[0] * 8 * 3 * 16 > 64 * 1024, "the tree must take the level path"
     rng = np.random.default_rng(5)
     x, y = random_point(P, 0, rng), random_point(P, 1, rng)
     gx = host(egt.gradient(G, 0, dev(L.to_lib(1, y))))
