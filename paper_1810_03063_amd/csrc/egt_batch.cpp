@@ -269,18 +269,27 @@ int egt_batch_admit(egt_batch* b, const egt_game* g, const egt_solve_opts* opts,
   egt_default_opts(&o);
   if (opts) o = *opts;
   const bool mixed = o.precision == EGT_PRECISION_MIXED;
-  if (mixed) {  // build the shared precision-form tables here, not on a worker
-    const int rc = ensure_mixed_tables(g);
-    if (rc) return rc;
-  }
   const int64_t need = (state_bytes(g, mixed) + kAlign - 1) / kAlign * kAlign;
-  std::lock_guard<std::mutex> lk(b->mu);
+  std::unique_lock<std::mutex> lk(b->mu);
   size_t k = 0;
   while (k < b->slots.size() && b->slots[k].phase != kFree) ++k;
   if (k == b->slots.size()) return fail(EGT_EBUDGET, "no free slot");
   int64_t off = 0;
   if (b->used + need > b->budget || !arena_take(b, need, &off))
     return fail(EGT_EBUDGET, "the solve does not fit the memory budget now");
+  b->used += need;
+  if (mixed) {  // the game's shared precision-form tables, built once admission is certain (not on a worker)
+    b->slots[k].phase = kQueued;  // hold the slot while the lock is released
+    lk.unlock();
+    const int rc = ensure_mixed_tables(g);
+    lk.lock();
+    if (rc) {
+      b->slots[k].phase = kFree;
+      arena_give(b, off, need);
+      b->used -= need;
+      return rc;
+    }
+  }
   Slot& sl = b->slots[k];
   sl.phase = kQueued;
   sl.g = g;
@@ -289,7 +298,6 @@ int egt_batch_admit(egt_batch* b, const egt_game* g, const egt_solve_opts* opts,
   sl.bytes = need;
   sl.status = EGT_OK;
   sl.t0 = std::chrono::steady_clock::now();
-  b->used += need;
   b->queue.push_back((int)k);
   b->work_cv.notify_one();
   *slot = (int32_t)k;
