@@ -193,6 +193,10 @@ def precision_form(egt, torch, G, steps, fp64, reps):
     res = r["last"]
     ms_iter = r["elapsed"] / sum(r["iters"]) * 1e3
     fp64_ms_iter = fp64["elapsed"] / sum(fp64["iters"]) * 1e3
+    # FP64 with the same gap cadence (the best responses of the gap run only
+    # on the iterations that test it)
+    r10 = timed_solves(egt, torch, G, 1, 0, gap_every=10)
+    fp64_10_ms_iter = r10["elapsed"] / sum(r10["iters"]) * 1e3
     y32 = egt.uniform(G, 1).float().contiguous()
     out32 = G.empty(0, dtype=torch.float32)
     prod_s = _timed(torch, lambda: egt.gradient_mixed(G, 0, y32, out32), reps)
@@ -203,6 +207,8 @@ def precision_form(egt, torch, G, steps, fp64, reps):
         ms_per_solve=r["elapsed"] / steps * 1e3, ms_per_iteration=ms_iter, iters_per_solve=sum(r["iters"]) / steps,
         p50_ms=percentile(r["lat"], 50) * 1e3, p99_ms=percentile(r["lat"], 99) * 1e3,
         speedup_per_iteration_vs_fp64=fp64_ms_iter / ms_iter,
+        fp64_gap_every_10_ms_per_iteration=fp64_10_ms_iter,
+        speedup_per_iteration_vs_fp64_same_gap_cadence=fp64_10_ms_iter / ms_iter,
         speedup_per_solve_vs_fp64=(fp64["elapsed"] / len(fp64["lat"])) / (r["elapsed"] / steps),
         final_gap_fp64=res["gap"], value_minus_fp64=res["value_p1"] - fp64["last"]["value_p1"],
         product_us=round(prod_s * 1e6, 3), gemm_dense_gflop=flops / 1e9,

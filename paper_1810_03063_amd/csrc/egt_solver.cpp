@@ -489,8 +489,10 @@ void accept_rotate(egt_state* st) {
 
 // One attempt of the step focused on p at step size tau on the buffers of v,
 // with mu.  first = compute x_bar (otherwise reuse it).  Leaves the two EGV
-// terms (and in FP64 the two best-response values of the candidate's saddle
-// gap) as root partials in v.part; returns the number of value trees.
+// terms (and with with_gap the two best-response values of the candidate's
+// saddle gap: FP64 trees in the same launch, or in the precision form the
+// widened iterates through FP64 products) as root partials in v.part;
+// returns the number of value trees.
 static int attempt_v(egt_state* st, const View& v, int p, double tau, const double mu[2], bool first,
                      hipStream_t s, int* trees_out, bool with_gap = false) {
   const egt_game* g = st->g;
@@ -519,7 +521,7 @@ static int attempt_v(egt_state* st, const View& v, int p, double tau, const doub
     ps[0] = Pass{p, v.G[p], kSg[p] * (1.0 - tau), st->T1[p], kSg[p] * tau, mu_new, st->V[p], nullptr};
   ps[1] = Pass{o, v.T2[o], kSg[o], nullptr, 0.0, mu[o], st->V[o], nullptr};
   int trees = 2;
-  if (st->prec == kF64) {
+  if (st->prec == kF64 && with_gap) {
     if (fresh)
       gap_passes(st, v.T2[0], 1.0, nullptr, 0.0, v.T2[1], 1.0, nullptr, 0.0, ps + 2);
     else if (p == 0)
@@ -589,7 +591,8 @@ int step_launch(egt_state* st, int player, hipStream_t s) {
     first = true;
   }
   int rc, trees = 0;
-  if ((rc = attempt_v(st, current_view(st), st->step_p, st->step_tau, st->mu, first, s, &trees))) return rc;
+  if ((rc = attempt_v(st, current_view(st), st->step_p, st->step_tau, st->mu, first, s, &trees, st->prec == kF64)))
+    return rc;
   st->products += products_per_attempt(st);
   return enqueue_values(st, trees, s, st->hpart);
 }
@@ -766,7 +769,7 @@ int solve_loop_pipelined(egt_state* st, hipStream_t s, const std::atomic<bool>* 
   int p, trees = 0, cur = 0;
   double tau;
   side_and_tau(st, st->t, st->mu, st->tau, &p, &tau);
-  bool wg = mixed && gap_due(st->t + 1);
+  bool wg = gap_due(st->t + 1);
   if ((rc = attempt_v(st, current_view(st), p, tau, st->mu, true, s, &trees, wg))) return rc;
   EGT_TRY(hipEventRecord(st->ev[cur], s));
   for (;;) {
@@ -778,7 +781,7 @@ int solve_loop_pipelined(egt_state* st, hipStream_t s, const std::atomic<bool>* 
       double mu2[2] = {st->mu[0], st->mu[1]};
       mu2[p] *= (1.0 - tau);
       side_and_tau(st, st->t + 1, mu2, op.variant == EGT_VARIANT_AS ? tau : st->tau, &p2, &tau2);
-      if ((rc = attempt_v(st, next_view(st), p2, tau2, mu2, true, s, &t2))) return rc;
+      if ((rc = attempt_v(st, next_view(st), p2, tau2, mu2, true, s, &t2, gap_due(st->t + 2)))) return rc;
       EGT_TRY(hipEventRecord(st->ev[1 - cur], s));
       spec = true;
     }
@@ -821,14 +824,13 @@ int solve_loop_pipelined(egt_state* st, hipStream_t s, const std::atomic<bool>* 
       return rc;
     }
     cur = 1 - cur;
+    wg = gap_due(st->t + 1);  // (a speculated attempt ran only where the precision form tests no gap)
     if (spec) {
       p = p2;
       tau = tau2;
       trees = t2;
-      wg = false;
     } else {
       side_and_tau(st, st->t, st->mu, st->tau, &p, &tau);
-      wg = mixed && gap_due(st->t + 1);
       if ((rc = attempt_v(st, current_view(st), p, tau, st->mu, true, s, &trees, wg))) return rc;
       EGT_TRY(hipEventRecord(st->ev[cur], s));
     }
