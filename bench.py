@@ -40,9 +40,9 @@ CSRC = os.path.join(ROOT, "paper_1810_03063_amd", "csrc")
 # records the SHA-256 of the kernel's source file when the counters were
 # taken; a changed source makes the figure stale, and `traffic` is then null.
 COUNTERS = {
-    ("sbr_fused_kernel", "c1"): dict(fetch_kib=1145.6, write_kib=1895.5, fetch_factor=2.0, write_factor=1.0,
+    ("sbr_fused_kernel", "c1"): dict(fetch_kib=1145.5, write_kib=1895.5, fetch_factor=2.0, write_factor=1.0,
                                      source="egt_kernels.hip",
-                                     sha256="9089b8909de03b98abaa975e32f94e585e40190ad4e9f5f83c79265a6f456bc6"),
+                                     sha256="bae256900bb824f95e22d363d4c5a0cbb68cfa84534f8d711e985cf5b8baac1c"),
     ("product_kernel", "c1"): dict(fetch_kib=1521.7, write_kib=1895.5, fetch_factor=2.0, write_factor=1.0,
                                    source="egt_product.hip",
                                    sha256="fd172f962b87ba664bd46c9509a7e59c46f70ce9468aadd405a35e30c4be1b48"),
@@ -85,6 +85,8 @@ def parse():
                          "saturated batched throughput")
     ap.add_argument("--serve-shapes", default="c0,c1,c2,c3")
     ap.add_argument("--serve-budget-gb", type=float, default=16.0)
+    ap.add_argument("--serve-small-shapes", default="c0,c1,c2",
+                    help="shapes of a second saturated trace without the largest endgame ('' = skip)")
     ap.add_argument("--other-paths", type=int, default=1, help="CFR+, mirror prox and general-game measurements")
     ap.add_argument("--cfr-iters", type=int, default=20000)
     ap.add_argument("--fom-iters", type=int, default=2000)
@@ -355,10 +357,32 @@ def serving(egt, args):
     note("Poisson arrivals, batched FP64", loaded64)
     seq_out, seq_wall = serve_sequential(solve_one, reqs_for(rate))
     baseline = summarize(seq_out, seq_wall)
-    return dict(shapes=list(shapes), requests=n, budget_gb=args.serve_budget_gb, saturated=saturated,
-                saturated_sequential_fp64=seq_saturated,
-                capacity_vs_sequential=saturated["solves_per_sec"] / seq_saturated["solves_per_sec"],
-                poisson_rate_per_s=rate, batched=loaded, batched_fp64=loaded64, sequential_fp64=baseline)
+    note("Poisson arrivals, one at a time", baseline)
+    out = dict(shapes=list(shapes), requests=n, budget_gb=args.serve_budget_gb, saturated=saturated,
+               saturated_sequential_fp64=seq_saturated,
+               capacity_vs_sequential=saturated["solves_per_sec"] / seq_saturated["solves_per_sec"],
+               poisson_rate_per_s=rate, batched=loaded, batched_fp64=loaded64, sequential_fp64=baseline)
+    if args.serve_small_shapes:
+        # the same saturated comparison without the 8-size endgame, whose
+        # kernels fill the device by themselves
+        small = tuple(args.serve_small_shapes.split(","))
+
+        def small_reqs():
+            tr = serving_trace(2 * n, rate=0.0, seed=12, shapes=small)
+            return [Request(i, a, make_instance(shape, seed)) for i, (a, shape, seed) in enumerate(tr)]
+
+        eng = LibEngine(egt, budget, max_slots=64, precision="fp64", gap_every=1)
+        o, w = serve(eng, small_reqs())
+        eng.close()
+        sb = summarize(o, w)
+        so, sw = serve_sequential(solve_one, small_reqs())
+        ss = summarize(so, sw)
+        note(f"saturated {','.join(small)}, batched FP64", sb)
+        note(f"saturated {','.join(small)}, one at a time", ss)
+        out["small_shapes"] = dict(shapes=list(small), requests=2 * n, saturated_batched_fp64=sb,
+                                   saturated_sequential_fp64=ss,
+                                   capacity_vs_sequential=sb["solves_per_sec"] / ss["solves_per_sec"])
+    return out
 
 
 def cpu_info():
