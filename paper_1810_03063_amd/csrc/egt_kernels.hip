@@ -635,7 +635,7 @@ __global__ __launch_bounds__(64) void sum_partials_kernel(const double* partial,
 struct DownArgs {
   const int* anc;
   const void* QB;
-  int n, ld;
+  int n, ld, n_seq;
   void* q_out;
   const void* x_prev;
   double tau;
@@ -684,9 +684,15 @@ __global__ __launch_bounds__(kPassThreads) void top_down_pair_kernel(DownArgs a)
   TS* q_out = (TS*)a.q_out;
   TS* comb_out = (TS*)a.comb_out;
   const TS* x_prev = (const TS*)a.x_prev;
-  const int h = 2 * (blockIdx.x * kPassThreads + threadIdx.x);  // ld is even: h + 1 < ld too
-  const int s = blockIdx.y;
-  if (h >= a.ld) return;
+  // one-dimensional grid of (hand block, sequence) pairs in hand-block-major
+  // order, dealt to the XCDs in contiguous ranges: the blocks of one XCD share
+  // hand blocks, so the ancestor rows each sequence multiplies along its path
+  // are re-read from that XCD's L2
+  const int nbx = (a.ld / 2 + kPassThreads - 1) / kPassThreads;
+  const int pos = xcd_spread((int)blockIdx.x, (int)gridDim.x);
+  const int s = pos % a.n_seq, hb = pos / a.n_seq;
+  const int h = 2 * (hb * kPassThreads + threadIdx.x);  // ld is even: h + 1 < ld too
+  if (hb >= nbx || h >= a.ld) return;
   const size_t idx = (size_t)s * a.ld + h;
   const int* path = a.anc + (size_t)s * kMaxDepth;
   V2 f[kMaxDepth];
@@ -938,10 +944,12 @@ hipError_t launch_top_down(const egt_game* g, int player, const void* QB, void* 
   a.x_prev = x_prev;
   a.tau = tau;
   a.comb_out = comb_out;
+  a.n_seq = g->dp[player].n_seq;
+  if (a.n_seq == 0) return hipSuccess;
   const size_t pair_bytes = prec == kF32 ? 8 : 16;
   auto aligned = [&](const void* ptr) { return ((uintptr_t)ptr % pair_bytes) == 0; };
   if (g->ld % 2 == 0 && aligned(QB) && aligned(q_out) && aligned(x_prev) && aligned(comb_out)) {
-    const dim3 grid((unsigned)((g->ld / 2 + kPassThreads - 1) / kPassThreads), g->dp[player].n_seq);
+    const dim3 grid((unsigned)((g->ld / 2 + kPassThreads - 1) / kPassThreads) * (unsigned)g->dp[player].n_seq);
     if (prec == kF32)
       hipLaunchKernelGGL(top_down_pair_kernel<float>, grid, dim3(kPassThreads), 0, s, a);
     else
