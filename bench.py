@@ -261,9 +261,9 @@ def other_paths(egt, torch, args):
     """The paper's comparison methods and extensions, measured beside the
     headline: CFR+ to the same gap target on the second endgame (gradient
     computations against EGT's, the comparison of Section 7), mirror prox
-    there (Section 8), and the general route (Section 6): Leduc hold'em solved
-    to 1e-3 of its pot and the CSR product's roofline on a seeded random game
-    tree."""
+    there (Section 8), an endgame with Section 7's Libratus-style bet sizes,
+    and the general route (Section 6): Leduc hold'em solved to 1e-3 of its
+    pot and the CSR product's roofline on a seeded random game tree."""
     from instances import make_instance
     from instances.efg import leduc, random_efg
 
@@ -295,6 +295,16 @@ def other_paths(egt, torch, args):
         mirror_prox=dict(iters=args.fom_iters, step=args.fom_step, gap=mp_gap, seconds=t4 - t3,
                          iters_per_sec=args.fom_iters / (t4 - t3)),
     )
+    li = make_instance("lib", args.seed)
+    GL = egt.Game(li)
+    r = timed_solves(egt, torch, GL, 3, 1)
+    out["libratus_abstraction"] = dict(
+        workload=f"lib: 52-card river endgame, {GL.n} hands/player, Section 7's Libratus-style bet sizes with open "
+                 f"folds, {GL.n_seq[0] * GL.n} + {GL.n_seq[1] * GL.n} (sequence, hand) pairs; FP64 EGT/AS to gap <= "
+                 f"1e-3*pot",
+        solves_per_sec=3 / r["elapsed"], iters_per_solve=sum(r["iters"]) / 3,
+        ms_per_iteration=r["elapsed"] / sum(r["iters"]) * 1e3, final_gap=r["last"]["gap"], eps=1e-3 * li.pot)
+    GL.close()
     lg = leduc()
     GG = egt.GeneralGame(lg)
     r = timed_solves(egt, torch, GG, 3, 1)
