@@ -56,6 +56,14 @@ struct egt_state {
   void* T1[2] = {};
   void* T2[2] = {};
   void* QB[2] = {};
+  // FP64 level path: the local strategies q_bar of the smoothed best response
+  // that opens the next iteration, written by this iteration's value launch
+  // (whose EGV tree of that side is the same bottom-up pass), and what they
+  // were computed from: side, gradient buffer and mu (side -1: none)
+  void* QN[2] = {};
+  int qn_side = -1;
+  const void* qn_grad = nullptr;
+  double qn_mu = 0.0;
   // spares that let the next iteration run before this one is decided: on
   // acceptance X <- Xn <- Xs <- X and G <- T2 <- Gs <- G rotate, Xbar and the
   // partial-sum buffers alternate, so a rejected step still finds its x, G and
@@ -318,6 +326,7 @@ int state_create_in(const egt_game* g, const egt_solve_opts* o, hipStream_t s, v
     st->Xs[p] = take(vb);
     st->Gs[p] = take(vb);
     st->Xbar2[p] = take(vb);
+    if (!mixed && !g->fused_passes) st->QN[p] = take(vb);
     st->V[p] = (double*)take(sizeof(double) * (size_t)g->hp[p].n_nodes * g->ld);
     st->Vb[p] = (double*)take(sizeof(double) * (size_t)g->hp[p].n_nodes * g->ld);
     if (mixed) {
@@ -487,19 +496,32 @@ void accept_rotate(egt_state* st) {
   std::swap(st->hpart_dev, st->hpart2_dev);
 }
 
+void side_and_tau(const egt_state* st, int64_t t, const double mu[2], double tau_as, int* p, double* tau);
+
 // One attempt of the step focused on p at step size tau on the buffers of v,
-// with mu.  first = compute x_bar (otherwise reuse it).  Leaves the two EGV
+// with mu, as iteration t_at (the number of steps accepted before it).
+// first = compute x_bar (otherwise reuse it).  Leaves the two EGV
 // terms (and with with_gap the two best-response values of the candidate's
 // saddle gap: FP64 trees in the same launch, or in the precision form the
 // widened iterates through FP64 products) as root partials in v.part;
 // returns the number of value trees.
-static int attempt_v(egt_state* st, const View& v, int p, double tau, const double mu[2], bool first,
-                     hipStream_t s, int* trees_out, bool with_gap = false) {
+//
+// On the FP64 level path x_bar's bottom-up pass is usually already done: the
+// EGV tree of the side that steps next is the bottom-up pass of exactly the
+// smoothed best response that opens the next iteration (same gradient, bit
+// for bit, same mu), so the value launch also keeps that tree's q_bar (in QN)
+// and the next first attempt runs only the top-down pass on it.
+static int attempt_v(egt_state* st, const View& v, int64_t t_at, int p, double tau, const double mu[2],
+                     bool first, hipStream_t s, int* trees_out, bool with_gap = false) {
   const egt_game* g = st->g;
   const int o = 1 - p;
   int rc;
   if (first) {
-    if ((rc = sbr(st, p, v.G[p], kSg[p], nullptr, 0.0, mu[p], v.Xbar[p], v.X[p], tau, st->Xhat[p], s))) return rc;
+    if (st->qn_side == p && st->qn_grad == v.G[p] && st->qn_mu == mu[p]) {
+      EGT_TRY(launch_top_down(g, p, st->QN[p], v.Xbar[p], v.X[p], tau, st->Xhat[p], s, st->prec));
+    } else if ((rc = sbr(st, p, v.G[p], kSg[p], nullptr, 0.0, mu[p], v.Xbar[p], v.X[p], tau, st->Xhat[p], s))) {
+      return rc;
+    }
   } else {
     if ((rc = axpby(st, p, 1.0 - tau, v.X[p], tau, v.Xbar[p], st->Xhat[p], s))) return rc;
   }
@@ -537,6 +559,20 @@ static int attempt_v(egt_state* st, const View& v, int p, double tau, const doub
   if (!fresh) {
     epi[0].g_out = v.T2[p];
     epi[0].g_scale = kSg[p];
+  }
+  // the side of the iteration after this one if it is accepted: its EGV tree
+  // keeps q_bar for that iteration's first smoothed best response (the
+  // gradient it reads then is T2 of that side: kSg * (kSg * g~) = g~ exactly)
+  st->qn_side = -1;
+  if (st->QN[0]) {
+    double mu_n[2] = {mu[0], mu[1]}, tau_n;
+    mu_n[p] = mu_new;
+    int pn;
+    side_and_tau(st, t_at + 1, mu_n, tau, &pn, &tau_n);
+    ps[pn == p ? 0 : 1].QB = st->QN[pn];
+    st->qn_side = pn;
+    st->qn_grad = v.T2[pn];
+    st->qn_mu = mu_n[pn];
   }
   EGT_TRY(launch_passes(g, ps, trees, epi, v.part_dev, s, st->prec));
   if (with_gap && st->prec == kF32) {
@@ -591,7 +627,8 @@ int step_launch(egt_state* st, int player, hipStream_t s) {
     first = true;
   }
   int rc, trees = 0;
-  if ((rc = attempt_v(st, current_view(st), st->step_p, st->step_tau, st->mu, first, s, &trees, st->prec == kF64)))
+  if ((rc = attempt_v(st, current_view(st), st->t, st->step_p, st->step_tau, st->mu, first, s, &trees,
+                       st->prec == kF64)))
     return rc;
   st->products += products_per_attempt(st);
   return enqueue_values(st, trees, s, st->hpart);
@@ -681,6 +718,7 @@ int state_set(egt_state* st, const double* x, const double* y, double mu_x, doub
     return fail(EGT_EINVAL, "mu must be finite and > 0");
   if (!(tau > 0) || !(tau < 1)) return fail(EGT_EINVAL, "tau must lie in (0, 1)");
   if (iters < 0) return fail(EGT_EINVAL, "iters < 0");
+  st->qn_side = -1;  // G changes: no kept q_bar matches it
   int rc;
   if ((rc = narrow(st, 0, x, st->X[0], s))) return rc;
   if ((rc = narrow(st, 1, y, st->X[1], s))) return rc;
@@ -770,7 +808,7 @@ int solve_loop_pipelined(egt_state* st, hipStream_t s, const std::atomic<bool>* 
   double tau;
   side_and_tau(st, st->t, st->mu, st->tau, &p, &tau);
   bool wg = gap_due(st->t + 1);
-  if ((rc = attempt_v(st, current_view(st), p, tau, st->mu, true, s, &trees, wg))) return rc;
+  if ((rc = attempt_v(st, current_view(st), st->t, p, tau, st->mu, true, s, &trees, wg))) return rc;
   EGT_TRY(hipEventRecord(st->ev[cur], s));
   for (;;) {
     // the next iteration, assuming acceptance
@@ -781,7 +819,7 @@ int solve_loop_pipelined(egt_state* st, hipStream_t s, const std::atomic<bool>* 
       double mu2[2] = {st->mu[0], st->mu[1]};
       mu2[p] *= (1.0 - tau);
       side_and_tau(st, st->t + 1, mu2, op.variant == EGT_VARIANT_AS ? tau : st->tau, &p2, &tau2);
-      if ((rc = attempt_v(st, next_view(st), p2, tau2, mu2, true, s, &t2, gap_due(st->t + 2)))) return rc;
+      if ((rc = attempt_v(st, next_view(st), st->t + 1, p2, tau2, mu2, true, s, &t2, gap_due(st->t + 2)))) return rc;
       EGT_TRY(hipEventRecord(st->ev[1 - cur], s));
       spec = true;
     }
@@ -798,7 +836,7 @@ int solve_loop_pipelined(egt_state* st, hipStream_t s, const std::atomic<bool>* 
       st->backtracks++;
       if (tau < kTauFloor) return fail(EGT_ENOTCONV, "tau fell below 1e-30 in the EGT/as backtracking");
       // retry from x_hat with the halved tau, behind the discarded iteration
-      if ((rc = attempt_v(st, current_view(st), p, tau, st->mu, false, s, &trees, wg))) return rc;
+      if ((rc = attempt_v(st, current_view(st), st->t, p, tau, st->mu, false, s, &trees, wg))) return rc;
       EGT_TRY(hipEventRecord(st->ev[cur], s));
       continue;
     }
@@ -831,7 +869,7 @@ int solve_loop_pipelined(egt_state* st, hipStream_t s, const std::atomic<bool>* 
       trees = t2;
     } else {
       side_and_tau(st, st->t, st->mu, st->tau, &p, &tau);
-      if ((rc = attempt_v(st, current_view(st), p, tau, st->mu, true, s, &trees, wg))) return rc;
+      if ((rc = attempt_v(st, current_view(st), st->t, p, tau, st->mu, true, s, &trees, wg))) return rc;
       EGT_TRY(hipEventRecord(st->ev[cur], s));
     }
   }
@@ -871,7 +909,8 @@ int64_t state_bytes(const egt_game* g, bool mixed) {
   for (int p = 0; p < 2; ++p) {
     bytes += esz * 11 * (size_t)vec_elems(g, p) + sizeof(double) * 2 * (size_t)g->hp[p].n_nodes * g->ld;
     if (mixed) bytes += sizeof(double) * 2 * (size_t)vec_elems(g, p);
-    bytes += 15 * 256;
+    if (!mixed && !g->fused_passes) bytes += esz * (size_t)vec_elems(g, p);  // QN
+    bytes += 16 * 256;
   }
   bytes += 64 * sizeof(double) + 256;
   return (int64_t)bytes;

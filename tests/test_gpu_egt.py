@@ -336,6 +336,39 @@ def test_repeatable_and_checkpoint_resume_bitwise(egt):
     assert torch.equal(c["x"], a["x"]) and torch.equal(c["y"], a["y"])
 
 
+@pytest.mark.parametrize("variant,fresh", [("AS", False), ("ALT", False), ("AS", True)])
+def test_kept_local_strategies_bitwise(egt, variant, fresh):
+    """On the level path (c3) the value launch keeps the local strategies of
+    the next iteration's first smoothed best response (its EGV tree of that
+    side is the same bottom-up pass).  Stepping with them kept, and solving
+    with the pipelined loop, must give bit for bit what stepping with the full
+    pass gives (a state_set before every step drops what is kept)."""
+    inst = make_instance("c3", 0)
+    print(f"[case] kept q_bar c3 {variant} fresh={fresh}", flush=True)
+    G = egt.Game(inst)
+    n = 14
+    kw = dict(variant=variant, eps=1e-300, fresh_products=fresh)
+    a = egt.State(G, max_iters=10**9, **kw)
+    b = egt.State(G, max_iters=10**9, **kw)
+    sides_a, sides_b = [], []
+    for _ in range(n):
+        sides_a.append(a.step()[1])
+        f = b.get()
+        ay, atx = b.products()
+        b.set(f["x"], f["y"], f["mu_x"], f["mu_y"], f["tau"], f["iters"], ay, atx)
+        sides_b.append(b.step()[1])
+    r, c = egt.solve(G, keep_state=True, max_iters=n, **kw)
+    assert r["status"] == "EGT_ENOTCONV" and r["iters"] == n
+    assert sides_a == sides_b and len(set(sides_a)) == 2, "both sides step, so both kinds of reuse run"
+    fa, fb, fc = a.get(), b.get(), c.get()
+    for f in (fb, fc):
+        assert torch.equal(fa["x"], f["x"]) and torch.equal(fa["y"], f["y"])
+        assert (fa["mu_x"], fa["mu_y"], fa["tau"]) == (f["mu_x"], f["mu_y"], f["tau"])
+    for st in (a, b, c):
+        st.close()
+    G.close()
+
+
 def test_iteration_cap_reports_not_converged(egt):
     inst = make_instance("c0", 0)
     G = egt.Game(inst)
