@@ -150,6 +150,7 @@ struct TreePass {
   double cB;
   double mu;
   double* V;       // node values by value slot (FusedTabLayout): always FP64
+  double* VB;      // level path: also the best-response node values of the same gradient (mu = 0), or null
   void* QB;        // q_bar in the launch's precision
   void* g_out;     // g_scale (cA gA + cB gB), or null (the epilogue's g_out)
   double g_scale;
@@ -179,7 +180,11 @@ struct Epilogue {
   double g_scale;
 };
 
-// Host description of one pass (player instead of device tables).
+// Host description of one pass (player instead of device tables).  With VB
+// the pass is dual: besides its smoothed values it yields the best response
+// (mu = 0) to the same gradient, node values in VB; a launch of `count` passes
+// then returns the dual passes' best-response values after the `count`
+// smoothed ones, in pass order.
 struct Pass {
   int player;
   const void* gA;
@@ -189,6 +194,7 @@ struct Pass {
   double mu;
   double* V;
   void* QB;
+  double* VB = nullptr;
 };
 
 // Element type of the gradients, q_bar and strategies of a launch: FP64, or

@@ -349,6 +349,9 @@ __global__ __launch_bounds__(kPassThreads) void bottom_up_level_kernel(PassSet a
     t.V[(size_t)r.z * ld + h] = m;
     return;
   }
+  // dual pass: below a node without child nodes the best response's g~ is
+  // the same, so its value is the minimum
+  if (t.VB) t.VB[(size_t)r.z * ld + h] = m;
   const double temp = t.mu * p0.x;
   double sum = 0.0;
 #pragma unroll
@@ -430,6 +433,7 @@ __global__ __launch_bounds__(kPassThreads) void bottom_up_leaf_pair_kernel(PassS
     store_pair(Vrow, m0, m1, both);
     return;
   }
+  if (t.VB) store_pair(t.VB + (size_t)r.z * ld + h, m0, m1, both);  // dual pass: the best response's value
   const double temp = t.mu * p0.x;
   double sum0 = 0.0, sum1 = 0.0;
 #pragma unroll
@@ -460,7 +464,10 @@ __global__ __launch_bounds__(kPassThreads) void bottom_up_leaf_pair_kernel(PassS
 // added in slot order.  The node's g~ and weights meet in LDS; the minimum,
 // the weight sum and the value are then formed in the same order as above, so
 // per hand the result is bitwise the one the one-wavefront form gives.
-template <class TG, int HP>
+// DUAL: trees with VB also take the best response to the same gradient: the
+// g~ with the children's best-response values (in the same order), staged in
+// the weights' array, and its minimum.
+template <class TG, int HP, bool DUAL>
 __global__ __launch_bounds__(kPassThreads * kInternalWaves) void bottom_up_internal_kernel(PassSet a) {
   static_assert(HP == 1 || HP == 2, "one or two hands per lane");
   using V2 = typename std::conditional<std::is_same<TG, float>::value, float2, double2>::type;
@@ -504,6 +511,7 @@ __global__ __launch_bounds__(kPassThreads * kInternalWaves) void bottom_up_inter
     else
       p[0] = (std::remove_pointer_t<decltype(p)>)x0;
   };
+  const bool dual = DUAL && t.VB != nullptr;
   for (int jj = j; live && jj < na; jj += nw) {
     const size_t idx = (size_t)(s0 + jj) * ld + h;
     double x0, x1, b0, b1;
@@ -517,13 +525,19 @@ __global__ __launch_bounds__(kPassThreads * kInternalWaves) void bottom_up_inter
       x1 = t.cA * x1;
     }
     if (t.g_out) store2((TG*)t.g_out + idx, x0 * t.g_scale, x1 * t.g_scale);
+    double xb0 = x0, xb1 = x1;
     const int c0 = cbeg[s0 + jj], c1 = cbeg[s0 + jj + 1];
     for (int c = c0; c < c1; c += kChildBatch) {
       double cv0[kChildBatch], cv1[kChildBatch];
+      double cb0[DUAL ? kChildBatch : 1], cb1[DUAL ? kChildBatch : 1];
 #pragma unroll
       for (int u = 0; u < kChildBatch; ++u) {
         cv0[u] = 0.0;
         cv1[u] = 0.0;
+        if constexpr (DUAL) {
+          cb0[u] = 0.0;
+          cb1[u] = 0.0;
+        }
         if (c + u < c1) {
           const double* vp = t.V + (size_t)(c + u) * ld + h;
           if constexpr (HP == 2) {
@@ -533,6 +547,18 @@ __global__ __launch_bounds__(kPassThreads * kInternalWaves) void bottom_up_inter
           } else {
             cv0[u] = vp[0];
           }
+          if constexpr (DUAL) {
+            if (dual) {
+              const double* bp = t.VB + (size_t)(c + u) * ld + h;
+              if constexpr (HP == 2) {
+                const double2 q = *(const double2*)bp;
+                cb0[u] = q.x;
+                cb1[u] = q.y;
+              } else {
+                cb0[u] = bp[0];
+              }
+            }
+          }
         }
       }
 #pragma unroll
@@ -540,10 +566,18 @@ __global__ __launch_bounds__(kPassThreads * kInternalWaves) void bottom_up_inter
         if (c + u < c1) {
           x0 += cv0[u];
           x1 += cv1[u];
+          if constexpr (DUAL) {
+            xb0 += cb0[u];
+            xb1 += cb1[u];
+          }
         }
     }
     gl[jj][lane] = x0;
     if constexpr (HP == 2) gl[jj][kPassThreads + lane] = x1;
+    if (dual) {
+      wl[jj][lane] = xb0;
+      if constexpr (HP == 2) wl[jj][kPassThreads + lane] = xb1;
+    }
   }
   __syncthreads();
   double m0 = INFINITY, m1 = INFINITY;
@@ -556,6 +590,17 @@ __global__ __launch_bounds__(kPassThreads * kInternalWaves) void bottom_up_inter
   if (!(t.mu > 0.0)) {
     if (act && j == 0) store2(Vrow, m0, m1);
     return;
+  }
+  if (dual) {
+    if (act && j == 0) {
+      double mb0 = INFINITY, mb1 = INFINITY;
+      for (int i = 0; i < na; ++i) {
+        mb0 = fmin(mb0, wl[i][lane]);
+        if constexpr (HP == 2) mb1 = fmin(mb1, wl[i][kPassThreads + lane]);
+      }
+      store2(t.VB + (size_t)r.z * ld + h, mb0, mb1);
+    }
+    __syncthreads();  // the weights below overwrite wl
   }
   const double temp = t.mu * p0.x;
   for (int jj = j; live && jj < na; jj += nw) {
@@ -582,12 +627,18 @@ __global__ __launch_bounds__(kPassThreads * kInternalWaves) void bottom_up_inter
 }
 
 // Root sums of the level path: block k sums tree k, roots in order (value
-// slots C + r), hands strided over the threads, then a fixed-order reduction.
+// slots C + r), hands strided over the threads, then a fixed-order reduction;
+// blocks count + k sum the best-response values of dual tree k.
 __global__ __launch_bounds__(256) void root_sums_kernel(PassSet a, double* out) {
   constexpr int kRootBatch = 4;                     // roots whose values are requested together
   constexpr int kHandSteps = 8;                     // hands per thread and root (n <= 2048 = 256 x 8)
   __shared__ double part[4];
-  const TreePass& t = a.t[blockIdx.x];
+  const TreePass& t = a.t[blockIdx.x % a.count];
+  const double* Vsrc = (int)blockIdx.x < a.count ? t.V : t.VB;
+  if (!Vsrc) {
+    if (threadIdx.x == 0) out[blockIdx.x] = 0.0;
+    return;
+  }
   double s = 0.0;
   const int C = t.P.n_nodes - t.P.n_roots;  // the r-th root's value slot is C + r
   // each thread adds its hands h = tid + 256 m root by root, m ascending; the
@@ -596,7 +647,7 @@ __global__ __launch_bounds__(256) void root_sums_kernel(PassSet a, double* out) 
     double v[kRootBatch][kHandSteps];
 #pragma unroll
     for (int u = 0; u < kRootBatch; ++u) {
-      const double* row = t.V + (size_t)(C + r0 + u) * a.ld;
+      const double* row = Vsrc + (size_t)(C + r0 + u) * a.ld;
 #pragma unroll
       for (int m = 0; m < kHandSteps; ++m) {
         const int h = (int)threadIdx.x + 256 * m;
@@ -816,6 +867,7 @@ static void fill_pass_set(const egt_game* g, const Pass* p, int count, PassSet& 
     t.cB = p[k].cB;
     t.mu = p[k].mu;
     t.V = p[k].V;
+    t.VB = p[k].VB;
     t.QB = p[k].QB;
     t.g_out = nullptr;
     t.g_scale = 0.0;
@@ -838,11 +890,28 @@ size_t fused_lds_bytes(int hands, int cap_tab_bytes, int cap_nodes, int cap_seqs
 template <class TG>
 static hipError_t passes_launch(const egt_game* g, const Pass* p, int count, const Epilogue* epi, double* partial,
                                 hipStream_t s) {
+  bool any_dual = false;
+  for (int k = 0; k < count; ++k) any_dual = any_dual || p[k].VB != nullptr;
+  const int n_epi = count;  // epilogues belong to the passes as given
   if (g->fused_passes) {
+    // a dual pass becomes a second tree with mu = 0 after the others
+    Pass q[kMaxTrees];
+    int nq = 0;
+    for (int k = 0; k < count; ++k) {
+      q[nq] = p[k];
+      q[nq++].VB = nullptr;
+    }
+    for (int k = 0; k < count; ++k) {
+      if (!p[k].VB) continue;
+      if (nq >= kMaxTrees) return hipErrorInvalidValue;
+      q[nq++] = Pass{p[k].player, p[k].gA, p[k].cA, p[k].gB, p[k].cB, 0.0, p[k].VB, nullptr};
+    }
+    p = q;
+    count = nq;
     FusedArgs a;
     fill_pass_set(g, p, count, a.ps);
     for (int k = 0; k < kMaxTrees; ++k)
-      a.epi[k] = (epi && k < count) ? epi[k] : Epilogue{nullptr, nullptr, 0.0, nullptr, nullptr, 0.0};
+      a.epi[k] = (epi && k < n_epi) ? epi[k] : Epilogue{nullptr, nullptr, 0.0, nullptr, nullptr, 0.0};
     a.partial = partial;
     a.cap_tab = (int)std::max(g->hp[0].fused_tab.size(), g->hp[1].fused_tab.size());
     a.cap_nodes = std::max(g->hp[0].n_nodes, g->hp[1].n_nodes);
@@ -875,7 +944,8 @@ static hipError_t passes_launch(const egt_game* g, const Pass* p, int count, con
     auto ok = [&](const void* ptr) { return ((uintptr_t)ptr % pb) == 0; };
     for (int k = 0; k < count; ++k) {
       const TreePass& t = a.t[k];
-      pair = pair && ok(t.gA) && ok(t.gB) && ok(t.g_out) && ok(t.QB) && ((uintptr_t)t.V % 16) == 0;
+      pair = pair && ok(t.gA) && ok(t.gB) && ok(t.g_out) && ok(t.QB) && ((uintptr_t)t.V % 16) == 0 &&
+             ((uintptr_t)t.VB % 16) == 0;
     }
   }
   for (int l = 0; l < max_levels; ++l) {
@@ -899,16 +969,23 @@ static hipError_t passes_launch(const egt_game* g, const Pass* p, int count, con
       wa = std::min(wa, kInternalWaves);  // a wavefront takes actions j, j + wa, ... beyond that
       // two hands per lane only where the level fills the chip several times
       // over; a narrow level is latency-bound and gains from more lanes
-      if (pair && (size_t)bx * total >= 4 * (size_t)g->n_cu)
-        hipLaunchKernelGGL((bottom_up_internal_kernel<TG, 2>), dim3(bx_pair, total), dim3(kPassThreads, wa), 0, s, a);
+      const bool hp2 = pair && (size_t)bx * total >= 4 * (size_t)g->n_cu;
+      if (hp2 && any_dual)
+        hipLaunchKernelGGL((bottom_up_internal_kernel<TG, 2, true>), dim3(bx_pair, total), dim3(kPassThreads, wa), 0, s,
+                           a);
+      else if (hp2)
+        hipLaunchKernelGGL((bottom_up_internal_kernel<TG, 2, false>), dim3(bx_pair, total), dim3(kPassThreads, wa), 0,
+                           s, a);
+      else if (any_dual)
+        hipLaunchKernelGGL((bottom_up_internal_kernel<TG, 1, true>), dim3(bx, total), dim3(kPassThreads, wa), 0, s, a);
       else
-        hipLaunchKernelGGL((bottom_up_internal_kernel<TG, 1>), dim3(bx, total), dim3(kPassThreads, wa), 0, s, a);
+        hipLaunchKernelGGL((bottom_up_internal_kernel<TG, 1, false>), dim3(bx, total), dim3(kPassThreads, wa), 0, s, a);
     }
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
   if (partial) {
-    hipLaunchKernelGGL(root_sums_kernel, dim3(count), dim3(256), 0, s, a, partial);
+    hipLaunchKernelGGL(root_sums_kernel, dim3(count * (any_dual ? 2 : 1)), dim3(256), 0, s, a, partial);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }

@@ -536,7 +536,7 @@ static int attempt_v(egt_state* st, const View& v, int64_t t_at, int p, double t
   const double mu_new = (1.0 - tau) * mu[p];
   // one launch for the value passes: EGV at (x_+, y_+) with mu_p+ and the
   // unchanged mu_o, and (FP64) the two best responses of the candidate's gap
-  Pass ps[4];
+  Pass ps[2];
   if (fresh)
     ps[0] = Pass{p, v.T2[p], kSg[p], nullptr, 0.0, mu_new, st->V[p], nullptr};
   else
@@ -544,18 +544,16 @@ static int attempt_v(egt_state* st, const View& v, int64_t t_at, int p, double t
   ps[1] = Pass{o, v.T2[o], kSg[o], nullptr, 0.0, mu[o], st->V[o], nullptr};
   int trees = 2;
   if (st->prec == kF64 && with_gap) {
-    if (fresh)
-      gap_passes(st, v.T2[0], 1.0, nullptr, 0.0, v.T2[1], 1.0, nullptr, 0.0, ps + 2);
-    else if (p == 0)
-      gap_passes(st, v.G[0], 1.0 - tau, st->T1[0], tau, v.T2[1], 1.0, nullptr, 0.0, ps + 2);
-    else
-      gap_passes(st, v.T2[0], 1.0, nullptr, 0.0, v.G[1], 1.0 - tau, st->T1[1], tau, ps + 2);
+    // the two trees are dual: each also takes the best response to its own
+    // gradient (the products at (x_+, y_+)), values 2 (p) and 3 (o)
+    ps[0].VB = st->Vb[p];
+    ps[1].VB = st->Vb[o];
     trees = 4;
   }
   // without fresh products the value launch also writes the accepted product
   // (1-tau) G[p] + tau T1[p] of tree 0 into T2[p], so accepting the step is a
   // rotation of buffers either way
-  Epilogue epi[4] = {};
+  Epilogue epi[2] = {};
   if (!fresh) {
     epi[0].g_out = v.T2[p];
     epi[0].g_scale = kSg[p];
@@ -574,7 +572,7 @@ static int attempt_v(egt_state* st, const View& v, int64_t t_at, int p, double t
     st->qn_grad = v.T2[pn];
     st->qn_mu = mu_n[pn];
   }
-  EGT_TRY(launch_passes(g, ps, trees, epi, v.part_dev, s, st->prec));
+  EGT_TRY(launch_passes(g, ps, 2, epi, v.part_dev, s, st->prec));
   if (with_gap && st->prec == kF32) {
     // precision form: the candidate's saddle gap in FP64 (widened iterates,
     // FP64 products, FP64 best responses) as values 2 and 3
@@ -592,6 +590,18 @@ static int attempt_v(egt_state* st, const View& v, int64_t t_at, int p, double t
 }
 
 int products_per_attempt(const egt_state* st) { return st->opts.fresh_products ? 4 : 3; }
+
+// The saddle gap an accepted attempt focused on p carried (values 2 and 3 of
+// its value launch): in FP64 the dual trees' best responses of p and of the
+// other player, in the precision form those of players 1 and 2 in order.
+void take_gap(egt_state* st, int p) {
+  const int i0 = (st->prec == kF64 && p == 1) ? 3 : 2;  // player 1's best response
+  const int i1 = 5 - i0;
+  st->br_min_x = st->hscal[i0];
+  st->br_max_y = -st->hscal[i1];
+  st->gap = -st->hscal[i1] - st->hscal[i0];
+  st->gap_valid = true;
+}
 
 // Side and step size of an iteration after t accepted steps (the variant's
 // rule: alternate with 2 / (t + 3), the larger mu with 2 / (t + 3), or the
@@ -658,14 +668,10 @@ int step_finish(egt_state* st, hipStream_t s, int* accepted, double* egv_out, in
   st->mu[p] *= (1.0 - tau);
   if (st->opts.variant == EGT_VARIANT_AS) st->tau = tau;
   st->t++;
-  if (trees == 4) {
-    st->br_min_x = st->hscal[2];
-    st->br_max_y = -st->hscal[3];
-    st->gap = -st->hscal[3] - st->hscal[2];
-    st->gap_valid = true;
-  } else {
+  if (trees == 4)
+    take_gap(st, p);
+  else
     st->gap_valid = false;
-  }
   st->last_egv = egv;
   st->step_open = false;
   *accepted = 1;
@@ -844,14 +850,10 @@ int solve_loop_pipelined(egt_state* st, hipStream_t s, const std::atomic<bool>* 
     st->mu[p] *= (1.0 - tau);
     if (op.variant == EGT_VARIANT_AS) st->tau = tau;
     st->t++;
-    if (trees == 4) {
-      st->br_min_x = st->hscal[2];
-      st->br_max_y = -st->hscal[3];
-      st->gap = -st->hscal[3] - st->hscal[2];
-      st->gap_valid = true;
-    } else {
+    if (trees == 4)
+      take_gap(st, p);
+    else
       st->gap_valid = false;
-    }
     st->last_egv = egv;
     if (gap_due(st->t) && st->gap_valid && st->gap <= op.eps) {
       *converged = true;
