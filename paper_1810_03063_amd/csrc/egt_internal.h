@@ -150,7 +150,7 @@ struct TreePass {
   double cB;
   double mu;
   double* V;       // node values by value slot (FusedTabLayout): always FP64
-  double* VB;      // level path: also the best-response node values of the same gradient (mu = 0), or null
+  double* VB;      // lowest level of the level path: also the best response's node values (the minimum), or null
   void* QB;        // q_bar in the launch's precision
   void* g_out;     // g_scale (cA gA + cB gB), or null (the epilogue's g_out)
   double g_scale;

@@ -464,10 +464,7 @@ __global__ __launch_bounds__(kPassThreads) void bottom_up_leaf_pair_kernel(PassS
 // added in slot order.  The node's g~ and weights meet in LDS; the minimum,
 // the weight sum and the value are then formed in the same order as above, so
 // per hand the result is bitwise the one the one-wavefront form gives.
-// DUAL: trees with VB also take the best response to the same gradient: the
-// g~ with the children's best-response values (in the same order), staged in
-// the weights' array, and its minimum.
-template <class TG, int HP, bool DUAL>
+template <class TG, int HP>
 __global__ __launch_bounds__(kPassThreads * kInternalWaves) void bottom_up_internal_kernel(PassSet a) {
   static_assert(HP == 1 || HP == 2, "one or two hands per lane");
   using V2 = typename std::conditional<std::is_same<TG, float>::value, float2, double2>::type;
@@ -511,7 +508,6 @@ __global__ __launch_bounds__(kPassThreads * kInternalWaves) void bottom_up_inter
     else
       p[0] = (std::remove_pointer_t<decltype(p)>)x0;
   };
-  const bool dual = DUAL && t.VB != nullptr;
   for (int jj = j; live && jj < na; jj += nw) {
     const size_t idx = (size_t)(s0 + jj) * ld + h;
     double x0, x1, b0, b1;
@@ -525,19 +521,13 @@ __global__ __launch_bounds__(kPassThreads * kInternalWaves) void bottom_up_inter
       x1 = t.cA * x1;
     }
     if (t.g_out) store2((TG*)t.g_out + idx, x0 * t.g_scale, x1 * t.g_scale);
-    double xb0 = x0, xb1 = x1;
     const int c0 = cbeg[s0 + jj], c1 = cbeg[s0 + jj + 1];
     for (int c = c0; c < c1; c += kChildBatch) {
       double cv0[kChildBatch], cv1[kChildBatch];
-      double cb0[DUAL ? kChildBatch : 1], cb1[DUAL ? kChildBatch : 1];
 #pragma unroll
       for (int u = 0; u < kChildBatch; ++u) {
         cv0[u] = 0.0;
         cv1[u] = 0.0;
-        if constexpr (DUAL) {
-          cb0[u] = 0.0;
-          cb1[u] = 0.0;
-        }
         if (c + u < c1) {
           const double* vp = t.V + (size_t)(c + u) * ld + h;
           if constexpr (HP == 2) {
@@ -547,18 +537,6 @@ __global__ __launch_bounds__(kPassThreads * kInternalWaves) void bottom_up_inter
           } else {
             cv0[u] = vp[0];
           }
-          if constexpr (DUAL) {
-            if (dual) {
-              const double* bp = t.VB + (size_t)(c + u) * ld + h;
-              if constexpr (HP == 2) {
-                const double2 q = *(const double2*)bp;
-                cb0[u] = q.x;
-                cb1[u] = q.y;
-              } else {
-                cb0[u] = bp[0];
-              }
-            }
-          }
         }
       }
 #pragma unroll
@@ -566,18 +544,10 @@ __global__ __launch_bounds__(kPassThreads * kInternalWaves) void bottom_up_inter
         if (c + u < c1) {
           x0 += cv0[u];
           x1 += cv1[u];
-          if constexpr (DUAL) {
-            xb0 += cb0[u];
-            xb1 += cb1[u];
-          }
         }
     }
     gl[jj][lane] = x0;
     if constexpr (HP == 2) gl[jj][kPassThreads + lane] = x1;
-    if (dual) {
-      wl[jj][lane] = xb0;
-      if constexpr (HP == 2) wl[jj][kPassThreads + lane] = xb1;
-    }
   }
   __syncthreads();
   double m0 = INFINITY, m1 = INFINITY;
@@ -590,17 +560,6 @@ __global__ __launch_bounds__(kPassThreads * kInternalWaves) void bottom_up_inter
   if (!(t.mu > 0.0)) {
     if (act && j == 0) store2(Vrow, m0, m1);
     return;
-  }
-  if (dual) {
-    if (act && j == 0) {
-      double mb0 = INFINITY, mb1 = INFINITY;
-      for (int i = 0; i < na; ++i) {
-        mb0 = fmin(mb0, wl[i][lane]);
-        if constexpr (HP == 2) mb1 = fmin(mb1, wl[i][kPassThreads + lane]);
-      }
-      store2(t.VB + (size_t)r.z * ld + h, mb0, mb1);
-    }
-    __syncthreads();  // the weights below overwrite wl
   }
   const double temp = t.mu * p0.x;
   for (int jj = j; live && jj < na; jj += nw) {
@@ -627,18 +586,12 @@ __global__ __launch_bounds__(kPassThreads * kInternalWaves) void bottom_up_inter
 }
 
 // Root sums of the level path: block k sums tree k, roots in order (value
-// slots C + r), hands strided over the threads, then a fixed-order reduction;
-// blocks count + k sum the best-response values of dual tree k.
+// slots C + r), hands strided over the threads, then a fixed-order reduction.
 __global__ __launch_bounds__(256) void root_sums_kernel(PassSet a, double* out) {
   constexpr int kRootBatch = 4;                     // roots whose values are requested together
   constexpr int kHandSteps = 8;                     // hands per thread and root (n <= 2048 = 256 x 8)
   __shared__ double part[4];
-  const TreePass& t = a.t[blockIdx.x % a.count];
-  const double* Vsrc = (int)blockIdx.x < a.count ? t.V : t.VB;
-  if (!Vsrc) {
-    if (threadIdx.x == 0) out[blockIdx.x] = 0.0;
-    return;
-  }
+  const TreePass& t = a.t[blockIdx.x];
   double s = 0.0;
   const int C = t.P.n_nodes - t.P.n_roots;  // the r-th root's value slot is C + r
   // each thread adds its hands h = tid + 256 m root by root, m ascending; the
@@ -647,7 +600,7 @@ __global__ __launch_bounds__(256) void root_sums_kernel(PassSet a, double* out) 
     double v[kRootBatch][kHandSteps];
 #pragma unroll
     for (int u = 0; u < kRootBatch; ++u) {
-      const double* row = Vsrc + (size_t)(C + r0 + u) * a.ld;
+      const double* row = t.V + (size_t)(C + r0 + u) * a.ld;
 #pragma unroll
       for (int m = 0; m < kHandSteps; ++m) {
         const int h = (int)threadIdx.x + 256 * m;
@@ -948,15 +901,38 @@ static hipError_t passes_launch(const egt_game* g, const Pass* p, int count, con
              ((uintptr_t)t.VB % 16) == 0;
     }
   }
-  for (int l = 0; l < max_levels; ++l) {
-    unsigned total = 0;
+  // Dual passes: the lowest level takes the best response with the smoothed
+  // pass (the same minimum); above it the best responses run as trees of
+  // their own (mu = 0, node values in VB, their children's values read from
+  // there), after the given ones in the same launches.
+  PassSet ax = a;
+  if (any_dual) {
+    int nx = count;
     for (int k = 0; k < count; ++k) {
-      const TreePass& t = a.t[k];
-      a.level_cnt[k] = l < t.n_levels ? t.level_begin[l + 1] - t.level_begin[l] : 0;
-      total += (unsigned)a.level_cnt[k];
+      ax.t[k].VB = nullptr;
+      if (!p[k].VB) continue;
+      if (nx >= kMaxTrees) return hipErrorInvalidValue;
+      TreePass& b = ax.t[nx++];
+      b = a.t[k];
+      b.mu = 0.0;
+      b.V = p[k].VB;
+      b.VB = nullptr;
+      b.QB = nullptr;
+      b.g_out = nullptr;
+      b.g_scale = 0.0;
+    }
+    ax.count = nx;
+  }
+  for (int l = 0; l < max_levels; ++l) {
+    PassSet& cur = l == 0 ? a : ax;
+    unsigned total = 0;
+    for (int k = 0; k < cur.count; ++k) {
+      const TreePass& t = cur.t[k];
+      cur.level_cnt[k] = l < t.n_levels ? t.level_begin[l + 1] - t.level_begin[l] : 0;
+      total += (unsigned)cur.level_cnt[k];
     }
     if (total == 0) continue;
-    a.level = l;
+    cur.level = l;
     if (l == 0 && pair) {
       hipLaunchKernelGGL(bottom_up_leaf_pair_kernel<TG>, dim3(bx_pair, total), dim3(kPassThreads), 0, s, a);
     } else if (l == 0) {
@@ -969,23 +945,16 @@ static hipError_t passes_launch(const egt_game* g, const Pass* p, int count, con
       wa = std::min(wa, kInternalWaves);  // a wavefront takes actions j, j + wa, ... beyond that
       // two hands per lane only where the level fills the chip several times
       // over; a narrow level is latency-bound and gains from more lanes
-      const bool hp2 = pair && (size_t)bx * total >= 4 * (size_t)g->n_cu;
-      if (hp2 && any_dual)
-        hipLaunchKernelGGL((bottom_up_internal_kernel<TG, 2, true>), dim3(bx_pair, total), dim3(kPassThreads, wa), 0, s,
-                           a);
-      else if (hp2)
-        hipLaunchKernelGGL((bottom_up_internal_kernel<TG, 2, false>), dim3(bx_pair, total), dim3(kPassThreads, wa), 0,
-                           s, a);
-      else if (any_dual)
-        hipLaunchKernelGGL((bottom_up_internal_kernel<TG, 1, true>), dim3(bx, total), dim3(kPassThreads, wa), 0, s, a);
+      if (pair && (size_t)bx * total >= 4 * (size_t)g->n_cu)
+        hipLaunchKernelGGL((bottom_up_internal_kernel<TG, 2>), dim3(bx_pair, total), dim3(kPassThreads, wa), 0, s, ax);
       else
-        hipLaunchKernelGGL((bottom_up_internal_kernel<TG, 1, false>), dim3(bx, total), dim3(kPassThreads, wa), 0, s, a);
+        hipLaunchKernelGGL((bottom_up_internal_kernel<TG, 1>), dim3(bx, total), dim3(kPassThreads, wa), 0, s, ax);
     }
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
   if (partial) {
-    hipLaunchKernelGGL(root_sums_kernel, dim3(count * (any_dual ? 2 : 1)), dim3(256), 0, s, a, partial);
+    hipLaunchKernelGGL(root_sums_kernel, dim3(ax.count), dim3(256), 0, s, ax, partial);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
