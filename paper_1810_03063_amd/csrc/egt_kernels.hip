@@ -338,7 +338,10 @@ __global__ __launch_bounds__(kPassThreads) void bottom_up_level_kernel(PassSet a
     if (j < na) {
       const size_t idx = (size_t)(s0 + j) * ld + h;
       double x = gB ? lin2(t.cA, (double)gA[idx], t.cB, (double)gB[idx]) : t.cA * (double)gA[idx];
-      if (g_out) g_out[idx] = (TG)(x * t.g_scale);
+      if (g_out) {
+        g_out[idx] = (TG)(x * t.g_scale);
+        x = (double)(TG)x;  // continue with the stored gradient (g_scale = +-1)
+      }
       const int c1 = cbeg[s0 + j + 1];
       for (int c = cbeg[s0 + j]; c < c1; ++c) x += t.V[(size_t)c * ld + h];
       g[j] = x;
@@ -421,7 +424,11 @@ __global__ __launch_bounds__(kPassThreads) void bottom_up_leaf_pair_kernel(PassS
         x0 = lin2(t.cA, (double)A.x, t.cB, (double)B.x);
         x1 = lin2(t.cA, (double)A.y, t.cB, (double)B.y);
       }
-      if (g_out) store_pair(g_out + idx, x0 * t.g_scale, x1 * t.g_scale, both);
+      if (g_out) {
+        store_pair(g_out + idx, x0 * t.g_scale, x1 * t.g_scale, both);
+        x0 = (double)(TG)x0;  // continue with the stored gradient (g_scale = +-1)
+        x1 = (double)(TG)x1;
+      }
       g0[j] = x0;
       g1[j] = x1;
       m0 = fmin(m0, x0);
@@ -520,7 +527,11 @@ __global__ __launch_bounds__(kPassThreads * kInternalWaves) void bottom_up_inter
       x0 = t.cA * x0;
       x1 = t.cA * x1;
     }
-    if (t.g_out) store2((TG*)t.g_out + idx, x0 * t.g_scale, x1 * t.g_scale);
+    if (t.g_out) {
+      store2((TG*)t.g_out + idx, x0 * t.g_scale, x1 * t.g_scale);
+      x0 = (double)(TG)x0;  // continue with the stored gradient (g_scale = +-1)
+      x1 = (double)(TG)x1;
+    }
     const int c0 = cbeg[s0 + jj], c1 = cbeg[s0 + jj + 1];
     for (int c = c0; c < c1; c += kChildBatch) {
       double cv0[kChildBatch], cv1[kChildBatch];

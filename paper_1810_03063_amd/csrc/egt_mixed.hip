@@ -10,8 +10,8 @@
 // showdown columns r_z form Y (n x L), and C = W Y is computed as
 // W Y_hi + W Y_lo with Y_hi = bf16(Y) and Y_lo = bf16(Y - Y_hi): W is exact in
 // BF16, each BF16 x BF16 product is exact in FP32, the accumulation is FP32.
-// The fold terminals keep their O(n) per-card evaluation (in FP64 arithmetic,
-// FP32 output) in launch_gradient_fold_f32, which also zeroes the rows; the
+// The fold terminals keep their O(n) per-card evaluation (in FP32) in
+// launch_gradient_fold_f32, which also zeroes the other rows; the
 // GEMM epilogue then adds the showdown part.  Each own sequence has at most
 // one showdown terminal (checked when the tables are built), so every output
 // element is updated by exactly one lane.

@@ -79,7 +79,6 @@ struct ProdArgs {
   TO* out;
   double show_sign;
   int groups;
-  int fold_only;           // skip showdown terminals (their part is added by the BF16 GEMM)
   const TermItem* items;   // work items instead of whole sequences, or null
   int n_items;
 };
@@ -196,7 +195,7 @@ __global__ __launch_bounds__(2 * kGroupThreads, MINW) void product_kernel(ProdAr
   for (int k = 0; k < HPT; ++k) acc[k] = 0.0;
   while (w < n_work) {
     // uniform within a group
-    const bool active = tr.kind >= 0 && !(a.fold_only && tr.kind != 0);
+    const bool active = tr.kind >= 0;
     const int kind = tr.kind;
     const double coef = tr.coef;
     // 1. stage the reach into R (strength order) and E (card lists)
@@ -373,6 +372,108 @@ __global__ __launch_bounds__(2 * kGroupThreads, MINW) void product_kernel(ProdAr
   }
 }
 
+// Precision form, fold terminals only (the BF16 GEMM adds the showdown
+// terminals' part afterwards), in FP32: one block per own sequence.  For each
+// fold terminal of the sequence the opponent's reach r(h') is staged into the
+// card lists E (each hand in the list of each of its cards), the card totals
+// C[c] are summed (four lanes per list, a quarter each, the quarters added in
+// a fixed order) into the list's total slot, the total T is summed (each
+// thread's hands, then the wavefronts in order), and
+//   op(h) = T - C[a] - C[b] + r(h)      (hand h holds cards a and b)
+// is accumulated with the terminal's chips.  The row gets b_own(h)/Z times
+// the sum (0 without fold terminals), its padding 0.
+struct FoldArgs {
+  DPlayer own;
+  const double* b_opp;
+  DHands H;
+  const float* v_opp;
+  float* out;
+};
+
+template <int HPT>
+__global__ __launch_bounds__(kGroupThreads) void fold_kernel(FoldArgs a) {
+  extern __shared__ __align__(16) float E[];  // [n_card_slots]
+  __shared__ float wtot[kGroupThreads / 64];
+  const int s = (int)blockIdx.x;
+  const int n = a.H.n, ld = a.H.ld, cph = a.H.cph;
+  const int tid = (int)threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int MT = a.own.term_stride;
+  float bo[HPT], acc[HPT];
+  unsigned hp[HPT], tot[HPT];  // the hand's E slots; E slots of its cards' totals (16 bits each)
+#pragma unroll
+  for (int k = 0; k < HPT; ++k) {
+    const int i = tid + k * kGroupThreads;
+    acc[k] = 0.0f;
+    bo[k] = i < n ? (float)a.b_opp[i] : 0.0f;
+    hp[k] = i < n ? a.H.hpos[i] : 0u;
+    tot[k] = 0u;
+    if (i < n) {
+      const uint4 t = a.H.htab[i];
+      tot[k] = (t.y & 0xffffu) | (t.z & 0xffff0000u);
+    }
+  }
+  for (int j = 0; j < MT; ++j) {
+    const TermRec tr = a.own.term_rec[(size_t)s * MT + j];  // uniform over the block
+    if (tr.kind != 0) continue;
+    const float* row = tr.opp >= 0 ? a.v_opp + (size_t)tr.opp * ld : nullptr;
+    float r[HPT];
+    float loc = 0.0f;
+#pragma unroll
+    for (int k = 0; k < HPT; ++k) {
+      const int i = tid + k * kGroupThreads;
+      r[k] = i < n ? bo[k] * (row ? row[i] : 1.0f) : 0.0f;
+    }
+#pragma unroll
+    for (int k = 0; k < HPT; ++k) {
+      const int i = tid + k * kGroupThreads;
+      if (i < n) {
+        E[hp[k] & 0xffffu] = r[k];
+        if (cph == 2) E[hp[k] >> 16] = r[k];
+      }
+      loc += r[k];
+    }
+    for (int off = 32; off > 0; off >>= 1) loc += __shfl_xor(loc, off, 64);
+    if (lane == 0) wtot[wv] = loc;
+    __syncthreads();
+    // card totals into each list's total slot
+    for (int c0 = 0; c0 < a.H.n_cards; c0 += kGroupThreads / 4) {
+      const int c = c0 + (tid >> 2), sub = tid & 3;
+      const bool valid = c < a.H.n_cards;
+      const int cb = valid ? a.H.card_begin[c] : 0;
+      const int len = valid ? a.H.card_begin[c + 1] - cb : 0;
+      float* L = E + cb + c;
+      const int qlen = (len + 3) >> 2;
+      const int lo = min(sub * qlen, len), hi = min(lo + qlen, len);
+      float part = 0.0f;
+      for (int k = lo; k < hi; ++k) part += L[k];
+      const int q0 = lane & ~3;
+      const float p0 = __shfl(part, q0, 64), p1 = __shfl(part, q0 + 1, 64), p2 = __shfl(part, q0 + 2, 64),
+                  p3 = __shfl(part, q0 + 3, 64);
+      if (valid && sub == 0) L[len] = ((p0 + p1) + p2) + p3;  // the total slot follows the list
+    }
+    const float T = ((wtot[0] + wtot[1]) + wtot[2]) + wtot[3];
+    __syncthreads();
+    const float coef = (float)tr.coef;
+#pragma unroll
+    for (int k = 0; k < HPT; ++k) {
+      const int i = tid + k * kGroupThreads;
+      if (i < n) {
+        float op = T - E[tot[k] & 0xffffu];
+        if (cph == 2) op = (op - E[tot[k] >> 16]) + r[k];
+        acc[k] += coef * op;
+      }
+    }
+    __syncthreads();  // the next terminal restages E
+  }
+  float* out = a.out + (size_t)s * ld;
+#pragma unroll
+  for (int k = 0; k < HPT; ++k) {
+    const int i = tid + k * kGroupThreads;
+    if (i < n) out[i] = acc[k] * (float)(a.own.belief[i] * a.H.invZ);
+  }
+  for (int i = n + tid; i < ld; i += kGroupThreads) out[i] = 0.0f;
+}
+
 size_t align2(size_t x) { return (x + 1) / 2 * 2; }
 
 // General games (Section 6's explicit sparse operator): one wavefront per CSR
@@ -409,8 +510,7 @@ size_t product_group_doubles(const egt_game* g) { return align2((size_t)g->n + 1
 size_t product_table_bytes(const egt_game* g) { return (16 + 8) * (size_t)g->n; }
 
 template <class TV, class TO>
-static hipError_t product_launch(const egt_game* g, int player, const TV* v_opp, TO* grad_out, int fold_only,
-                                 hipStream_t s) {
+static hipError_t product_launch(const egt_game* g, int player, const TV* v_opp, TO* grad_out, hipStream_t s) {
   ProdArgs<TV, TO> a;
   a.own = g->dp[player];
   a.b_opp = g->dp[1 - player].belief;
@@ -418,7 +518,6 @@ static hipError_t product_launch(const egt_game* g, int player, const TV* v_opp,
   a.v_opp = v_opp;
   a.out = grad_out;
   a.show_sign = player == 0 ? 1.0 : -1.0;
-  a.fold_only = fold_only;
   a.items = nullptr;
   a.n_items = 0;
   // two blocks per compute unit: each takes at most half of the CU's LDS
@@ -461,13 +560,29 @@ static hipError_t product_launch(const egt_game* g, int player, const TV* v_opp,
 
 hipError_t launch_gradient(const egt_game* g, int player, const double* v_opp, double* grad_out, hipStream_t s) {
   if (g->general) return launch_spmv(g, player, v_opp, grad_out, s);
-  return product_launch<double, double>(g, player, v_opp, grad_out, 0, s);
+  return product_launch<double, double>(g, player, v_opp, grad_out, s);
 }
 
 hipError_t launch_gradient_fold_f32(const egt_game* g, int player, const float* v_opp, float* grad_out,
                                     hipStream_t s) {
   if (g->general) return hipErrorInvalidValue;  // the precision form is river-only
-  return product_launch<float, float>(g, player, v_opp, grad_out, 1, s);
+  const DPlayer& P = g->dp[player];
+  if (P.n_seq == 0) return hipSuccess;
+  FoldArgs a;
+  a.own = P;
+  a.b_opp = g->dp[1 - player].belief;
+  a.H = g->dh;
+  a.v_opp = v_opp;
+  a.out = grad_out;
+  const size_t lds = sizeof(float) * (size_t)g->dh.n_card_slots;
+  const dim3 grid((unsigned)P.n_seq), block(kGroupThreads);
+  if (g->n <= 2 * kGroupThreads)
+    hipLaunchKernelGGL(fold_kernel<2>, grid, block, lds, s, a);
+  else if (g->n <= 5 * kGroupThreads)
+    hipLaunchKernelGGL(fold_kernel<5>, grid, block, lds, s, a);
+  else
+    hipLaunchKernelGGL(fold_kernel<8>, grid, block, lds, s, a);
+  return hipGetLastError();
 }
 
 }  // namespace egt

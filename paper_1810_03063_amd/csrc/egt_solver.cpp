@@ -56,7 +56,7 @@ struct egt_state {
   void* T1[2] = {};
   void* T2[2] = {};
   void* QB[2] = {};
-  // FP64 level path: the local strategies q_bar of the smoothed best response
+  // level path: the local strategies q_bar of the smoothed best response
   // that opens the next iteration, written by this iteration's value launch
   // (whose EGV tree of that side is the same bottom-up pass), and what they
   // were computed from: side, gradient buffer and mu (side -1: none)
@@ -326,7 +326,7 @@ int state_create_in(const egt_game* g, const egt_solve_opts* o, hipStream_t s, v
     st->Xs[p] = take(vb);
     st->Gs[p] = take(vb);
     st->Xbar2[p] = take(vb);
-    if (!mixed && !g->fused_passes) st->QN[p] = take(vb);
+    if (!g->fused_passes) st->QN[p] = take(vb);
     st->V[p] = (double*)take(sizeof(double) * (size_t)g->hp[p].n_nodes * g->ld);
     st->Vb[p] = (double*)take(sizeof(double) * (size_t)g->hp[p].n_nodes * g->ld);
     if (mixed) {
@@ -506,11 +506,12 @@ void side_and_tau(const egt_state* st, int64_t t, const double mu[2], double tau
 // widened iterates through FP64 products) as root partials in v.part;
 // returns the number of value trees.
 //
-// On the FP64 level path x_bar's bottom-up pass is usually already done: the
-// EGV tree of the side that steps next is the bottom-up pass of exactly the
+// On the level path x_bar's bottom-up pass is usually already done: the EGV
+// tree of the side that steps next is the bottom-up pass of exactly the
 // smoothed best response that opens the next iteration (same gradient, bit
-// for bit, same mu), so the value launch also keeps that tree's q_bar (in QN)
-// and the next first attempt runs only the top-down pass on it.
+// for bit, since the tree that stores the accepted product continues with
+// the stored values; same mu), so the value launch also keeps that tree's
+// q_bar (in QN) and the next first attempt runs only the top-down pass on it.
 static int attempt_v(egt_state* st, const View& v, int64_t t_at, int p, double tau, const double mu[2],
                      bool first, hipStream_t s, int* trees_out, bool with_gap = false) {
   const egt_game* g = st->g;
@@ -911,7 +912,7 @@ int64_t state_bytes(const egt_game* g, bool mixed) {
   for (int p = 0; p < 2; ++p) {
     bytes += esz * 11 * (size_t)vec_elems(g, p) + sizeof(double) * 2 * (size_t)g->hp[p].n_nodes * g->ld;
     if (mixed) bytes += sizeof(double) * 2 * (size_t)vec_elems(g, p);
-    if (!mixed && !g->fused_passes) bytes += esz * (size_t)vec_elems(g, p);  // QN
+    if (!g->fused_passes) bytes += esz * (size_t)vec_elems(g, p);  // QN
     bytes += 16 * 256;
   }
   bytes += 64 * sizeof(double) + 256;

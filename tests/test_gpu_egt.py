@@ -336,18 +336,19 @@ def test_repeatable_and_checkpoint_resume_bitwise(egt):
     assert torch.equal(c["x"], a["x"]) and torch.equal(c["y"], a["y"])
 
 
-@pytest.mark.parametrize("variant,fresh", [("AS", False), ("ALT", False), ("AS", True)])
-def test_kept_local_strategies_bitwise(egt, variant, fresh):
+@pytest.mark.parametrize("variant,fresh,precision", [("AS", False, "fp64"), ("ALT", False, "fp64"),
+                                                     ("AS", True, "fp64"), ("AS", False, "mixed")])
+def test_kept_local_strategies_bitwise(egt, variant, fresh, precision):
     """On the level path (c3) the value launch keeps the local strategies of
     the next iteration's first smoothed best response (its EGV tree of that
-    side is the same bottom-up pass).  Stepping with them kept, and solving
+    side is the same bottom-up pass, in FP64 and in the precision form).  Stepping with them kept, and solving
     with the pipelined loop, must give bit for bit what stepping with the full
     pass gives (a state_set before every step drops what is kept)."""
     inst = make_instance("c3", 0)
-    print(f"[case] kept q_bar c3 {variant} fresh={fresh}", flush=True)
+    print(f"[case] kept q_bar c3 {variant} fresh={fresh} {precision}", flush=True)
     G = egt.Game(inst)
     n = 14
-    kw = dict(variant=variant, eps=1e-300, fresh_products=fresh)
+    kw = dict(variant=variant, eps=1e-300, fresh_products=fresh, precision=precision)
     a = egt.State(G, max_iters=10**9, **kw)
     b = egt.State(G, max_iters=10**9, **kw)
     sides_a, sides_b = [], []

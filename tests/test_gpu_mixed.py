@@ -2,12 +2,13 @@
 stated and bounded.
 
 * product (BF16 hi+lo showdown GEMM with FP32 accumulation, fold terminals
-  in FP64 arithmetic): on FP32 inputs, compared with the oracle applied to the
+  in FP32 arithmetic): on FP32 inputs, compared with the oracle applied to the
   same FP32-rounded inputs.  Bound per entry:
       |err| <= 2e-4 * (b_own(h)/Z) * sum_z |u(z)| * sum_h' |r_z(h')|
   (Y in hi+lo BF16 keeps 2^-16 of each entry; FP32 accumulation over
   2 x n_pad <= 2176 terms adds at most 2176 x 2^-24 = 1.3e-4 of the absolute
-  sum; the observed errors are printed and are far smaller);
+  sum, and a fold terminal's FP32 sums over at most 2048 hands at most
+  2048 x 2^-24 = 1.2e-4; the observed errors are printed and are far smaller);
 * smoothed best response (FP32 exponentials and strategy, FP64 normalisers
   and values): |q_err| <= 1e-5, |value_err| <= 1e-6 (|value| + sum |V|);
 * one step from the oracle's iterate: strategies within 2e-3 of the oracle's
