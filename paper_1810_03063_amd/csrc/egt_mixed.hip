@@ -36,13 +36,26 @@ constexpr int kBatch = 3;     // k-steps whose operands a wave loads before mult
 constexpr int kRedStride = kTile + 1;
 constexpr int kTiledMinColumns = 512;  // from this many showdown columns on, the tiled GEMM
 
-__device__ inline unsigned short bf16_rn(float f) {
-  unsigned u = __float_as_uint(f);
-  u += 0x7fffu + ((u >> 16) & 1u);  // round to nearest, ties to even (finite inputs)
-  return (unsigned short)(u >> 16);
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+typedef __bf16 bf16x2v __attribute__((ext_vector_type(2)));
+
+// Two floats to BF16, round to nearest with ties to even (gfx950 converts a
+// pair in one instruction), packed low element first.
+__device__ inline unsigned bf16x2_rn(float a, float b) {
+  return __builtin_bit_cast(unsigned, __builtin_convertvector((f32x2){a, b}, bf16x2v));
 }
 
-__device__ inline float bf16_to_f32(unsigned short b) { return __uint_as_float(((unsigned)b) << 16); }
+// Eight FP32 reaches split into BF16 hi = bf16(r) and lo = bf16(r - hi).
+__device__ inline void split8(const float r[8], bf16x8& hi, bf16x8& lo) {
+  unsigned h[4], l[4];
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    h[e] = bf16x2_rn(r[2 * e], r[2 * e + 1]);
+    l[e] = bf16x2_rn(r[2 * e] - __uint_as_float(h[e] << 16), r[2 * e + 1] - __uint_as_float(h[e] & 0xffff0000u));
+  }
+  hi = __builtin_bit_cast(bf16x8, h);
+  lo = __builtin_bit_cast(bf16x8, l);
+}
 
 struct GemmArgs {
   const unsigned short* W;  // [ld][ld] BF16 bits, row h, contiguous h'
@@ -115,12 +128,7 @@ __global__ __launch_bounds__(64 * kKWaves) void show_gemm_kernel(GemmArgs a) {
       const float r[8] = {b0[u].x * v0[u].x, b0[u].y * v0[u].y, b0[u].z * v0[u].z, b0[u].w * v0[u].w,
                           b1[u].x * v1[u].x, b1[u].y * v1[u].y, b1[u].z * v1[u].z, b1[u].w * v1[u].w};
       bf16x8 hi, lo;
-#pragma unroll
-      for (int e = 0; e < 8; ++e) {
-        const unsigned short h16 = bf16_rn(r[e]);
-        hi[e] = (short)h16;
-        lo[e] = (short)bf16_rn(r[e] - bf16_to_f32(h16));
-      }
+      split8(r, hi, lo);
       const bf16x8 am = *(const bf16x8*)&av[u];
       acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(am, hi, acc, 0, 0, 0);
       acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(am, lo, acc, 0, 0, 0);
@@ -231,12 +239,7 @@ __global__ __launch_bounds__(256) void show_gemm_tiled_kernel(GemmArgs a) {
     const float r[8] = {b0.x * q.v0.x, b0.y * q.v0.y, b0.z * q.v0.z, b0.w * q.v0.w,
                         b1.x * q.v1.x, b1.y * q.v1.y, b1.z * q.v1.z, b1.w * q.v1.w};
     bf16x8 hi, lo;
-#pragma unroll
-    for (int e = 0; e < 8; ++e) {
-      const unsigned short h16 = bf16_rn(r[e]);
-      hi[e] = (short)h16;
-      lo[e] = (short)bf16_rn(r[e] - bf16_to_f32(h16));
-    }
+    split8(r, hi, lo);
     *(bf16x8*)&d.bh[bcol * kTKS + bk] = hi;
     *(bf16x8*)&d.bl[bcol * kTKS + bk] = lo;
   };
