@@ -41,14 +41,26 @@ constexpr int kFusedSlots = 64;        // fused pass: node slots per block (x HB
 //   node value           V = (m - mu beta log S) + mu beta log n, S = sum_a w_a
 //                        added in action order;
 //   local probability    q_bar_a = w_a / S.
-// The precision form takes the exponential in FP32 (of the FP64 argument)
-// and keeps S, the logarithm and V in FP64.
+// The precision form takes the exponential in FP32 of the FP64 shift times
+// 1/temp, keeps S, the logarithm and V in FP64, and forms q_bar with the FP32
+// reciprocal of S (itemp and rsum are used by the precision form only).
 template <class TG>
-__device__ inline double lse_weight(double m, double g, double temp) {
+__device__ inline double lse_weight(double m, double g, double temp, double itemp) {
   if constexpr (std::is_same<TG, float>::value)
-    return (double)expf((float)((m - g) / temp));
+    return (double)expf((float)((m - g) * itemp));
   else
     return exp((m - g) / temp);
+}
+template <class TG>
+__device__ inline double inv_or_zero(double x) {
+  return std::is_same<TG, float>::value ? 1.0 / x : 0.0;
+}
+template <class TG>
+__device__ inline double qbar(double w, double sum, double rsum) {
+  if constexpr (std::is_same<TG, float>::value)
+    return (double)((float)w * (float)rsum);
+  else
+    return w / sum;
 }
 __device__ inline double lse_value(double m, double temp, double sum, double logn) {
   return (m - temp * log(sum)) + temp * logn;
@@ -130,20 +142,21 @@ __device__ __forceinline__ void fused_node(const int4* rec, const double2* prm, 
     return;
   }
   const double2 p0 = prm[2 * v], p1 = prm[2 * v + 1];  // {beta, 1 / beta}, {log n_v, 0}
-  const double temp = mu * p0.x;
+  const double temp = mu * p0.x, itemp = inv_or_zero<TG>(temp);
   double sum = 0.0;
 #pragma unroll
   for (int k = 0; k < kMaxActions; ++k) {
     if (k < na) {
-      g[k] = lse_weight<TG>(m, g[k], temp);
+      g[k] = lse_weight<TG>(m, g[k], temp, itemp);
       sum += g[k];
     }
   }
   Vs[r.z * HB + hl] = lse_value(m, temp, sum, p1.x);
   if (want_q) {
+    const double rs = inv_or_zero<TG>(sum);
 #pragma unroll
     for (int k = 0; k < kMaxActions; ++k)
-      if (k < na) Ql[(s0 + k) * HB + hl] = (double)(TG)(g[k] / sum);
+      if (k < na) Ql[(s0 + k) * HB + hl] = (double)(TG)qbar<TG>(g[k], sum, rs);
   }
 }
 
@@ -355,20 +368,21 @@ __global__ __launch_bounds__(kPassThreads) void bottom_up_level_kernel(PassSet a
   // dual pass: below a node without child nodes the best response's g~ is
   // the same, so its value is the minimum
   if (t.VB) t.VB[(size_t)r.z * ld + h] = m;
-  const double temp = t.mu * p0.x;
+  const double temp = t.mu * p0.x, itemp = inv_or_zero<TG>(temp);
   double sum = 0.0;
 #pragma unroll
   for (int j = 0; j < kMaxActions; ++j) {
     if (j < na) {
-      g[j] = lse_weight<TG>(m, g[j], temp);
+      g[j] = lse_weight<TG>(m, g[j], temp, itemp);
       sum += g[j];
     }
   }
   t.V[(size_t)r.z * ld + h] = lse_value(m, temp, sum, p1.x);
   if (t.QB) {
+    const double rs = inv_or_zero<TG>(sum);
 #pragma unroll
     for (int j = 0; j < kMaxActions; ++j)
-      if (j < na) ((TG*)t.QB)[(size_t)(s0 + j) * ld + h] = (TG)(g[j] / sum);
+      if (j < na) ((TG*)t.QB)[(size_t)(s0 + j) * ld + h] = (TG)qbar<TG>(g[j], sum, rs);
   }
 }
 
@@ -441,22 +455,25 @@ __global__ __launch_bounds__(kPassThreads) void bottom_up_leaf_pair_kernel(PassS
     return;
   }
   if (t.VB) store_pair(t.VB + (size_t)r.z * ld + h, m0, m1, both);  // dual pass: the best response's value
-  const double temp = t.mu * p0.x;
+  const double temp = t.mu * p0.x, itemp = inv_or_zero<TG>(temp);
   double sum0 = 0.0, sum1 = 0.0;
 #pragma unroll
   for (int j = 0; j < kMaxActions; ++j) {
     if (j < na) {
-      g0[j] = lse_weight<TG>(m0, g0[j], temp);
-      g1[j] = lse_weight<TG>(m1, g1[j], temp);
+      g0[j] = lse_weight<TG>(m0, g0[j], temp, itemp);
+      g1[j] = lse_weight<TG>(m1, g1[j], temp, itemp);
       sum0 += g0[j];
       sum1 += g1[j];
     }
   }
   store_pair(Vrow, lse_value(m0, temp, sum0, p1.x), lse_value(m1, temp, sum1, p1.x), both);
   if (t.QB) {
+    const double rs0 = inv_or_zero<TG>(sum0), rs1 = inv_or_zero<TG>(sum1);
 #pragma unroll
     for (int j = 0; j < kMaxActions; ++j)
-      if (j < na) store_pair((TG*)t.QB + (size_t)(s0 + j) * ld + h, g0[j] / sum0, g1[j] / sum1, both);
+      if (j < na)
+        store_pair((TG*)t.QB + (size_t)(s0 + j) * ld + h, qbar<TG>(g0[j], sum0, rs0), qbar<TG>(g1[j], sum1, rs1),
+                   both);
   }
 }
 
@@ -572,11 +589,11 @@ __global__ __launch_bounds__(kPassThreads * kInternalWaves) void bottom_up_inter
     if (act && j == 0) store2(Vrow, m0, m1);
     return;
   }
-  const double temp = t.mu * p0.x;
+  const double temp = t.mu * p0.x, itemp = inv_or_zero<TG>(temp);
   for (int jj = j; live && jj < na; jj += nw) {
     double w1 = 0.0;
-    const double w0 = lse_weight<TG>(m0, gl[jj][lane], temp);
-    if constexpr (HP == 2) w1 = lse_weight<TG>(m1, gl[jj][kPassThreads + lane], temp);
+    const double w0 = lse_weight<TG>(m0, gl[jj][lane], temp, itemp);
+    if constexpr (HP == 2) w1 = lse_weight<TG>(m1, gl[jj][kPassThreads + lane], temp, itemp);
     wl[jj][lane] = w0;
     if constexpr (HP == 2) wl[jj][kPassThreads + lane] = w1;
   }
@@ -589,10 +606,12 @@ __global__ __launch_bounds__(kPassThreads * kInternalWaves) void bottom_up_inter
     }
     if (j == 0)
       store2(Vrow, lse_value(m0, temp, sum0, p1.x), HP == 2 ? lse_value(m1, temp, sum1, p1.x) : 0.0);
-    if (t.QB)
+    if (t.QB) {
+      const double rs0 = inv_or_zero<TG>(sum0), rs1 = inv_or_zero<TG>(sum1);
       for (int jj = j; jj < na; jj += nw)
-        store2((TG*)t.QB + (size_t)(s0 + jj) * ld + h, wl[jj][lane] / sum0,
-               HP == 2 ? wl[jj][kPassThreads + lane] / sum1 : 0.0);
+        store2((TG*)t.QB + (size_t)(s0 + jj) * ld + h, qbar<TG>(wl[jj][lane], sum0, rs0),
+               HP == 2 ? qbar<TG>(wl[jj][kPassThreads + lane], sum1, rs1) : 0.0);
+    }
   }
 }
 
