@@ -500,7 +500,7 @@ void side_and_tau(const egt_state* st, int64_t t, const double mu[2], double tau
 
 // One attempt of the step focused on p at step size tau on the buffers of v,
 // with mu, as iteration t_at (the number of steps accepted before it).
-// first = compute x_bar (otherwise reuse it).  Leaves the two EGV
+// first = the iteration's first attempt (otherwise a retry with a halved tau).  Leaves the two EGV
 // terms (and with with_gap the two best-response values of the candidate's
 // saddle gap: FP64 trees in the same launch, or in the precision form the
 // widened iterates through FP64 products) as root partials in v.part;
@@ -517,13 +517,17 @@ static int attempt_v(egt_state* st, const View& v, int64_t t_at, int p, double t
   const egt_game* g = st->g;
   const int o = 1 - p;
   int rc;
+  // x_bar itself is needed only when the attempt fails: the first attempt
+  // writes x_hat alone, a retry recomputes x_bar (the same pass on the same
+  // gradient and mu, so bit for bit the same) and combines it with the new tau
   if (first) {
     if (st->qn_side == p && st->qn_grad == v.G[p] && st->qn_mu == mu[p]) {
-      EGT_TRY(launch_top_down(g, p, st->QN[p], v.Xbar[p], v.X[p], tau, st->Xhat[p], s, st->prec));
-    } else if ((rc = sbr(st, p, v.G[p], kSg[p], nullptr, 0.0, mu[p], v.Xbar[p], v.X[p], tau, st->Xhat[p], s))) {
+      EGT_TRY(launch_top_down(g, p, st->QN[p], nullptr, v.X[p], tau, st->Xhat[p], s, st->prec));
+    } else if ((rc = sbr(st, p, v.G[p], kSg[p], nullptr, 0.0, mu[p], nullptr, v.X[p], tau, st->Xhat[p], s))) {
       return rc;
     }
   } else {
+    if ((rc = sbr(st, p, v.G[p], kSg[p], nullptr, 0.0, mu[p], v.Xbar[p], nullptr, 0.0, nullptr, s))) return rc;
     if ((rc = axpby(st, p, 1.0 - tau, v.X[p], tau, v.Xbar[p], st->Xhat[p], s))) return rc;
   }
   if ((rc = grad(st, o, st->Xhat[p], st->T1[o], s))) return rc;
