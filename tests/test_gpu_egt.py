@@ -348,7 +348,9 @@ def test_kept_local_strategies_bitwise(egt, variant, fresh, precision):
     print(f"[case] kept q_bar c3 {variant} fresh={fresh} {precision}", flush=True)
     G = egt.Game(inst)
     n = 14
-    kw = dict(variant=variant, eps=1e-300, fresh_products=fresh, precision=precision)
+    # tau0 = 0.9: the first EGT/as attempts fail the excessive gap test, so
+    # retries (which recompute x_bar) run between kept passes
+    kw = dict(variant=variant, eps=1e-300, fresh_products=fresh, precision=precision, tau0=0.9)
     a = egt.State(G, max_iters=10**9, **kw)
     b = egt.State(G, max_iters=10**9, **kw)
     sides_a, sides_b = [], []
@@ -360,6 +362,7 @@ def test_kept_local_strategies_bitwise(egt, variant, fresh, precision):
         sides_b.append(b.step()[1])
     r, c = egt.solve(G, keep_state=True, max_iters=n, **kw)
     assert r["status"] == "EGT_ENOTCONV" and r["iters"] == n
+    assert variant != "AS" or r["backtracks"] >= 1, "EGT/as retried at least once"
     assert sides_a == sides_b and len(set(sides_a)) == 2, "both sides step, so both kinds of reuse run"
     fa, fb, fc = a.get(), b.get(), c.get()
     for f in (fb, fc):
