@@ -324,10 +324,10 @@ def other_paths(egt, torch, args):
 
 def serving(egt, args):
     """Trace of solve requests (shapes drawn uniformly), continuously batched
-    under an HBM budget: all at t = 0 (the saturated capacity, batched and
-    sequential), then Poisson arrivals at 0.9 x the batched capacity, batched
-    in the precision form, batched in FP64, and served one at a time in FP64
-    (the baseline)."""
+    under an HBM budget: all at t = 0 (the saturated capacity: batched in the
+    precision form, batched in FP64, and sequential FP64), then Poisson
+    arrivals at 0.9 x the batched capacity, batched in the precision form,
+    batched in FP64, and served one at a time in FP64 (the baseline)."""
     from instances import make_instance
     from instances.endgames import serving_trace
     from paper_1810_03063_amd.serve import LibEngine, Request, serve, serve_sequential, summarize
@@ -357,6 +357,8 @@ def serving(egt, args):
 
     saturated = run(0.0)  # every request at t = 0
     note("saturated, batched", saturated)
+    saturated64 = run(0.0, "fp64")
+    note("saturated, batched FP64", saturated64)
     seq_sat_out, seq_sat_wall = serve_sequential(solve_one, reqs_for(0.0))
     seq_saturated = summarize(seq_sat_out, seq_sat_wall)
     note("saturated, one at a time", seq_saturated)
@@ -371,6 +373,8 @@ def serving(egt, args):
     out = dict(shapes=list(shapes), requests=n, budget_gb=args.serve_budget_gb, saturated=saturated,
                saturated_sequential_fp64=seq_saturated,
                capacity_vs_sequential=saturated["solves_per_sec"] / seq_saturated["solves_per_sec"],
+               saturated_fp64=saturated64,
+               capacity_vs_sequential_fp64=saturated64["solves_per_sec"] / seq_saturated["solves_per_sec"],
                poisson_rate_per_s=rate, batched=loaded, batched_fp64=loaded64, sequential_fp64=baseline)
     if args.serve_small_shapes:
         # the same saturated comparison without the 8-size endgame, whose
