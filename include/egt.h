@@ -238,7 +238,7 @@ int egt_saddle_gap_noalloc(const egt_game* game, const double* x, const double* 
 /* ------------------------------------------------------------------------ */
 
 /* Payoff product of the precision form (same operator as egt_gradient, Section
- * 2): fold terminals by the O(n) per-card evaluation in FP64 arithmetic; all
+ * 2): fold terminals by the O(n) per-card evaluation in FP32 arithmetic; all
  * showdown terminals of the player stacked into one contraction W Y on the
  * BF16 matrix cores, with W in {-1, 0, +1} (exact in BF16) over the
  * strength-ordered hands and Y = b_o * v_o split into hi + lo BF16, FP32
@@ -249,7 +249,9 @@ int egt_gradient_mixed(const egt_game* game, int player, const float* strat_othe
                        hipStream_t stream);
 
 /* Smoothed best response of the precision form (Section 4, Eq. 4): FP32
- * gradient in, FP32 exponentials and strategy, FP64 normalisers and values.
+ * gradient in; the shift of each exponent in FP64, scaled by the FP32-rounded
+ * reciprocal of mu beta; FP32 exponentials, local strategies and strategy;
+ * FP64 normalisers and values.
  * strat_out / value_out as in egt_smoothed_br (value_out is a device double). */
 int egt_smoothed_br_mixed(const egt_game* game, int player, const float* grad, double mu,
                           float* strat_out, double* value_out, hipStream_t stream);
