@@ -249,9 +249,9 @@ int egt_gradient_mixed(const egt_game* game, int player, const float* strat_othe
                        hipStream_t stream);
 
 /* Smoothed best response of the precision form (Section 4, Eq. 4): FP32
- * gradient in; the shift of each exponent in FP64, scaled by the FP32-rounded
- * reciprocal of mu beta; FP32 exponentials, local strategies and strategy;
- * FP64 normalisers and values.
+ * gradient in; each exponent's shift times 1 / (mu beta) in FP64, rounded to
+ * FP32 for the exponential; FP32 local strategies and strategy; FP64
+ * normalisers and values.
  * strat_out / value_out as in egt_smoothed_br (value_out is a device double). */
 int egt_smoothed_br_mixed(const egt_game* game, int player, const float* grad, double mu,
                           float* strat_out, double* value_out, hipStream_t stream);
