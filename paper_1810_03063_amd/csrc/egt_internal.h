@@ -178,6 +178,7 @@ struct Epilogue {
   void* comb_out;
   void* g_out;     // single-launch pass only: g_scale (cA gA + cB gB) of this tree, or null
   double g_scale;
+  void* qb_out = nullptr;  // single-launch pass only: the local strategies q_bar (before the top-down), or null
 };
 
 // Host description of one pass (player instead of device tables).  With VB

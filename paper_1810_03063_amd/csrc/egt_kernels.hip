@@ -227,9 +227,13 @@ __global__ __launch_bounds__(kFusedSlots * HB) void sbr_fused_kernel(FusedArgs a
       const int i = base + u * kThreads + tid;
       if (i < SH) {
         const double x = gB ? lin2(t.cA, va[u], t.cB, vb[u]) : t.cA * va[u];
-        Gl[i] = x;
         if (want_x) Xl[i] = vx[u];
-        if (g_out) g_out[(size_t)(i / HB) * ld + h0 + i % HB] = (TG)(x * e.g_scale);  // 0 in the padding
+        if (g_out) {
+          g_out[(size_t)(i / HB) * ld + h0 + i % HB] = (TG)(x * e.g_scale);  // 0 in the padding
+          Gl[i] = (double)(TG)x;  // continue with the stored gradient (g_scale = +-1)
+        } else {
+          Gl[i] = x;
+        }
       }
     }
   }
@@ -244,7 +248,7 @@ __global__ __launch_bounds__(kFusedSlots * HB) void sbr_fused_kernel(FusedArgs a
   __syncthreads();
 
   // 2. bottom-up
-  const bool want_q = (e.q_out || e.comb_out) && t.mu > 0.0;
+  const bool want_q = (e.q_out || e.comb_out || e.qb_out) && t.mu > 0.0;
   const double mu = t.mu;
   for (int l = 0; l < t.n_levels; ++l) {
     if (l > 0) {
@@ -274,6 +278,15 @@ __global__ __launch_bounds__(kFusedSlots * HB) void sbr_fused_kernel(FusedArgs a
       if (h0 + hl < n) fused_node<TG, HB>(rec, prm, Gl, Ql, Vs, v, hl, mu, want_q);
     }
     __syncthreads();
+  }
+
+  // the local strategies, for a later top-down pass (0 in the padding)
+  if (e.qb_out && want_q) {
+    TG* qb_out = (TG*)e.qb_out;
+    for (int i = tid; i < SH; i += kThreads) {
+      const int hh = h0 + i % HB;
+      qb_out[(size_t)(i / HB) * ld + hh] = hh < n ? (TG)Ql[i] : (TG)0;
+    }
   }
 
   // 3. partial root sum

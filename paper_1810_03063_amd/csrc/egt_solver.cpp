@@ -56,7 +56,7 @@ struct egt_state {
   void* T1[2] = {};
   void* T2[2] = {};
   void* QB[2] = {};
-  // level path: the local strategies q_bar of the smoothed best response
+  // the local strategies q_bar of the smoothed best response
   // that opens the next iteration, written by this iteration's value launch
   // (whose EGV tree of that side is the same bottom-up pass), and what they
   // were computed from: side, gradient buffer and mu (side -1: none)
@@ -326,7 +326,7 @@ int state_create_in(const egt_game* g, const egt_solve_opts* o, hipStream_t s, v
     st->Xs[p] = take(vb);
     st->Gs[p] = take(vb);
     st->Xbar2[p] = take(vb);
-    if (!g->fused_passes) st->QN[p] = take(vb);
+    st->QN[p] = take(vb);
     st->V[p] = (double*)take(sizeof(double) * (size_t)g->hp[p].n_nodes * g->ld);
     st->Vb[p] = (double*)take(sizeof(double) * (size_t)g->hp[p].n_nodes * g->ld);
     if (mixed) {
@@ -506,7 +506,7 @@ void side_and_tau(const egt_state* st, int64_t t, const double mu[2], double tau
 // widened iterates through FP64 products) as root partials in v.part;
 // returns the number of value trees.
 //
-// On the level path x_bar's bottom-up pass is usually already done: the EGV
+// x_bar's bottom-up pass is usually already done: the EGV
 // tree of the side that steps next is the bottom-up pass of exactly the
 // smoothed best response that opens the next iteration (same gradient, bit
 // for bit, since the tree that stores the accepted product continues with
@@ -572,7 +572,8 @@ static int attempt_v(egt_state* st, const View& v, int64_t t_at, int p, double t
     mu_n[p] = mu_new;
     int pn;
     side_and_tau(st, t_at + 1, mu_n, tau, &pn, &tau_n);
-    ps[pn == p ? 0 : 1].QB = st->QN[pn];
+    ps[pn == p ? 0 : 1].QB = st->QN[pn];     // level path
+    epi[pn == p ? 0 : 1].qb_out = st->QN[pn];  // single-launch path
     st->qn_side = pn;
     st->qn_grad = v.T2[pn];
     st->qn_mu = mu_n[pn];
@@ -916,7 +917,7 @@ int64_t state_bytes(const egt_game* g, bool mixed) {
   for (int p = 0; p < 2; ++p) {
     bytes += esz * 11 * (size_t)vec_elems(g, p) + sizeof(double) * 2 * (size_t)g->hp[p].n_nodes * g->ld;
     if (mixed) bytes += sizeof(double) * 2 * (size_t)vec_elems(g, p);
-    if (!g->fused_passes) bytes += esz * (size_t)vec_elems(g, p);  // QN
+    bytes += esz * (size_t)vec_elems(g, p);  // QN
     bytes += 16 * 256;
   }
   bytes += 64 * sizeof(double) + 256;

@@ -336,16 +336,18 @@ def test_repeatable_and_checkpoint_resume_bitwise(egt):
     assert torch.equal(c["x"], a["x"]) and torch.equal(c["y"], a["y"])
 
 
-@pytest.mark.parametrize("variant,fresh,precision", [("AS", False, "fp64"), ("ALT", False, "fp64"),
-                                                     ("AS", True, "fp64"), ("AS", False, "mixed")])
-def test_kept_local_strategies_bitwise(egt, variant, fresh, precision):
-    """On the level path (c3) the value launch keeps the local strategies of
-    the next iteration's first smoothed best response (its EGV tree of that
-    side is the same bottom-up pass, in FP64 and in the precision form).  Stepping with them kept, and solving
+@pytest.mark.parametrize("cfg,variant,fresh,precision", [("c3", "AS", False, "fp64"), ("c3", "ALT", False, "fp64"),
+                                                         ("c3", "AS", True, "fp64"), ("c3", "AS", False, "mixed"),
+                                                         ("c1", "AS", False, "fp64"), ("c1", "ALT", False, "mixed")])
+def test_kept_local_strategies_bitwise(egt, cfg, variant, fresh, precision):
+    """The value launch keeps the local strategies of the next iteration's
+    first smoothed best response (its EGV tree of that side is the same
+    bottom-up pass, in FP64 and in the precision form), on the level path
+    (c3) and on the single-launch path (c1).  Stepping with them kept, and solving
     with the pipelined loop, must give bit for bit what stepping with the full
     pass gives (a state_set before every step drops what is kept)."""
-    inst = make_instance("c3", 0)
-    print(f"[case] kept q_bar c3 {variant} fresh={fresh} {precision}", flush=True)
+    inst = make_instance(cfg, 0)
+    print(f"[case] kept q_bar {cfg} {variant} fresh={fresh} {precision}", flush=True)
     G = egt.Game(inst)
     n = 14
     # tau0 = 0.9: the first EGT/as attempts fail the excessive gap test, so
