@@ -181,6 +181,11 @@ __global__ __launch_bounds__(kFusedSlots * HB) void sbr_fused_kernel(FusedArgs a
   double* Ql = Gl + (size_t)a.cap_seqs * HB;      // [cap_seqs][HB] q_bar, then q
   double* Xl = Ql + (size_t)a.cap_seqs * HB;      // [cap_seqs][HB] x_prev of the epilogue
   double* Vs = Xl + (size_t)a.cap_seqs * HB;      // [cap_nodes][HB] node values by slot
+  // a dual tree (VB; every tree of the launch is then dual) also takes the
+  // best response to the same gradient: its g~ and node values beside
+  const bool dual = t.VB != nullptr && t.mu > 0.0;
+  double* GBl = Vs + (size_t)a.cap_nodes * HB;  // [cap_seqs][HB] dual: gradient, then the best response's g~
+  double* VBs = GBl + (size_t)a.cap_seqs * HB;  // [cap_nodes][HB] dual: best-response node values
   const int tid = threadIdx.x;
   const int h0 = hblk * HB, n = a.ps.n;
   const size_t ld = a.ps.ld;
@@ -227,6 +232,7 @@ __global__ __launch_bounds__(kFusedSlots * HB) void sbr_fused_kernel(FusedArgs a
       const int i = base + u * kThreads + tid;
       if (i < SH) {
         const double x = gB ? lin2(t.cA, va[u], t.cB, vb[u]) : t.cA * va[u];
+        if (dual) GBl[i] = x;
         if (want_x) Xl[i] = vx[u];
         if (g_out) {
           g_out[(size_t)(i / HB) * ld + h0 + i % HB] = (TG)(x * e.g_scale);  // 0 in the padding
@@ -269,13 +275,30 @@ __global__ __launch_bounds__(kFusedSlots * HB) void sbr_fused_kernel(FusedArgs a
         }
         for (; c < c1; ++c) x += Vs[c * HB + hl];
         Gl[s * HB + hl] = x;
+        if (dual) {  // the same additions on the best-response values
+          double xb = GBl[s * HB + hl];
+          int cb = c0;
+          for (; cb + 4 <= c1; cb += 4) {
+            const double v0 = VBs[cb * HB + hl], v1 = VBs[(cb + 1) * HB + hl];
+            const double v2 = VBs[(cb + 2) * HB + hl], v3 = VBs[(cb + 3) * HB + hl];
+            xb += v0;
+            xb += v1;
+            xb += v2;
+            xb += v3;
+          }
+          for (; cb < c1; ++cb) xb += VBs[cb * HB + hl];
+          GBl[s * HB + hl] = xb;
+        }
       }
       __syncthreads();
     }
     const int nb0 = t.level_begin[l], cnt = (t.level_begin[l + 1] - nb0) * HB;
     for (int i = tid; i < cnt; i += kThreads) {
       const int v = nb0 + i / HB, hl = i % HB;
-      if (h0 + hl < n) fused_node<TG, HB>(rec, prm, Gl, Ql, Vs, v, hl, mu, want_q);
+      if (h0 + hl < n) {
+        fused_node<TG, HB>(rec, prm, Gl, Ql, Vs, v, hl, mu, want_q);
+        if (dual) fused_node<TG, HB>(rec, prm, GBl, nullptr, VBs, v, hl, 0.0, false);  // mu = 0: the minimum
+      }
     }
     __syncthreads();
   }
@@ -299,6 +322,16 @@ __global__ __launch_bounds__(kFusedSlots * HB) void sbr_fused_kernel(FusedArgs a
 #pragma unroll
     for (int off = HB / 2; off > 0; off >>= 1) sv += __shfl_down(sv, off, HB);
     if (tid == 0) a.partial[(size_t)k * nb + hblk] = sv;
+  }
+  if (a.partial && dual && tid < HB) {  // the best response's, after the launch's trees
+    double sv = 0.0;
+    if (h0 + tid < n) {
+      const int C = N - t.P.n_roots;
+      for (int r = 0; r < t.P.n_roots; ++r) sv += VBs[(C + r) * HB + tid];
+    }
+#pragma unroll
+    for (int off = HB / 2; off > 0; off >>= 1) sv += __shfl_down(sv, off, HB);
+    if (tid == 0) a.partial[(size_t)(a.ps.count + k) * nb + hblk] = sv;
   }
 
   // 4. top-down and epilogue
@@ -890,14 +923,26 @@ static hipError_t passes_launch(const egt_game* g, const Pass* p, int count, con
   for (int k = 0; k < count; ++k) any_dual = any_dual || p[k].VB != nullptr;
   const int n_epi = count;  // epilogues belong to the passes as given
   if (g->fused_passes) {
-    // a dual pass becomes a second tree with mu = 0 after the others
+    const int cap_tab = (int)std::max(g->hp[0].fused_tab.size(), g->hp[1].fused_tab.size());
+    const int cap_nodes = std::max(g->hp[0].n_nodes, g->hp[1].n_nodes);
+    const int cap_seqs = std::max(g->hp[0].n_seq, g->hp[1].n_seq);
+    const size_t dual_lds = sizeof(double) * (size_t)g->fused_hands * ((size_t)cap_seqs + (size_t)cap_nodes);
+    // dual passes inside the kernel when every pass is dual, every one is
+    // smoothed and the extra LDS fits; otherwise each becomes a second tree
+    // with mu = 0 after the others
+    bool all_dual = true;
+    for (int k = 0; k < count; ++k) all_dual = all_dual && p[k].VB != nullptr && p[k].mu > 0.0;
+    const bool in_kernel =
+        any_dual && all_dual &&
+        fused_lds_bytes(g->fused_hands, cap_tab, cap_nodes, cap_seqs) + dual_lds <= (size_t)g->lds_per_block;
     Pass q[kMaxTrees];
     int nq = 0;
     for (int k = 0; k < count; ++k) {
       q[nq] = p[k];
-      q[nq++].VB = nullptr;
+      if (!in_kernel) q[nq].VB = nullptr;
+      ++nq;
     }
-    for (int k = 0; k < count; ++k) {
+    for (int k = 0; any_dual && !in_kernel && k < count; ++k) {
       if (!p[k].VB) continue;
       if (nq >= kMaxTrees) return hipErrorInvalidValue;
       q[nq++] = Pass{p[k].player, p[k].gA, p[k].cA, p[k].gB, p[k].cB, 0.0, p[k].VB, nullptr};
@@ -913,7 +958,7 @@ static hipError_t passes_launch(const egt_game* g, const Pass* p, int count, con
     a.cap_nodes = std::max(g->hp[0].n_nodes, g->hp[1].n_nodes);
     a.cap_seqs = std::max(g->hp[0].n_seq, g->hp[1].n_seq);
     const int hb = g->fused_hands;
-    const size_t lds = fused_lds_bytes(hb, a.cap_tab, a.cap_nodes, a.cap_seqs);
+    const size_t lds = fused_lds_bytes(hb, a.cap_tab, a.cap_nodes, a.cap_seqs) + (in_kernel ? dual_lds : 0);
     a.n_hblocks = g->ld / hb;
     const dim3 grid((unsigned)(a.n_hblocks * count));
     if (hb == 4)
