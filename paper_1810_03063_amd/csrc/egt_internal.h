@@ -150,7 +150,8 @@ struct TreePass {
   double cB;
   double mu;
   double* V;       // node values by value slot (FusedTabLayout): always FP64
-  double* VB;      // lowest level of the level path: also the best response's node values (the minimum), or null
+  double* VB;      // dual pass: also the best response's node values (the level path's lowest level, or the
+                   // whole single-launch pass), or null
   void* QB;        // q_bar in the launch's precision
   void* g_out;     // g_scale (cA gA + cB gB), or null (the epilogue's g_out)
   double g_scale;
