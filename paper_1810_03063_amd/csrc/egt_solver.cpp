@@ -56,10 +56,10 @@ struct egt_state {
   void* T1[2] = {};
   void* T2[2] = {};
   void* QB[2] = {};
-  // the local strategies q_bar of the smoothed best response
-  // that opens the next iteration, written by this iteration's value launch
-  // (whose EGV tree of that side is the same bottom-up pass), and what they
-  // were computed from: side, gradient buffer and mu (side -1: none)
+  // the local strategies q_bar of the smoothed best response that opens the
+  // next iteration, written by this iteration's value launch (whose EGV tree
+  // of that side is the same bottom-up pass), and what they were computed
+  // from: side, gradient buffer and mu (side -1: none)
   void* QN[2] = {};
   int qn_side = -1;
   const void* qn_grad = nullptr;
@@ -500,18 +500,18 @@ void side_and_tau(const egt_state* st, int64_t t, const double mu[2], double tau
 
 // One attempt of the step focused on p at step size tau on the buffers of v,
 // with mu, as iteration t_at (the number of steps accepted before it).
-// first = the iteration's first attempt (otherwise a retry with a halved tau).  Leaves the two EGV
-// terms (and with with_gap the two best-response values of the candidate's
-// saddle gap: FP64 trees in the same launch, or in the precision form the
-// widened iterates through FP64 products) as root partials in v.part;
-// returns the number of value trees.
+// first = the iteration's first attempt (otherwise a retry with a halved
+// tau).  Leaves the two EGV terms (and with with_gap the two best-response
+// values of the candidate's saddle gap: dual FP64 trees in the same launch,
+// or in the precision form the widened iterates through FP64 products) as
+// root partials in v.part; returns the number of values.
 //
-// x_bar's bottom-up pass is usually already done: the EGV
-// tree of the side that steps next is the bottom-up pass of exactly the
-// smoothed best response that opens the next iteration (same gradient, bit
-// for bit, since the tree that stores the accepted product continues with
-// the stored values; same mu), so the value launch also keeps that tree's
-// q_bar (in QN) and the next first attempt runs only the top-down pass on it.
+// x_bar's bottom-up pass is usually already done: the EGV tree of the side
+// that steps next is the bottom-up pass of exactly the smoothed best response
+// that opens the next iteration (same gradient, bit for bit, since the tree
+// that stores the accepted product continues with the stored values; same
+// mu), so the value launch also keeps that tree's q_bar (in QN) and the next
+// first attempt runs only the top-down pass on it.
 static int attempt_v(egt_state* st, const View& v, int64_t t_at, int p, double tau, const double mu[2],
                      bool first, hipStream_t s, int* trees_out, bool with_gap = false) {
   const egt_game* g = st->g;
@@ -566,8 +566,7 @@ static int attempt_v(egt_state* st, const View& v, int64_t t_at, int p, double t
   // the side of the iteration after this one if it is accepted: its EGV tree
   // keeps q_bar for that iteration's first smoothed best response (the
   // gradient it reads then is T2 of that side: kSg * (kSg * g~) = g~ exactly)
-  st->qn_side = -1;
-  if (st->QN[0]) {
+  {
     double mu_n[2] = {mu[0], mu[1]}, tau_n;
     mu_n[p] = mu_new;
     int pn;
