@@ -91,6 +91,17 @@ def test_mixed_product_error_ragged_k(egt):
     _check_mixed_product(egt, inst, 0)
 
 
+@pytest.mark.parametrize("name", ["max-hands", "two-hands"])
+def test_mixed_product_error_hand_counts(egt, name):
+    """The largest hand count the library takes (2048 hands: eight per thread
+    in the fold kernel, sixteen 128-row tiles of the GEMM) and two one-card
+    hands (rows mostly padding)."""
+    from tests.test_gpu_ops import _edge_instances
+    inst = dict(_edge_instances())[name]
+    print(f"[case] mixed product {name}", flush=True)
+    _check_mixed_product(egt, inst, 0)
+
+
 def _check_mixed_product(egt, inst, seed):
     P = Problem(inst)
     G = egt.Game(inst)
